@@ -1,0 +1,185 @@
+"""Sequential CPU oracle for Blocked Bloom filters with choices.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU
+baseline leg of the benchmark are the only users. The product library never
+imports this package, and this package imports nothing from the product.
+
+``bbfc_oracle.c`` holds the definitions (built into ``liboracle.so`` with
+gcc); this module is a ctypes wrapper over numpy arrays. ``brute`` is an
+independent pure-Python restatement for tiny inputs and ``closed_form``
+holds the paper's analytic formulas.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "bbfc_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+COST_NONE, COST_MIX, COST_LA, COST_EXP = 0, 1, 2, 3
+COST_NAMES = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain C, no contraction of a*b+c)."""
+    cmd = [
+        "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+        "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm",
+    ]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        build()
+    lib = ctypes.CDLL(LIB)
+    u64, u32, i32, dbl = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_double
+    lib.bbo_hash.argtypes = [u64, u64, u64]
+    lib.bbo_hash.restype = u64
+    lib.bbo_mask.argtypes = [_u64p, u32, u64, _u64p]
+    lib.bbo_mask.restype = None
+    lib.bbo_default_param.argtypes = [i32, u32]
+    lib.bbo_default_param.restype = dbl
+    lib.bbo_cost.argtypes = [i32, dbl, u32, u32, u32]
+    lib.bbo_cost.restype = dbl
+    lib.bbo_insert_one.argtypes = [_u64p, u64, u32, u32, i32, dbl, _u64p, _u64p, u64]
+    lib.bbo_insert_one.restype = i32
+    lib.bbo_insert.argtypes = [_u64p, u64, u32, u32, i32, dbl, _u64p, _u64p, _u64p, u64]
+    lib.bbo_insert.restype = u64
+    lib.bbo_query_one.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, u64]
+    lib.bbo_query_one.restype = i32
+    lib.bbo_query.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, _u64p, u64, _u64p]
+    lib.bbo_query.restype = u64
+    lib.bbo_derive_multipliers.argtypes = [u64, u64, u32, u32, _u64p, _u64p]
+    lib.bbo_derive_multipliers.restype = None
+    lib.bbo_envelope.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, _u64p, u64]
+    lib.bbo_envelope.restype = None
+    lib.bbo_block_loads.argtypes = [_u64p, u64, _u64p]
+    lib.bbo_block_loads.restype = None
+    lib.bbo_conditional_fpr.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, u64]
+    lib.bbo_conditional_fpr.restype = dbl
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.uint64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_u64p)
+
+
+def _u64(seq) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(seq, dtype=np.uint64))
+
+
+def hash_(a: int, x: int, b: int) -> int:
+    return int(_load().bbo_hash(a, x, b))
+
+
+def mask(bit_mult, x: int) -> np.ndarray:
+    am = _u64(bit_mult)
+    out = np.zeros(8, dtype=np.uint64)
+    _load().bbo_mask(_ptr(am), len(am), x, _ptr(out))
+    return out
+
+
+def default_param(kind: int, k: int) -> float:
+    return float(_load().bbo_default_param(kind, k))
+
+
+def cost(kind: int, param: float, k: int, j: int, a: int) -> float:
+    return float(_load().bbo_cost(kind, param, k, j, a))
+
+
+def derive_multipliers(seed: int, M: int, c: int, k: int):
+    bm = np.zeros(c, dtype=np.uint64)
+    am = np.zeros(k, dtype=np.uint64)
+    _load().bbo_derive_multipliers(seed, M, c, k, _ptr(bm), _ptr(am))
+    return [int(v) for v in bm], [int(v) for v in am]
+
+
+class OracleFilter:
+    """A filter held in host memory and driven by the sequential oracle."""
+
+    def __init__(self, n_blocks: int, choices: int, k: int, cost_kind: int = COST_NONE,
+                 cost_param: float | None = None, block_mult=None, bit_mult=None, seed: int = 0):
+        if choices < 1 or k < 1 or n_blocks < 1:
+            raise ValueError("bad filter shape")
+        self.M, self.c, self.k = int(n_blocks), int(choices), int(k)
+        self.kind = int(cost_kind)
+        if cost_param is None or (isinstance(cost_param, float) and np.isnan(cost_param)):
+            cost_param = default_param(self.kind, self.k)
+        self.param = float(cost_param)
+        if block_mult is None or bit_mult is None:
+            dbm, dam = derive_multipliers(seed, self.M, self.c, self.k)
+            block_mult = dbm if block_mult is None else block_mult
+            bit_mult = dam if bit_mult is None else bit_mult
+        self.block_mult = _u64(block_mult)
+        self.bit_mult = _u64(bit_mult)
+        assert len(self.block_mult) == self.c and len(self.bit_mult) == self.k
+        self.words = np.zeros(8 * self.M, dtype=np.uint64)
+
+    def insert(self, keys) -> int:
+        keys = _u64(keys)
+        return int(_load().bbo_insert(_ptr(self.words), self.M, self.c, self.k, self.kind, self.param,
+                                      _ptr(self.block_mult), _ptr(self.bit_mult), _ptr(keys), len(keys)))
+
+    def insert_one(self, key: int) -> int:
+        return int(_load().bbo_insert_one(_ptr(self.words), self.M, self.c, self.k, self.kind,
+                                          self.param, _ptr(self.block_mult), _ptr(self.bit_mult), key))
+
+    def query_bits(self, keys) -> np.ndarray:
+        """Packed answers: bit t of word t//64 (LSB first) for keys[t]."""
+        keys = _u64(keys)
+        out = np.zeros((len(keys) + 63) // 64, dtype=np.uint64)
+        _load().bbo_query(_ptr(self.words), self.M, self.c, self.k, _ptr(self.block_mult),
+                          _ptr(self.bit_mult), _ptr(keys), len(keys), _ptr(out))
+        return out
+
+    def query(self, keys) -> np.ndarray:
+        """Answers as a bool array."""
+        bits = self.query_bits(keys)
+        n = len(keys)
+        return np.unpackbits(bits.view(np.uint8), bitorder="little")[:n].astype(bool)
+
+    def count_hits(self, keys) -> int:
+        keys = _u64(keys)
+        return int(_load().bbo_query(_ptr(self.words), self.M, self.c, self.k, _ptr(self.block_mult),
+                                     _ptr(self.bit_mult), _ptr(keys), len(keys), None))
+
+    def query_one(self, key: int) -> bool:
+        return bool(_load().bbo_query_one(_ptr(self.words), self.M, self.c, self.k,
+                                          _ptr(self.block_mult), _ptr(self.bit_mult), key))
+
+    def envelope(self, keys) -> np.ndarray:
+        keys = _u64(keys)
+        env = np.zeros_like(self.words)
+        _load().bbo_envelope(_ptr(env), self.M, self.c, self.k, _ptr(self.block_mult),
+                             _ptr(self.bit_mult), _ptr(keys), len(keys))
+        return env
+
+    def block_loads(self, words: np.ndarray | None = None) -> np.ndarray:
+        w = self.words if words is None else _u64(words)
+        hist = np.zeros(513, dtype=np.uint64)
+        _load().bbo_block_loads(_ptr(w), self.M, _ptr(hist))
+        return hist
+
+    def conditional_fpr(self, keys, words: np.ndarray | None = None) -> float:
+        w = self.words if words is None else _u64(words)
+        keys = _u64(keys)
+        return float(_load().bbo_conditional_fpr(_ptr(w), self.M, self.c, self.k,
+                                                 _ptr(self.block_mult), _ptr(keys), len(keys)))

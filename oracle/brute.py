@@ -1,0 +1,83 @@
+"""Independent pure-Python restatement of the filter for tiny inputs.
+
+TEST INFRASTRUCTURE ONLY. It shares nothing with ``bbfc_oracle.c``: blocks
+are Python ``set``s of bit addresses F', a key's addresses F(x) are a
+``set``, and j, a come from set union and difference exactly as the paper
+defines them (Section 3.2: j = |F' u F(x)|, a = |F(x) \\ F'|). Hashing uses
+Python's unbounded integers reduced modulo 2^64 (Section 3.4). The result is
+converted to 64-bit words only at the end, so the word layout of the C
+oracle is checked too.
+"""
+
+from __future__ import annotations
+
+import math
+
+U64 = 1 << 64
+
+
+def lin_hash(a: int, x: int, b: int) -> int:
+    """((a*x) mod 2^64) mod b with the even-b modifications of Section 3.4."""
+    p = (a * x) % U64
+    if b == 1:
+        return 0
+    s = b.bit_length() - 1
+    if (1 << s) == b:
+        return p // (1 << (64 - s))  # the s most significant bits of p
+    if b % 2 == 0:
+        return (p ^ (p // (1 << 32))) % b
+    return p % b
+
+
+def bit_set(bit_mult, x: int) -> set[int]:
+    """F(x) = { f_i(x) } with f_i into [512] (eq. bitset, random strategy)."""
+    return {lin_hash(a, x, 512) for a in bit_mult}
+
+
+def cost(kind: str, param: float, k: int, j: int, a: int) -> float:
+    """App. A eqs. cost:mix, cost:la, cost:exp (same left-to-right order)."""
+    if kind == "mix":
+        return param * k * math.pow(j / 256.0, k) + a
+    if kind == "la":
+        return k * math.pow((j + param * k) / 256.0, k) + a
+    if kind == "exp":
+        return math.pow(param, j / 128.0) + a / k
+    raise ValueError(kind)
+
+
+class BruteFilter:
+    def __init__(self, M: int, c: int, k: int, kind: str, param: float, block_mult, bit_mult):
+        self.M, self.c, self.k, self.kind, self.param = M, c, k, kind, param
+        self.block_mult = [int(v) for v in block_mult]
+        self.bit_mult = [int(v) for v in bit_mult]
+        self.blocks: list[set[int]] = [set() for _ in range(M)]
+
+    def candidates(self, x: int) -> list[int]:
+        return [lin_hash(b, x, self.M) for b in self.block_mult]
+
+    def insert(self, x: int) -> int:
+        F = bit_set(self.bit_mult, x)
+        cand = self.candidates(x)
+        ja = []
+        for b in cand:
+            Fp = self.blocks[b]
+            ja.append((len(Fp | F), len(F - Fp)))
+        if any(a == 0 for _, a in ja):
+            return -1
+        best = 0
+        if self.c > 1:
+            costs = [cost(self.kind, self.param, self.k, j, a) for j, a in ja]
+            best = min(range(self.c), key=lambda i: (costs[i], i))
+        self.blocks[cand[best]] |= F
+        return best
+
+    def query(self, x: int) -> bool:
+        F = bit_set(self.bit_mult, x)
+        return any(F <= self.blocks[b] for b in self.candidates(x))
+
+    def words(self) -> list[int]:
+        out = []
+        for S in self.blocks:
+            for w in range(8):
+                out.append(sum(1 << (f - 64 * w) for f in S if f // 64 == w))
+        return out

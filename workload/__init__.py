@@ -1,0 +1,109 @@
+"""Seeded synthetic inputs shared by the oracle-side tests and the GPU path.
+
+This module only draws numbers. It holds none of the filter's arithmetic
+(no hashing into blocks or bits, no cost, no popcount): every value it
+returns is an input that both the sequential CPU oracle and the HIP library
+receive unchanged.
+
+Keys are counter-based SplitMix64 outputs (Steele, Lea and Flood,
+"Fast splittable pseudorandom number generators", OOPSLA 2014):
+
+    key(seed, i) = mix64(seed + (i + 1) * GAMMA)          (mod 2^64)
+
+``mix64`` is a bijection of 64-bit words and ``GAMMA`` is odd, so for a fixed
+seed distinct counters give distinct keys. Positive keys use counters
+[0, n) and negative keys [n, 2n): the two sets are disjoint by construction.
+
+Hash multipliers (the "random large integer a, coprime with b" of the
+paper's Section 3.4) are drawn here as well for the tests, so that both
+sides receive the same parameters as plain inputs.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+GAMMA = 0x9E3779B97F4A7C15
+MIX1 = 0xBF58476D1CE4E5B9
+MIX2 = 0x94D049BB133111EB
+MASK64 = (1 << 64) - 1
+
+__all__ = [
+    "GAMMA",
+    "splitmix64_keys",
+    "splitmix64_scalar",
+    "SplitMix64",
+    "draw_multipliers",
+    "positive_keys",
+    "negative_keys",
+]
+
+
+def splitmix64_scalar(seed: int, i: int) -> int:
+    """key(seed, i) in plain Python integers (used to spot-check samples)."""
+    z = (seed + (i + 1) * GAMMA) & MASK64
+    z = ((z ^ (z >> 30)) * MIX1) & MASK64
+    z = ((z ^ (z >> 27)) * MIX2) & MASK64
+    return z ^ (z >> 31)
+
+
+def splitmix64_keys(seed: int, start: int, n: int) -> np.ndarray:
+    """key(seed, start), ..., key(seed, start + n - 1) as a uint64 array.
+
+    numpy's uint64 array arithmetic wraps modulo 2^64, which is exactly the
+    generator's definition.
+    """
+    if n < 0 or start < 0:
+        raise ValueError("start and n must be non-negative")
+    out = np.empty(n, dtype=np.uint64)
+    chunk = 1 << 24
+    s = np.uint64(seed & MASK64)
+    g = np.uint64(GAMMA)
+    m1 = np.uint64(MIX1)
+    m2 = np.uint64(MIX2)
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        ctr = np.arange(start + lo + 1, start + hi + 1, dtype=np.uint64)
+        z = s + ctr * g
+        z = (z ^ (z >> np.uint64(30))) * m1
+        z = (z ^ (z >> np.uint64(27))) * m2
+        out[lo:hi] = z ^ (z >> np.uint64(31))
+    return out
+
+
+def positive_keys(seed: int, n: int) -> np.ndarray:
+    """The n keys to insert: counters [0, n)."""
+    return splitmix64_keys(seed, 0, n)
+
+
+def negative_keys(seed: int, n_pos: int, n: int) -> np.ndarray:
+    """n keys never inserted: counters [n_pos, n_pos + n)."""
+    return splitmix64_keys(seed, n_pos, n)
+
+
+class SplitMix64:
+    """Sequential SplitMix64 stream (state advances by GAMMA per draw)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next(self) -> int:
+        self.state = (self.state + GAMMA) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * MIX1) & MASK64
+        z = ((z ^ (z >> 27)) * MIX2) & MASK64
+        return z ^ (z >> 31)
+
+
+def draw_multipliers(seed: int, count: int, coprime_to: int = 2) -> list[int]:
+    """``count`` random odd 64-bit multipliers, each >= 2^32 and coprime to
+    ``coprime_to``; used as hash parameters handed to both sides."""
+    rng = SplitMix64(seed ^ 0x5DEECE66D)
+    out: list[int] = []
+    while len(out) < count:
+        a = rng.next() | 1
+        if a >= (1 << 32) and math.gcd(a, coprime_to) == 1:
+            out.append(a)
+    return out
