@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Insert and query throughput of a Blocked Bloom filter with choices on one MI355X.
+
+Workload: 2^30 uniform random 64-bit keys (counter-based SplitMix64, seed 0)
+inserted into a filter of 2^25 blocks of 512 bits (2 GiB, 16 bits per key,
+larger than the 256 MB Infinity Cache), 2 choices, k = 11 bit hashes
+(round(16 ln 2)), lookahead cost with mu = 3.5; then the 2^30 inserted keys
+and 2^30 disjoint random keys are queried. All keys are generated in HBM
+before timing.
+
+One step = clear the filter + insert the 2^30 keys + query the 2^31 keys,
+each one kernel launch through the C ABI. value = keys inserted and queried
+per second, in Mkeys/s.
+
+The JSON line also carries the roofline of the dominant kernel (algorithmic
+bytes per launch / measured launch duration against the HBM peak), the
+measured random-64-byte read and atomic-OR rates of the probe kernels, and
+the sequential CPU oracle timed on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per key (c = 2): a query reads the 8-byte key and two
+# random 64-byte blocks and writes one answer bit; an insert reads the key
+# and two blocks and rewrites one 64-byte block.
+QUERY_BYTES_PER_KEY = 8 + 64 * 2 + 1 / 8
+INSERT_BYTES_PER_KEY = 8 + 64 * 2 + 64
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--log2-keys", type=int, default=30, help="keys to insert (2^n); blocks = keys/32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="target seconds per oracle leg")
+    return ap.parse_args()
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for rel in ("paper_2501_18977_amd/csrc/bbfc_kernels.hip", "paper_2501_18977_amd/csrc/bbfc_common.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if it is absent or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha") != kernel_source_sha():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n_blocks, c, k, target_s):
+    """The sequential oracle on a bounded sample of the same workload."""
+    import numpy as np
+
+    import oracle
+    import workload
+
+    f = oracle.OracleFilter(n_blocks, c, k, oracle.COST_LA, None, seed=0)
+
+    def timed(fn, keys):
+        t = time.perf_counter()
+        fn(keys)
+        return time.perf_counter() - t
+
+    # size each leg to about target_s seconds from a 2^18-key calibration
+    cal = workload.positive_keys(0, 1 << 18)
+    t_cal = timed(f.insert, cal)
+    n_ins = int(min(1 << 26, max(1 << 18, (1 << 18) * target_s / max(t_cal, 1e-6))))
+    ins_keys = workload.splitmix64_keys(0, 1 << 18, n_ins)
+    t_ins = timed(f.insert, ins_keys)
+    q_cal = np.concatenate([cal[: 1 << 17], workload.negative_keys(0, 1 << 30, 1 << 17)])
+    t_qcal = timed(f.count_hits, q_cal)
+    n_q = int(min(1 << 26, max(1 << 18, (1 << 18) * target_s / max(t_qcal, 1e-6))))
+    half = n_q // 2
+    q_keys = np.concatenate([ins_keys[:half], workload.negative_keys(0, 1 << 30, n_q - half)])
+    t_q = timed(f.count_hits, q_keys)
+    r_ins = n_ins / t_ins
+    r_q = n_q / t_q
+    # the step's mix: one insert per two queries
+    value = 3.0 / (1.0 / r_ins + 2.0 / r_q) / 1e6
+    return {
+        "value": round(value, 3),
+        "unit": "Mkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"sequential oracle, 1 thread: {n_ins} inserts (after {1 << 18} warm-up inserts) into the same "
+                   f"{n_blocks}-block filter and {n_q} queries (half inserted, half never inserted), "
+                   f"{t_ins + t_q:.1f} s; rates combined with the step's 1 insert : 2 queries mix"),
+        "insert_mkeys_s": round(r_ins / 1e6, 3),
+        "query_mkeys_s": round(r_q / 1e6, 3),
+    }
+
+
+def main():
+    args = parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2501_18977_amd as bbfc
+    import workload
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    props = torch.cuda.get_device_properties(dev)
+
+    n = 1 << args.log2_keys
+    n_blocks = n // 32  # 16 bits per key
+    c, k = 2, 11  # k = round(16 ln 2)
+    n_q = 2 * n
+
+    keys = torch.empty(n_q, dtype=torch.int64, device=dev)
+    workload.device_keys(0, 0, n, out=keys[:n])          # positives: counters [0, n)
+    workload.device_keys(0, n, n, out=keys[n:])          # negatives: counters [n, 2n)
+    out = torch.empty(n_q // 64, dtype=torch.int64, device=dev)
+    filt = bbfc.Filter(n_blocks, c, k, "la", seed=0)
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+
+    def step():
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        evs[0].record(stream)
+        filt.clear(stream)
+        evs[1].record(stream)
+        filt.insert(keys[:n], stream)
+        evs[2].record(stream)
+        filt.query(keys, out=out, stream=stream)
+        evs[3].record(stream)
+        return evs
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_step = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    ins_ms = [e[1].elapsed_time(e[2]) for e in per_step]
+    qry_ms = [e[2].elapsed_time(e[3]) for e in per_step]
+    clr_ms = [e[0].elapsed_time(e[1]) for e in per_step]
+    ms_per_step = wall * 1e3 / args.steps
+    value = (n + n_q) / (ms_per_step / 1e3) / 1e6
+
+    # correctness guard on the last step: every inserted key answers true
+    pos_words = out[: n // 64]
+    fn_free = bool(torch.all(pos_words == -1).item())
+    neg_bits = int(np.bitwise_count(out[n // 64:].cpu().numpy().view(np.uint64)).sum())
+    fpr = neg_bits / n
+
+    avg_ins = sum(ins_ms) / len(ins_ms)
+    avg_qry = sum(qry_ms) / len(qry_ms)
+    if avg_ins >= avg_qry:
+        dom, dom_ms, dom_bytes = "insert", avg_ins, INSERT_BYTES_PER_KEY * n
+    else:
+        dom, dom_ms, dom_bytes = "query", avg_qry, QUERY_BYTES_PER_KEY * n_q
+    achieved = dom_bytes / (dom_ms / 1e3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": f"{dom}_kernel<2,pow2>",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(dom),
+        "bytes_per_launch_algorithmic": int(dom_bytes),
+        "launch_ms": round(dom_ms, 3),
+    }
+
+    probe = None
+    if not args.no_probe:
+        probe = {}
+        lines = 1 << 26  # 4 GiB buffer, beyond the Infinity Cache
+        buf = torch.zeros(lines * 8, dtype=torch.int64, device=dev)
+        sink = torch.zeros(1 << 16, dtype=torch.int64, device=dev)
+        for name, fn, acc in (
+            ("rand64_read", lambda a: bbfc.probe_gather64(buf, a, 7, sink, stream), 1 << 28),
+            ("rand64_atomic_or", lambda a: bbfc.probe_atomic64(buf, a, 9, stream), 1 << 27),
+        ):
+            fn(acc >> 4)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn(acc)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            probe[name + "_GBs"] = round(acc * 64 / (ms / 1e3) / 1e9, 1)
+            probe[name + "_Glines_s"] = round(acc / (ms / 1e3) / 1e9, 2)
+        del buf
+        # fraction of the measured random-64-byte ceiling
+        ceil = probe["rand64_read_GBs"] if dom == "query" else probe["rand64_atomic_or_GBs"]
+        probe["dominant_frac_of_probe"] = round(achieved / ceil, 4) if ceil else None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(n_blocks, c, k, args.cpu_seconds)
+
+    rec = {
+        "metric": "Mkeys/s insert & query, 2-choice 512b blocks; % of random-access HBM peak",
+        "value": round(value, 1),
+        "unit": "Mkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"plain filter: 2^{args.log2_keys} random 64-bit keys inserted into 2^"
+                         f"{int(math.log2(n_blocks))} blocks of 512 bits, 2 choices, k=11, lookahead cost "
+                         f"mu=3.5; queries: the 2^{args.log2_keys} inserted + 2^{args.log2_keys} never inserted"),
+            "n_keys": n,
+            "n_queries": n_q,
+            "n_blocks": n_blocks,
+            "filter_bytes": n_blocks * 64,
+            "choices": c,
+            "bits_per_key": k,
+            "cost": "la",
+        },
+        "insert_mkeys_s": round(n / (avg_ins / 1e3) / 1e6, 1),
+        "query_mkeys_s": round(n_q / (avg_qry / 1e3) / 1e6, 1),
+        "insert_ms": round(avg_ins, 3),
+        "query_ms": round(avg_qry, 3),
+        "clear_ms": round(sum(clr_ms) / len(clr_ms), 3),
+        "zero_false_negatives": fn_free,
+        "fpr_negatives": fpr,
+        "roofline": roofline,
+        "probe": probe,
+        "cpu_baseline": cpu,
+        "device": props.name,
+        "cus": props.multi_processor_count,
+        "kernel_source_sha": kernel_source_sha(),
+    }
+    filt.close()
+    print(json.dumps(rec), flush=True)
+    if not fn_free:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,218 @@
+/*
+ * bbfc.h -- C ABI of the MI355X (gfx950) library for Blocked Bloom filters
+ * with choices (Schmitz, Zentgraf, Rahmann, arXiv 2501.18977).
+ *
+ * The filter (Section 3.1): M blocks of 512 bits, c candidate blocks per
+ * key chosen by block hashes h_1..h_c, k bit hashes f_1..f_k into a block.
+ * insert(x) sets F(x) = { f_i(x) } in the candidate block of lowest cost
+ * (Section 3.2, App. A), or does nothing if a candidate already holds F(x);
+ * query(x) answers true iff F(x) lies inside some candidate block. A query
+ * of an inserted key always answers true; a key never inserted may answer
+ * true with the filter's false-positive rate (Section 1).
+ *
+ * Conventions shared by every entry point
+ *   - Status: every call returns BBFC_OK (0) or a negative bbfc_status.
+ *     Argument errors are detected before anything is enqueued and return
+ *     BBFC_EINVAL with nothing done; bbfc_last_error() then describes the
+ *     problem (thread-local text, valid until the next call on the thread).
+ *   - Device work is enqueued on the caller's HIP stream and is asynchronous;
+ *     only bbfc_download, bbfc_upload and bbfc_destroy synchronise.
+ *     A null stream means the legacy default stream.
+ *   - Ownership: the library owns the filter memory (hipMalloc in create,
+ *     hipFree in destroy). The caller owns key and output buffers, which are
+ *     device pointers on the filter's device and must stay valid until the
+ *     stream has executed the work that reads or writes them.
+ *   - Keys are 64-bit unsigned integers, hashed as u = 64-bit words
+ *     (Section 3.4) whatever their meaningful width (a canonical 31-mer
+ *     uses 62 bits).
+ *   - Bit layout: bit f in [0, 512) of block b is bit (f mod 64) of 64-bit
+ *     word 8*b + f/64 of the filter; words are little-endian.
+ *   - A handle may be used from one host thread at a time. Concurrent
+ *     insert and query launches on different streams are allowed: bits are
+ *     only ever set, so a query sees some subset of the in-flight inserts.
+ */
+#ifndef BBFC_H
+#define BBFC_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bbfc_filter *bbfc_handle;
+
+typedef enum {
+    BBFC_OK = 0,
+    BBFC_EINVAL = -1,      /* bad argument; nothing was enqueued             */
+    BBFC_ENOMEM = -2,      /* device allocation failed                       */
+    BBFC_EHIP = -3,        /* a HIP runtime call or kernel launch failed     */
+    BBFC_EUNSUPPORTED = -4 /* valid request this build does not implement    */
+} bbfc_status;
+
+/* Cost functions for block selection (App. A; Section 3.2):
+ *   MIX  sigma*k*(j/256)^k + a        (eq. cost:mix)
+ *   LA   k*((j + mu*k)/256)^k + a     (eq. cost:la; lookahead)
+ *   EXP  beta^(j/128) + a/k           (eq. cost:exp)
+ * where j is the number of bits set in the block after the insertion and a
+ * the number of those that are new (Section 3.2). Costs are IEEE-754 double,
+ * evaluated left to right as written; equal doubles tie, and on a tie the
+ * lower choice index wins. NONE is required for, and only allowed with,
+ * one choice (a Blocked Bloom filter, Section 2.2). */
+typedef enum {
+    BBFC_COST_NONE = 0,
+    BBFC_COST_MIX = 1,
+    BBFC_COST_LA = 2,
+    BBFC_COST_EXP = 3
+} bbfc_cost_kind;
+
+/* kind plus its parameter (sigma, mu or beta). A NaN param selects the
+ * paper's value: sigma 2.5 for k <= 10 and 50 for k >= 11 (the printed
+ * values are 2.5 at k = 7 and 50 at k = 14, App. C), mu 3.5 (App. C),
+ * beta (1 + sqrt 5)/2 (Section 4). Ignored for BBFC_COST_NONE. */
+typedef struct {
+    int32_t kind; /* a bbfc_cost_kind */
+    double param;
+} bbfc_cost;
+
+/* Limits of this build. */
+#define BBFC_MAX_CHOICES 4u
+#define BBFC_MAX_BITS_PER_KEY 32u
+
+/* Create an empty filter of n_blocks 512-bit blocks (64 bytes each, the
+ * allocation is 256-byte aligned) on the current HIP device, with `choices`
+ * candidate blocks per key (c, Section 3.1) and `bits_per_key` bit hashes
+ * (k, Section 3.1: the number of hashes, not the space per key; the space
+ * is fixed by n_blocks). Hash multipliers are drawn from seed 0 (see
+ * bbfc_create_seeded).
+ *   n_blocks >= 1; 1 <= choices <= 4; 1 <= bits_per_key <= 32;
+ *   cost.kind == NONE iff choices == 1.
+ * On success *out receives the handle; on failure *out is left untouched.
+ * Errors: EINVAL (ranges, null out), ENOMEM (filter does not fit), EHIP. */
+bbfc_status bbfc_create(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
+                        bbfc_handle *out);
+
+/* As bbfc_create, with the linear hashes' multipliers (Section 3.4: "a
+ * random large integer a, coprime with b") drawn from a SplitMix64 stream
+ * (Steele, Lea, Flood 2014) started at `seed`: each draw is made odd, draws
+ * below 2^32 or sharing a factor with the modulus are skipped; the first
+ * `choices` accepted draws (modulus n_blocks) are the block multipliers,
+ * the next `bits_per_key` (modulus 512) the bit multipliers. */
+bbfc_status bbfc_create_seeded(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
+                               uint64_t seed, bbfc_handle *out);
+
+/* As bbfc_create, with explicit multipliers: block_mult[choices] (each must
+ * be coprime to n_blocks) and bit_mult[bits_per_key] (each must be odd).
+ * Both arrays are host memory, copied; the caller keeps ownership. */
+bbfc_status bbfc_create_with_multipliers(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key,
+                                         bbfc_cost cost, const uint64_t *block_mult,
+                                         const uint64_t *bit_mult, bbfc_handle *out);
+
+/* Synchronise the device, then free the filter. A null handle is EINVAL. */
+bbfc_status bbfc_destroy(bbfc_handle h);
+
+/* Insert d_keys[0..n) (device memory) with racing atomic inserts
+ * (Sections 3.1, 3.2). Every key's mask ends up in one of its candidates,
+ * so every inserted key queries true afterwards. Keys inserted by the same
+ * call decide on block contents that may miss the bits of keys still in
+ * flight, so the filter may differ from a one-key-at-a-time build; the
+ * library bounds the keys in flight to a fraction of n_blocks (see
+ * bbfc_set_insert_inflight) so that the false-positive rate stays that of
+ * the sequential build. With choices == 1 the result equals the sequential
+ * build bit for bit. n == 0 is a no-op. Errors: EINVAL (null handle, null
+ * keys with n > 0), EHIP. */
+bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipStream_t stream);
+
+/* Insert d_keys[0..n) with exactly the sequential semantics: the result is
+ * the filter obtained by inserting the keys one at a time in index order
+ * (Section 3.2 applied key by key). Runs on a single wavefront; consecutive
+ * keys whose candidate blocks are pairwise disjoint are processed together.
+ * Meant for small inputs and for checking. Errors as bbfc_insert. */
+bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uint64_t n,
+                                      hipStream_t stream);
+
+/* Query d_keys[0..n) (Section 3.1). Writes ceil(n/64) words to d_out_bits
+ * (device memory): bit t mod 64 of word t/64, least significant first, is
+ * the answer for d_keys[t]; bits past n in the last word are zero. The
+ * output must not overlap the keys. Errors: EINVAL (null handle, null
+ * pointers with n > 0), EHIP. */
+bbfc_status bbfc_query(bbfc_handle h, const uint64_t *d_keys, uint64_t n, uint64_t *d_out_bits,
+                       hipStream_t stream);
+
+/* Set every filter bit to zero (stream-ordered, uses a fill kernel). */
+bbfc_status bbfc_clear(bbfc_handle h, hipStream_t stream);
+
+/* Copy all 8*n_blocks filter words from / to host memory. Both synchronise
+ * `stream` before returning. Used to checkpoint and restore a filter. */
+bbfc_status bbfc_upload(bbfc_handle h, const uint64_t *h_words, hipStream_t stream);
+bbfc_status bbfc_download(bbfc_handle h, uint64_t *h_words, hipStream_t stream);
+
+/* Filter shape and hash parameters. Any output pointer may be null;
+ * block_mult receives `choices` words and bit_mult `bits_per_key` words.
+ * cost->param receives the resolved value (never NaN). */
+bbfc_status bbfc_get_params(bbfc_handle h, uint64_t *n_blocks, uint32_t *choices, uint32_t *bits_per_key,
+                            bbfc_cost *cost, uint64_t *block_mult, uint64_t *bit_mult);
+
+/* Device address of the filter words (8*n_blocks uint64, owned by the
+ * library, valid until bbfc_destroy). */
+bbfc_status bbfc_get_words(bbfc_handle h, uint64_t **d_words);
+
+/* Upper bound on keys a racing insert keeps in flight. 0 restores the
+ * default, n_blocks/32 keys (at least one wavefront of 64); a larger bound
+ * is faster on small filters, at the price of decisions on staler block
+ * contents. */
+bbfc_status bbfc_set_insert_inflight(bbfc_handle h, uint64_t max_keys);
+
+/* Number of blocks for n_keys keys at `space_bits_per_key` bits per key:
+ * ceil(n_keys * space_bits_per_key / 512), at least 1 (App. C sizes a
+ * filter by rounding the bit count up to a multiple of 512). */
+uint64_t bbfc_blocks_for(uint64_t n_keys, double space_bits_per_key);
+
+/* Dense integer rank of every cost value, as the device compares them:
+ * out[a*513 + j] for 0 <= a <= k, 0 <= j <= 512 is the number of distinct
+ * doubles cost(j', a') smaller than cost(j, a) over all pairs with
+ * 1 <= a' <= min(j', k); pairs with a == 0, a > j are 0xFFFF. Host memory,
+ * (k+1)*513 entries. Pure host computation (no device needed). */
+bbfc_status bbfc_rank_table(bbfc_cost cost, uint32_t bits_per_key, uint16_t *out);
+
+const char *bbfc_status_string(bbfc_status s);
+const char *bbfc_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* Measurement hooks: the kernels that calibrate the roofline. They do   */
+/* not touch any filter.                                                  */
+/* ------------------------------------------------------------------ */
+
+/* Random 64-byte gathers: n_access reads of whole 64-byte lines at
+ * pseudo-random 64-byte-aligned positions of d_buf (n_lines lines, a power
+ * of two), eight lanes per line, as the filter kernels read blocks. Writes
+ * one checksum word per workgroup into d_sink (>= 65536 words). */
+bbfc_status bbfc_probe_gather64(const uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
+                                uint64_t *d_sink, hipStream_t stream);
+
+/* Random 64-bit atomic ORs: n_access lines, eight lanes each ORing one
+ * word of the line, as the insert kernel writes (n_lines a power of two). */
+bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
+                                hipStream_t stream);
+
+/* Plain streaming copy of n_words words (calibrates traffic counters). */
+bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Host-side checks of the device hashing code (no device needed).      */
+/* ------------------------------------------------------------------ */
+
+/* Block index h(x) in [0, n_blocks) for multiplier a, through the same
+ * source the kernels compile (Section 3.4). */
+uint64_t bbfc_host_block_hash(uint64_t n_blocks, uint64_t a, uint64_t x);
+
+/* Bit address f(x) in [0, 512) for multiplier a (Section 3.4, b = 2^9). */
+uint32_t bbfc_host_bit_hash(uint64_t a, uint64_t x);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBFC_H */

@@ -1,0 +1,318 @@
+"""Blocked Bloom filters with choices on AMD MI355X (gfx950).
+
+Python binding of the C ABI in ``include/bbfc.h``: argument marshalling only.
+Every insert and query runs in the HIP kernels of ``libbbfc.so``; there is no
+CPU fallback, and a missing library raises an error.
+
+Keys are 64-bit CUDA/HIP tensors (``torch.int64`` or ``torch.uint64``; the bits
+are what count). Work is enqueued on the current torch stream unless a
+stream is given.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+__all__ = [
+    "BBFCError",
+    "COST_NONE",
+    "COST_MIX",
+    "COST_LA",
+    "COST_EXP",
+    "Filter",
+    "blocks_for",
+    "rank_table",
+    "host_block_hash",
+    "host_bit_hash",
+    "lib",
+    "library_path",
+    "probe_gather64",
+    "probe_atomic64",
+    "probe_copy",
+    "unpack_bits",
+]
+
+COST_NONE, COST_MIX, COST_LA, COST_EXP = 0, 1, 2, 3
+_COST_BY_NAME = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libbbfc.so")
+
+
+class BBFCError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"bbfc error {status}: {message}")
+        self.status = status
+
+
+class _Cost(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("param", ctypes.c_double)]
+
+
+_lib = None
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_vp = ctypes.c_void_p
+_st = ctypes.c_int
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded ``libbbfc.so``; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(
+            f"{_LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+            "(hipcc --offload-arch=gfx950); there is no fallback path"
+        )
+    L = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "bbfc_create": (_st, [_u64, _u32, _u32, _Cost, _vp]),
+        "bbfc_create_seeded": (_st, [_u64, _u32, _u32, _Cost, _u64, _vp]),
+        "bbfc_create_with_multipliers": (_st, [_u64, _u32, _u32, _Cost, _vp, _vp, _vp]),
+        "bbfc_destroy": (_st, [_vp]),
+        "bbfc_insert": (_st, [_vp, _vp, _u64, _vp]),
+        "bbfc_insert_deterministic": (_st, [_vp, _vp, _u64, _vp]),
+        "bbfc_query": (_st, [_vp, _vp, _u64, _vp, _vp]),
+        "bbfc_clear": (_st, [_vp, _vp]),
+        "bbfc_upload": (_st, [_vp, _vp, _vp]),
+        "bbfc_download": (_st, [_vp, _vp, _vp]),
+        "bbfc_get_params": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+        "bbfc_get_words": (_st, [_vp, _vp]),
+        "bbfc_set_insert_inflight": (_st, [_vp, _u64]),
+        "bbfc_blocks_for": (_u64, [_u64, ctypes.c_double]),
+        "bbfc_rank_table": (_st, [_Cost, _u32, _vp]),
+        "bbfc_status_string": (ctypes.c_char_p, [_st]),
+        "bbfc_last_error": (ctypes.c_char_p, []),
+        "bbfc_probe_gather64": (_st, [_vp, _u64, _u64, _u64, _vp, _vp]),
+        "bbfc_probe_atomic64": (_st, [_vp, _u64, _u64, _u64, _vp]),
+        "bbfc_probe_copy": (_st, [_vp, _vp, _u64, _vp]),
+        "bbfc_host_block_hash": (_u64, [_u64, _u64, _u64]),
+        "bbfc_host_bit_hash": (_u32, [_u64, _u64]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        msg = lib().bbfc_last_error().decode(errors="replace")
+        raise BBFCError(status, msg)
+
+
+def _cost_struct(cost, param) -> _Cost:
+    kind = _COST_BY_NAME[cost] if isinstance(cost, str) else int(cost)
+    return _Cost(kind, float("nan") if param is None else float(param))
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _device_u64(t, what: str):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a GPU tensor")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise TypeError(f"{what} must be int64 or uint64, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t
+
+
+def blocks_for(n_keys: int, space_bits_per_key: float) -> int:
+    return int(lib().bbfc_blocks_for(n_keys, space_bits_per_key))
+
+
+def rank_table(cost, bits_per_key: int, param=None):
+    """The cost rank table as a numpy uint16 array of shape (k+1, 513)."""
+    import numpy as np
+
+    out = np.empty((bits_per_key + 1) * 513, dtype=np.uint16)
+    _check(lib().bbfc_rank_table(_cost_struct(cost, param), bits_per_key, out.ctypes.data))
+    return out.reshape(bits_per_key + 1, 513)
+
+
+def host_block_hash(n_blocks: int, a: int, x: int) -> int:
+    return int(lib().bbfc_host_block_hash(n_blocks, a, x))
+
+
+def host_bit_hash(a: int, x: int) -> int:
+    return int(lib().bbfc_host_bit_hash(a, x))
+
+
+@dataclass(frozen=True)
+class Params:
+    n_blocks: int
+    choices: int
+    bits_per_key: int
+    cost_kind: int
+    cost_param: float
+    block_mult: tuple
+    bit_mult: tuple
+
+
+class Filter:
+    """One filter resident in device memory (owned by the library)."""
+
+    def __init__(self, n_blocks: int, choices: int, bits_per_key: int, cost="none", cost_param=None, *,
+                 seed: int | None = None, block_mult=None, bit_mult=None):
+        L = lib()
+        h = ctypes.c_void_p()
+        cs = _cost_struct(cost, cost_param)
+        if block_mult is not None or bit_mult is not None:
+            if block_mult is None or bit_mult is None:
+                raise ValueError("give both block_mult and bit_mult")
+            bm = (ctypes.c_uint64 * len(block_mult))(*[int(v) for v in block_mult])
+            am = (ctypes.c_uint64 * len(bit_mult))(*[int(v) for v in bit_mult])
+            if len(block_mult) != choices or len(bit_mult) != bits_per_key:
+                raise ValueError("multiplier counts must equal choices and bits_per_key")
+            _check(L.bbfc_create_with_multipliers(n_blocks, choices, bits_per_key, cs, bm, am, ctypes.byref(h)))
+        elif seed is not None:
+            _check(L.bbfc_create_seeded(n_blocks, choices, bits_per_key, cs, seed, ctypes.byref(h)))
+        else:
+            _check(L.bbfc_create(n_blocks, choices, bits_per_key, cs, ctypes.byref(h)))
+        self._h = h
+        self.params = self._read_params()
+
+    # -------------------------------------------------------------- info
+    def _read_params(self) -> Params:
+        M, c, k = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
+        cs = _Cost()
+        bm = (ctypes.c_uint64 * 4)()
+        am = (ctypes.c_uint64 * 32)()
+        _check(lib().bbfc_get_params(self._h, ctypes.byref(M), ctypes.byref(c), ctypes.byref(k), ctypes.byref(cs),
+                                     bm, am))
+        return Params(M.value, c.value, k.value, cs.kind, cs.param, tuple(bm[: c.value]), tuple(am[: k.value]))
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("filter is closed")
+        return self._h
+
+    @property
+    def n_blocks(self) -> int:
+        return self.params.n_blocks
+
+    @property
+    def words_ptr(self) -> int:
+        p = ctypes.c_void_p()
+        _check(lib().bbfc_get_words(self.handle, ctypes.byref(p)))
+        return int(p.value)
+
+    def set_insert_inflight(self, max_keys: int) -> None:
+        _check(lib().bbfc_set_insert_inflight(self.handle, max_keys))
+
+    # -------------------------------------------------------------- ops
+    def insert(self, keys, stream=None) -> None:
+        keys = _device_u64(keys, "keys")
+        _check(lib().bbfc_insert(self.handle, keys.data_ptr(), keys.numel(), _stream_handle(stream)))
+
+    def insert_deterministic(self, keys, stream=None) -> None:
+        keys = _device_u64(keys, "keys")
+        _check(lib().bbfc_insert_deterministic(self.handle, keys.data_ptr(), keys.numel(), _stream_handle(stream)))
+
+    def query(self, keys, out=None, stream=None):
+        """Packed answers: an int64 tensor of ceil(n/64) words (bit t%64 of
+        word t//64 answers keys[t])."""
+        import torch
+
+        keys = _device_u64(keys, "keys")
+        n = keys.numel()
+        n_words = (n + 63) // 64
+        if out is None:
+            out = torch.empty(max(n_words, 1), dtype=torch.int64, device=keys.device)
+        else:
+            out = _device_u64(out, "out")
+            if out.numel() < n_words:
+                raise ValueError("output too small")
+        _check(lib().bbfc_query(self.handle, keys.data_ptr(), n, out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def clear(self, stream=None) -> None:
+        _check(lib().bbfc_clear(self.handle, _stream_handle(stream)))
+
+    def download(self, stream=None):
+        """All filter words as a numpy uint64 array (synchronises)."""
+        import numpy as np
+
+        out = np.empty(8 * self.n_blocks, dtype=np.uint64)
+        _check(lib().bbfc_download(self.handle, out.ctypes.data, _stream_handle(stream)))
+        return out
+
+    def upload(self, words, stream=None) -> None:
+        import numpy as np
+
+        words = np.ascontiguousarray(words, dtype=np.uint64)
+        if words.size != 8 * self.n_blocks:
+            raise ValueError("word count must be 8 * n_blocks")
+        _check(lib().bbfc_upload(self.handle, words.ctypes.data, _stream_handle(stream)))
+
+    def close(self) -> None:
+        if self._h is not None:
+            _check(lib().bbfc_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------- measurement hooks
+
+def probe_gather64(buf, n_access: int, seed: int, sink, stream=None) -> None:
+    if sink.numel() < 65536:
+        raise ValueError("probe sink needs at least 65536 words")
+    n_lines = buf.numel() // 8
+    if n_lines & (n_lines - 1):
+        raise ValueError("probe buffer must hold a power-of-two number of 64-byte lines")
+    _check(lib().bbfc_probe_gather64(buf.data_ptr(), n_lines, n_access, seed, sink.data_ptr(),
+                                     _stream_handle(stream)))
+
+
+def probe_atomic64(buf, n_access: int, seed: int, stream=None) -> None:
+    n_lines = buf.numel() // 8
+    if n_lines & (n_lines - 1):
+        raise ValueError("probe buffer must hold a power-of-two number of 64-byte lines")
+    _check(lib().bbfc_probe_atomic64(buf.data_ptr(), n_lines, n_access, seed, _stream_handle(stream)))
+
+
+def probe_copy(src, dst, stream=None) -> None:
+    n = min(src.numel(), dst.numel())
+    _check(lib().bbfc_probe_copy(src.data_ptr(), dst.data_ptr(), n, _stream_handle(stream)))
+
+
+def unpack_bits(words, n: int):
+    """Packed answer words (torch or numpy) to a numpy bool array of length n."""
+    import numpy as np
+
+    if hasattr(words, "cpu"):
+        words = words.cpu().numpy()
+    w = np.ascontiguousarray(words).view(np.uint64)
+    return np.unpackbits(w.view(np.uint8), bitorder="little")[:n].astype(bool)
+

@@ -1,0 +1,65 @@
+"""Builds the gfx950 HIP library ``libbbfc.so`` in-tree with hipcc."""
+
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libbbfc.so")
+SOURCES = ["bbfc_api.cpp", "bbfc_kernels.hip", "bbfc_probe.hip"]
+HEADERS = ["bbfc_common.hpp", "bbfc_internal.hpp"]
+ARCH = os.environ.get("BBFC_OFFLOAD_ARCH", "gfx950")
+
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    "-fno-strict-aliasing",
+    "-ffp-contract=off",
+    "-Wall",
+    "-Wno-unused-command-line-argument",
+    # packed FP32 instructions stay off in every gfx950 object
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+]
+
+
+def hipcc() -> str:
+    env = os.environ.get("HIPCC")
+    if env:
+        return env
+    found = shutil.which("hipcc")
+    return found or "/opt/rocm/bin/hipcc"
+
+
+def sources() -> list[str]:
+    return [os.path.join(CSRC, s) for s in SOURCES]
+
+
+def build(extra_flags: list[str] | None = None, out: str | None = None, verbose: bool = False) -> str:
+    """Compile every source into ``libbbfc.so`` (always rebuilds)."""
+    out = out or LIB
+    tmp = out + ".tmp"
+    cmd = [hipcc(), *HIP_FLAGS, *(extra_flags or []), "-I", os.path.join(ROOT, "include"), "-o", tmp, *sources()]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def is_stale() -> bool:
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    deps = sources() + [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(ROOT, "include", "bbfc.h")]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,501 @@
+// Host side of the C ABI declared in include/bbfc.h: argument checks, hash
+// parameters, the cost rank table, filter lifetime and kernel launches.
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "bbfc_common.hpp"
+#include "bbfc_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bbfc_status fail(bbfc_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+bbfc_status fail(bbfc_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+bbfc_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(BBFC_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Makes the filter's device current for the scope of a call.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev_) == hipSuccess && prev_ != dev && hipSetDevice(dev) == hipSuccess)
+            switched_ = true;
+    }
+    ~DeviceGuard()
+    {
+        if (switched_)
+            (void)hipSetDevice(prev_);
+    }
+
+  private:
+    int prev_ = -1;
+    bool switched_ = false;
+};
+
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): golden-gamma increment and
+// the variant-13 finaliser.
+uint64_t splitmix64(uint64_t &state)
+{
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t gcd_u64(uint64_t a, uint64_t b)
+{
+    while (b != 0) {
+        const uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+bool is_pow2(uint64_t v) { return v != 0 && (v & (v - 1)) == 0; }
+
+// The paper's parameter values: sigma (MIX) is printed for k = 7 (2.5) and
+// k = 14 (50) in App. C; other k take the value of the nearer printed k.
+// mu = 3.5 (App. C); beta = golden ratio (Section 4, App. C).
+double default_param(int32_t kind, uint32_t k)
+{
+    switch (kind) {
+    case BBFC_COST_MIX:
+        return k <= 10 ? 2.5 : 50.0;
+    case BBFC_COST_LA:
+        return 3.5;
+    case BBFC_COST_EXP:
+        return (1.0 + sqrt(5.0)) / 2.0;
+    default:
+        return 0.0;
+    }
+}
+
+// Insertion cost of a candidate whose block would hold j bits after the
+// insertion, a of them new (App. A eqs. cost:mix, cost:la, cost:exp),
+// evaluated left to right in double.
+double cost_value(int32_t kind, double param, uint32_t k, uint32_t j, uint32_t a)
+{
+    const double dk = (double)k;
+    switch (kind) {
+    case BBFC_COST_MIX:
+        return param * dk * pow((double)j / 256.0, dk) + (double)a;
+    case BBFC_COST_LA:
+        return dk * pow(((double)j + param * dk) / 256.0, dk) + (double)a;
+    case BBFC_COST_EXP:
+        return pow(param, (double)j / 128.0) + (double)a / dk;
+    default:
+        return 0.0;
+    }
+}
+
+// Dense rank of cost(j, a) among all feasible pairs 1 <= a <= min(j, k),
+// j <= 512: equal doubles share a rank, so rank order is double order.
+std::vector<uint16_t> build_rank_table(int32_t kind, double param, uint32_t k)
+{
+    const uint32_t stride = 513;
+    std::vector<uint16_t> table((size_t)(k + 1) * stride, 0xFFFF);
+    std::vector<std::pair<double, uint32_t>> all;
+    all.reserve((size_t)k * stride);
+    for (uint32_t a = 1; a <= k; ++a)
+        for (uint32_t j = a; j <= 512; ++j)
+            all.emplace_back(cost_value(kind, param, k, j, a), a * stride + j);
+    std::sort(all.begin(), all.end());
+    uint16_t rank = 0;
+    for (size_t i = 0; i < all.size(); ++i) {
+        if (i > 0 && all[i].first != all[i - 1].first)
+            ++rank;
+        table[all[i].second] = rank;
+    }
+    return table;
+}
+
+bbfc_status check_shape(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_cost cost)
+{
+    if (n_blocks < 1)
+        return fail(BBFC_EINVAL, "n_blocks must be >= 1");
+    if (n_blocks > (UINT64_MAX / 64))
+        return fail(BBFC_EINVAL, "n_blocks too large");
+    if (choices < 1 || choices > BBFC_MAX_CHOICES)
+        return fail(BBFC_EINVAL, "choices must be in [1, %u], got %u", BBFC_MAX_CHOICES, choices);
+    if (k < 1 || k > BBFC_MAX_BITS_PER_KEY)
+        return fail(BBFC_EINVAL, "bits_per_key must be in [1, %u], got %u", BBFC_MAX_BITS_PER_KEY, k);
+    if (choices == 1 && cost.kind != BBFC_COST_NONE)
+        return fail(BBFC_EINVAL, "one choice takes BBFC_COST_NONE");
+    if (choices > 1 && (cost.kind < BBFC_COST_MIX || cost.kind > BBFC_COST_EXP))
+        return fail(BBFC_EINVAL, "choices > 1 needs a cost kind MIX, LA or EXP, got %d", (int)cost.kind);
+    if (choices > 1 && !isnan(cost.param) && !isfinite(cost.param))
+        return fail(BBFC_EINVAL, "cost parameter must be finite or NaN");
+    if (cost.kind == BBFC_COST_EXP && !isnan(cost.param) && !(cost.param > 0.0))
+        return fail(BBFC_EINVAL, "EXP base must be > 0");
+    return BBFC_OK;
+}
+
+bbfc_status create_impl(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_cost cost, const uint64_t *block_mult,
+                        const uint64_t *bit_mult, bbfc_handle *out)
+{
+    if (out == nullptr)
+        return fail(BBFC_EINVAL, "out handle pointer is null");
+    bbfc_status st = check_shape(n_blocks, choices, k, cost);
+    if (st != BBFC_OK)
+        return st;
+    for (uint32_t i = 0; i < choices; ++i)
+        if (gcd_u64(block_mult[i], n_blocks) != 1 && n_blocks != 1)
+            return fail(BBFC_EINVAL, "block multiplier %u is not coprime to n_blocks", i);
+    for (uint32_t i = 0; i < k; ++i)
+        if ((bit_mult[i] & 1) == 0)
+            return fail(BBFC_EINVAL, "bit multiplier %u is even", i);
+
+    auto *f = new bbfc_filter();
+    f->M = n_blocks;
+    f->c = choices;
+    f->k = k;
+    f->cost_kind = choices > 1 ? cost.kind : BBFC_COST_NONE;
+    f->cost_param = choices > 1 ? (isnan(cost.param) ? default_param(cost.kind, k) : cost.param) : 0.0;
+    memcpy(f->block_mult, block_mult, choices * sizeof(uint64_t));
+    memcpy(f->bit_mult, bit_mult, k * sizeof(uint64_t));
+    if (n_blocks == 1) {
+        f->hash_mode = bbfc::kModeOne;
+    } else if (is_pow2(n_blocks)) {
+        f->hash_mode = bbfc::kModePow2;
+        f->pow2_shift = 64u - (uint32_t)__builtin_ctzll(n_blocks);
+    } else {
+        f->hash_mode = (n_blocks & 1) ? bbfc::kModeOdd : bbfc::kModeEven;
+    }
+    f->fm = bbfc::make_fastmod(n_blocks);
+
+    hipError_t e = hipGetDevice(&f->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&f->num_cus, hipDeviceAttributeMultiprocessorCount, f->device);
+    if (e != hipSuccess) {
+        delete f;
+        return hip_fail(e, "querying the current device");
+    }
+    e = hipMalloc(&f->d_words, n_blocks * 64);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete f;
+        return fail(BBFC_ENOMEM, "hipMalloc of %llu bytes failed: %s", (unsigned long long)(n_blocks * 64),
+                    hipGetErrorString(e));
+    }
+    if (choices > 1) {
+        f->h_rank = build_rank_table(f->cost_kind, f->cost_param, k);
+        const size_t bytes = f->h_rank.size() * sizeof(uint16_t);
+        e = hipMalloc(&f->d_rank, bytes);
+        if (e == hipSuccess)
+            e = hipMemcpy(f->d_rank, f->h_rank.data(), bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(f->d_words);
+            if (f->d_rank)
+                (void)hipFree(f->d_rank);
+            delete f;
+            return hip_fail(e, "uploading the rank table");
+        }
+    }
+    e = bbfc::launch_fill_zero(f->d_words, n_blocks * 8, nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(f->d_words);
+        if (f->d_rank)
+            (void)hipFree(f->d_rank);
+        delete f;
+        return hip_fail(e, "clearing a new filter");
+    }
+    *out = f;
+    return BBFC_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+bbfc_status bbfc_create_with_multipliers(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
+                                         const uint64_t *block_mult, const uint64_t *bit_mult, bbfc_handle *out)
+{
+    if (block_mult == nullptr || bit_mult == nullptr)
+        return fail(BBFC_EINVAL, "multiplier arrays must not be null");
+    return create_impl(n_blocks, choices, bits_per_key, cost, block_mult, bit_mult, out);
+}
+
+bbfc_status bbfc_create_seeded(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
+                               uint64_t seed, bbfc_handle *out)
+{
+    bbfc_status st = check_shape(n_blocks, choices, bits_per_key, cost);
+    if (st != BBFC_OK)
+        return st;
+    uint64_t bm[BBFC_MAX_CHOICES];
+    uint64_t am[BBFC_MAX_BITS_PER_KEY];
+    uint64_t state = seed;
+    for (uint32_t i = 0; i < choices;) {
+        const uint64_t a = splitmix64(state) | 1;
+        if (a >= (1ull << 32) && gcd_u64(a, n_blocks) == 1)
+            bm[i++] = a;
+    }
+    for (uint32_t i = 0; i < bits_per_key;) {
+        const uint64_t a = splitmix64(state) | 1;
+        if (a >= (1ull << 32))
+            am[i++] = a;
+    }
+    return create_impl(n_blocks, choices, bits_per_key, cost, bm, am, out);
+}
+
+bbfc_status bbfc_create(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
+                        bbfc_handle *out)
+{
+    return bbfc_create_seeded(n_blocks, choices, bits_per_key, cost, 0, out);
+}
+
+bbfc_status bbfc_destroy(bbfc_handle h)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    DeviceGuard guard(h->device);
+    hipError_t e = hipDeviceSynchronize();
+    hipError_t e1 = hipFree(h->d_words);
+    hipError_t e2 = h->d_rank ? hipFree(h->d_rank) : hipSuccess;
+    delete h;
+    if (e != hipSuccess)
+        return hip_fail(e, "synchronising before destroy");
+    if (e1 != hipSuccess)
+        return hip_fail(e1, "freeing the filter");
+    if (e2 != hipSuccess)
+        return hip_fail(e2, "freeing the rank table");
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (n == 0)
+        return BBFC_OK;
+    if (d_keys == nullptr)
+        return fail(BBFC_EINVAL, "null keys with n = %llu", (unsigned long long)n);
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_insert(*h, d_keys, n, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching insert");
+}
+
+bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (n == 0)
+        return BBFC_OK;
+    if (d_keys == nullptr)
+        return fail(BBFC_EINVAL, "null keys with n = %llu", (unsigned long long)n);
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_insert_det(*h, d_keys, n, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching deterministic insert");
+}
+
+bbfc_status bbfc_query(bbfc_handle h, const uint64_t *d_keys, uint64_t n, uint64_t *d_out_bits, hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (n == 0)
+        return BBFC_OK;
+    if (d_keys == nullptr || d_out_bits == nullptr)
+        return fail(BBFC_EINVAL, "null keys or output with n = %llu", (unsigned long long)n);
+    const uintptr_t k0 = (uintptr_t)d_keys, k1 = k0 + n * 8;
+    const uintptr_t o0 = (uintptr_t)d_out_bits, o1 = o0 + ((n + 63) / 64) * 8;
+    if (k0 < o1 && o0 < k1)
+        return fail(BBFC_EINVAL, "output overlaps the keys");
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_query(*h, d_keys, n, d_out_bits, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching query");
+}
+
+bbfc_status bbfc_clear(bbfc_handle h, hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_fill_zero(h->d_words, h->M * 8, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching clear");
+}
+
+bbfc_status bbfc_upload(bbfc_handle h, const uint64_t *h_words, hipStream_t stream)
+{
+    if (h == nullptr || h_words == nullptr)
+        return fail(BBFC_EINVAL, "null handle or host buffer");
+    DeviceGuard guard(h->device);
+    hipError_t e = hipMemcpyAsync(h->d_words, h_words, h->M * 64, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "uploading filter words");
+}
+
+bbfc_status bbfc_download(bbfc_handle h, uint64_t *h_words, hipStream_t stream)
+{
+    if (h == nullptr || h_words == nullptr)
+        return fail(BBFC_EINVAL, "null handle or host buffer");
+    DeviceGuard guard(h->device);
+    hipError_t e = hipMemcpyAsync(h_words, h->d_words, h->M * 64, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "downloading filter words");
+}
+
+bbfc_status bbfc_get_params(bbfc_handle h, uint64_t *n_blocks, uint32_t *choices, uint32_t *bits_per_key,
+                            bbfc_cost *cost, uint64_t *block_mult, uint64_t *bit_mult)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (n_blocks)
+        *n_blocks = h->M;
+    if (choices)
+        *choices = h->c;
+    if (bits_per_key)
+        *bits_per_key = h->k;
+    if (cost) {
+        cost->kind = h->cost_kind;
+        cost->param = h->cost_param;
+    }
+    if (block_mult)
+        memcpy(block_mult, h->block_mult, h->c * sizeof(uint64_t));
+    if (bit_mult)
+        memcpy(bit_mult, h->bit_mult, h->k * sizeof(uint64_t));
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_get_words(bbfc_handle h, uint64_t **d_words)
+{
+    if (h == nullptr || d_words == nullptr)
+        return fail(BBFC_EINVAL, "null handle or output pointer");
+    *d_words = h->d_words;
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_set_insert_inflight(bbfc_handle h, uint64_t max_keys)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    h->max_inflight = max_keys;
+    return BBFC_OK;
+}
+
+uint64_t bbfc_blocks_for(uint64_t n_keys, double space_bits_per_key)
+{
+    if (!(space_bits_per_key > 0.0) || n_keys == 0)
+        return 1;
+    const double blocks = ceil((double)n_keys * space_bits_per_key / 512.0);
+    return blocks < 1.0 ? 1 : (uint64_t)blocks;
+}
+
+bbfc_status bbfc_rank_table(bbfc_cost cost, uint32_t bits_per_key, uint16_t *out)
+{
+    if (out == nullptr)
+        return fail(BBFC_EINVAL, "null output");
+    bbfc_status st = check_shape(1, 2, bits_per_key, cost);
+    if (st != BBFC_OK)
+        return st;
+    const double param = isnan(cost.param) ? default_param(cost.kind, bits_per_key) : cost.param;
+    std::vector<uint16_t> t = build_rank_table(cost.kind, param, bits_per_key);
+    memcpy(out, t.data(), t.size() * sizeof(uint16_t));
+    return BBFC_OK;
+}
+
+const char *bbfc_status_string(bbfc_status s)
+{
+    switch (s) {
+    case BBFC_OK:
+        return "ok";
+    case BBFC_EINVAL:
+        return "invalid argument";
+    case BBFC_ENOMEM:
+        return "out of device memory";
+    case BBFC_EHIP:
+        return "HIP runtime error";
+    case BBFC_EUNSUPPORTED:
+        return "unsupported";
+    default:
+        return "unknown status";
+    }
+}
+
+const char *bbfc_last_error(void)
+{
+    return g_last_error.c_str();
+}
+
+bbfc_status bbfc_probe_gather64(const uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
+                                uint64_t *d_sink, hipStream_t stream)
+{
+    if (d_buf == nullptr || d_sink == nullptr || !is_pow2(n_lines))
+        return fail(BBFC_EINVAL, "probe needs buffers and a power-of-two line count");
+    hipError_t e = bbfc::launch_probe_gather64(d_buf, n_lines, n_access, seed, d_sink, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching gather probe");
+}
+
+bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
+                                hipStream_t stream)
+{
+    if (d_buf == nullptr || !is_pow2(n_lines))
+        return fail(BBFC_EINVAL, "probe needs a buffer and a power-of-two line count");
+    hipError_t e = bbfc::launch_probe_atomic64(d_buf, n_lines, n_access, seed, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching atomic probe");
+}
+
+bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, hipStream_t stream)
+{
+    if (d_src == nullptr || d_dst == nullptr)
+        return fail(BBFC_EINVAL, "null buffer");
+    hipError_t e = bbfc::launch_probe_copy(d_src, d_dst, n_words, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching copy probe");
+}
+
+uint64_t bbfc_host_block_hash(uint64_t n_blocks, uint64_t a, uint64_t x)
+{
+    if (n_blocks == 0)
+        return 0;
+    bbfc::KParams p{};
+    p.M = n_blocks;
+    const bbfc::FastMod fm = bbfc::make_fastmod(n_blocks);
+    p.fm_magic = fm.magic;
+    p.fm_sh1 = fm.sh1;
+    p.fm_sh2 = fm.sh2;
+    if (n_blocks == 1)
+        return bbfc::block_hash<bbfc::kModeOne>(p, a, x);
+    if (is_pow2(n_blocks)) {
+        p.pow2_shift = 64u - (uint32_t)__builtin_ctzll(n_blocks);
+        return bbfc::block_hash<bbfc::kModePow2>(p, a, x);
+    }
+    if (n_blocks & 1)
+        return bbfc::block_hash<bbfc::kModeOdd>(p, a, x);
+    return bbfc::block_hash<bbfc::kModeEven>(p, a, x);
+}
+
+uint32_t bbfc_host_bit_hash(uint64_t a, uint64_t x)
+{
+    return bbfc::bit_hash(a, x);
+}
+
+} // extern "C"

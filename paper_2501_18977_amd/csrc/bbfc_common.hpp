@@ -1,0 +1,104 @@
+// Shared host/device definitions of the filter library (not part of the ABI).
+//
+// Hashing follows Section 3.4 of the paper: x -> ((a*x) mod 2^64) mod b, where
+// for b = 2^s the s most significant bits of a*x are used, and for even b
+// that is not a power of two the high 32 bits are xor-folded into the low
+// bits before the remainder. Keys are always treated as 64-bit words.
+#pragma once
+
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/bbfc.h"
+
+namespace bbfc {
+
+// How block addresses reduce a*x into [0, M).
+enum HashMode : int {
+    kModeOne = 0,  // M == 1: every key maps to block 0
+    kModePow2 = 1, // M == 2^s: top s bits
+    kModeEven = 2, // M even, not 2^s: fold, then remainder
+    kModeOdd = 3,  // M odd: remainder
+};
+
+// Remainder by an invariant 64-bit divisor d >= 1 without a division
+// instruction: Granlund and Montgomery, "Division by invariant integers
+// using multiplication" (PLDI 1994), Fig. 4.1 with N = 64:
+//   l = ceil(log2 d), m' = floor(2^64 (2^l - d) / d) + 1,
+//   t = mulhi(m', n), q = (t + ((n - t) >> sh1)) >> sh2,
+//   sh1 = min(l, 1), sh2 = max(l - 1, 0);  r = n - q d.
+struct FastMod {
+    uint64_t d;
+    uint64_t magic;
+    uint32_t sh1;
+    uint32_t sh2;
+};
+
+inline FastMod make_fastmod(uint64_t d)
+{
+    FastMod fm{};
+    fm.d = d;
+    uint32_t l = 0;
+    while (l < 64 && (((unsigned __int128)1 << l) < d))
+        l++;
+    unsigned __int128 two_l = (unsigned __int128)1 << l;
+    unsigned __int128 num = (((unsigned __int128)1) << 64) * (two_l - d);
+    fm.magic = (uint64_t)(num / d + 1);
+    fm.sh1 = l < 1 ? l : 1;
+    fm.sh2 = l > 0 ? l - 1 : 0;
+    return fm;
+}
+
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ inline uint64_t fastmod(uint64_t n, uint64_t d, uint64_t magic, uint32_t sh1, uint32_t sh2)
+{
+    uint64_t t = mulhi64(magic, n);
+    uint64_t q = (t + ((n - t) >> sh1)) >> sh2;
+    return n - q * d;
+}
+
+// Everything a kernel needs to address the filter, passed by value.
+struct KParams {
+    uint64_t *words;        // 8*M words, block b = words[8b .. 8b+8)
+    const uint16_t *rank;   // (k+1)*513 cost ranks, index a*513 + j
+    uint64_t M;
+    uint64_t fm_magic;      // FastMod of M (modes Even, Odd)
+    uint32_t fm_sh1;
+    uint32_t fm_sh2;
+    uint32_t pow2_shift;    // 64 - log2(M) (mode Pow2)
+    uint32_t k;
+    uint64_t block_mult[BBFC_MAX_CHOICES];
+    uint64_t bit_mult[BBFC_MAX_BITS_PER_KEY];
+};
+
+template <int MODE>
+__host__ __device__ inline uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x)
+{
+    uint64_t prod = a * x;
+    if constexpr (MODE == kModeOne) {
+        return 0;
+    } else if constexpr (MODE == kModePow2) {
+        return prod >> p.pow2_shift;
+    } else if constexpr (MODE == kModeEven) {
+        return fastmod(prod ^ (prod >> 32), p.M, p.fm_magic, p.fm_sh1, p.fm_sh2);
+    } else {
+        return fastmod(prod, p.M, p.fm_magic, p.fm_sh1, p.fm_sh2);
+    }
+}
+
+// Bit address in [0, 512): the top 9 bits of a*x (b = 512 = 2^9).
+__host__ __device__ inline uint32_t bit_hash(uint64_t a, uint64_t x)
+{
+    return (uint32_t)((a * x) >> 55);
+}
+
+} // namespace bbfc

@@ -1,0 +1,48 @@
+// Library-internal state and kernel launchers (not part of the ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include <vector>
+
+#include "bbfc_common.hpp"
+
+struct bbfc_filter {
+    uint64_t M = 0;
+    uint32_t c = 0;
+    uint32_t k = 0;
+    int32_t cost_kind = BBFC_COST_NONE;
+    double cost_param = 0.0;
+    uint64_t block_mult[BBFC_MAX_CHOICES] = {};
+    uint64_t bit_mult[BBFC_MAX_BITS_PER_KEY] = {};
+    int hash_mode = bbfc::kModeOne;
+    bbfc::FastMod fm{};
+    uint32_t pow2_shift = 0;
+    uint64_t *d_words = nullptr;  // 8*M words
+    uint16_t *d_rank = nullptr;   // (k+1)*513 ranks, null for one choice
+    std::vector<uint16_t> h_rank;
+    int device = 0;
+    int num_cus = 0;
+    uint64_t max_inflight = 0;    // 0: n_blocks/32
+};
+
+namespace bbfc {
+
+KParams make_kparams(const bbfc_filter &f);
+
+// Keys in flight for a racing insert on this filter.
+uint64_t insert_inflight(const bbfc_filter &f);
+
+hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
+hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
+hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out,
+                        hipStream_t s);
+hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s);
+
+hipError_t launch_probe_gather64(const uint64_t *buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
+                                 uint64_t *sink, hipStream_t s);
+hipError_t launch_probe_atomic64(uint64_t *buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
+                                 hipStream_t s);
+hipError_t launch_probe_copy(const uint64_t *src, uint64_t *dst, uint64_t n_words, hipStream_t s);
+
+} // namespace bbfc

@@ -1,0 +1,131 @@
+// Roofline probes: the memory access patterns of the filter kernels without
+// the filter arithmetic. They measure what the device sustains for random
+// 64-byte line reads and random 64-bit atomic ORs, eight lanes per line as
+// in the insert and query kernels, and a plain streaming copy whose byte
+// count calibrates the hardware traffic counters.
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "bbfc_internal.hpp"
+
+namespace bbfc {
+
+namespace {
+
+constexpr int kProbeWG = 256;
+
+// Counter-based line index (SplitMix64 finaliser of seed + i).
+__device__ inline uint64_t probe_line(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Each wavefront handles 64 accesses per iteration: lane (g, w) reads word w
+// of line 8g + r in round r, with all eight rounds in flight at once.
+__global__ __launch_bounds__(kProbeWG) void probe_gather64_kernel(const uint64_t *__restrict__ buf, uint64_t line_mask,
+                                                                  uint64_t n_access, uint64_t seed,
+                                                                  uint64_t *__restrict__ sink)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = lane >> 3;
+    const uint32_t w = lane & 7;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    uint64_t acc = 0;
+    for (uint64_t base = wave * 64; base < n_access; base += n_waves * 64) {
+        uint64_t v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint64_t a = base + g * 8 + r;
+            v[r] = 0;
+            if (a < n_access)
+                v[r] = buf[(probe_line(seed, a) & line_mask) * 8 + w];
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            acc += v[r];
+    }
+    // Stored only in the (practically impossible) case of a magic sum, so
+    // the loads cannot be removed and nothing else is written.
+    if (acc == 0x9E3779B97F4A7C15ull)
+        sink[blockIdx.x & 0xFFFF] = acc;
+}
+
+__global__ __launch_bounds__(kProbeWG) void probe_atomic64_kernel(uint64_t *__restrict__ buf, uint64_t line_mask,
+                                                                  uint64_t n_access, uint64_t seed)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = lane >> 3;
+    const uint32_t w = lane & 7;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t base = wave * 64; base < n_access; base += n_waves * 64) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint64_t a = base + g * 8 + r;
+            if (a < n_access) {
+                const uint64_t h = probe_line(seed, a);
+                __hip_atomic_fetch_or(&buf[(h & line_mask) * 8 + w], 1ull << ((h >> 58) ^ w), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kProbeWG) void probe_copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                              uint64_t n_vec)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_vec; i += stride)
+        dst[i] = src[i];
+}
+
+uint32_t probe_grid(const void *kernel)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kProbeWG, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (cus < 1)
+        cus = 1;
+    return (uint32_t)(per_cu * cus);
+}
+
+} // namespace
+
+hipError_t launch_probe_gather64(const uint64_t *buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
+                                 uint64_t *sink, hipStream_t s)
+{
+    uint32_t grid = probe_grid((const void *)probe_gather64_kernel);
+    const uint64_t need = (n_access + 255) / 256;
+    if (need < grid)
+        grid = (uint32_t)(need ? need : 1);
+    hipLaunchKernelGGL(probe_gather64_kernel, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_access, seed, sink);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_atomic64(uint64_t *buf, uint64_t n_lines, uint64_t n_access, uint64_t seed, hipStream_t s)
+{
+    uint32_t grid = probe_grid((const void *)probe_atomic64_kernel);
+    const uint64_t need = (n_access + 255) / 256;
+    if (need < grid)
+        grid = (uint32_t)(need ? need : 1);
+    hipLaunchKernelGGL(probe_atomic64_kernel, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_access, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_copy(const uint64_t *src, uint64_t *dst, uint64_t n_words, hipStream_t s)
+{
+    const uint64_t n_vec = n_words / 2; // whole 16-byte vectors; an odd last word is not copied
+    uint32_t grid = probe_grid((const void *)probe_copy_kernel) * 2;
+    hipLaunchKernelGGL(probe_copy_kernel, dim3(grid), dim3(kProbeWG), 0, s, reinterpret_cast<const uint4 *>(src),
+                       reinterpret_cast<uint4 *>(dst), n_vec);
+    return hipGetLastError();
+}
+
+} // namespace bbfc

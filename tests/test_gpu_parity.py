@@ -1,0 +1,265 @@
+"""Parity of the HIP path with the sequential oracle (GPU only).
+
+Every check runs the kernels through the C ABI and compares with the oracle
+on the same seeded inputs:
+
+* query: bit-exact on filters the oracle built (uploaded to the device);
+* deterministic insert: filter words bit-exact with the oracle's;
+* racing insert with one choice: bit-exact (the result is order-free);
+* racing insert with choices: zero false negatives, every set bit lies in
+  the oracle's envelope (each key's mask in all of its candidates), and the
+  false-positive rate within 2% relative of the oracle's sequential build.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2501_18977_amd as bbfc
+import workload
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+COSTS = {"none": oracle.COST_NONE, "mix": oracle.COST_MIX, "la": oracle.COST_LA, "exp": oracle.COST_EXP}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def to_dev(a: np.ndarray, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to(dev)
+
+
+def from_dev(t) -> np.ndarray:
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def make_pair(M, c, k, cost, seed):
+    bm = workload.draw_multipliers(seed, c, coprime_to=M)
+    am = workload.draw_multipliers(seed + 7919, k)
+    ref = oracle.OracleFilter(M, c, k, COSTS[cost], None, bm, am)
+    gpu = bbfc.Filter(M, c, k, cost, block_mult=bm, bit_mult=am)
+    return ref, gpu
+
+
+# (M, c, k, cost, keys): every hash mode (M = 1, 2^s, even, odd), c = 1..4,
+# all costs, k from 1 to 32, loads from light to overloaded.
+SMALL_CONFIGS = [
+    (1, 2, 5, "exp", 40),
+    (8, 3, 6, "mix", 300),
+    (1 << 10, 2, 14, "la", 16 * 1024 // 16 * 32),
+    (3000, 3, 8, "mix", 3000 * 512 // 12),
+    (1001, 2, 11, "exp", 1001 * 512 // 16),
+    (1 << 15, 1, 10, "none", (1 << 15) * 512 // 16),
+    (777, 4, 20, "la", 777 * 512 // 24),
+    (1 << 12, 2, 32, "exp", (1 << 12) * 512 // 48),
+    (1 << 12, 2, 1, "exp", 20000),
+    (6, 2, 7, "la", 500),
+]
+
+
+def test_device_keys_match_numpy_generator(dev):
+    got = from_dev(workload.device_keys(99, 12345, 100003, device=dev))
+    want = workload.splitmix64_keys(99, 12345, 100003)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("M,c,k,cost,n", SMALL_CONFIGS)
+def test_query_bits_match_oracle_on_oracle_built_filter(dev, M, c, k, cost, n):
+    ref, gpu = make_pair(M, c, k, cost, seed=M + 31 * c + k)
+    try:
+        keys = workload.positive_keys(M + k, n)
+        ref.insert(keys)
+        gpu.upload(ref.words)
+        probe = np.concatenate([keys, workload.negative_keys(M + k, n, n + 4321)])
+        got = from_dev(gpu.query(to_dev(probe, dev)))
+        want = ref.query_bits(probe)
+        assert np.array_equal(got, want)
+        assert bbfc.unpack_bits(got, len(probe))[:n].all()
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 4097])
+def test_query_ragged_sizes(dev, n):
+    ref, gpu = make_pair(257, 2, 9, "exp", seed=n)
+    try:
+        ref.insert(workload.positive_keys(5, 3000))
+        gpu.upload(ref.words)
+        probe = np.concatenate([workload.positive_keys(5, n // 2), workload.negative_keys(5, 3000, n - n // 2)])
+        out = torch.full((n // 64 + 3,), -1, dtype=torch.int64, device=dev)
+        gpu.query(to_dev(probe, dev), out=out)
+        got = from_dev(out)
+        want = ref.query_bits(probe)
+        nw = (n + 63) // 64
+        assert np.array_equal(got[:nw], want)
+        assert np.all(got[nw:] == np.uint64(2**64 - 1)), "wrote past ceil(n/64) words"
+    finally:
+        gpu.close()
+
+
+def test_empty_calls_are_noops(dev):
+    gpu = bbfc.Filter(64, 2, 8, "la", seed=1)
+    try:
+        empty = torch.empty(0, dtype=torch.int64, device=dev)
+        out = torch.full((2,), 7, dtype=torch.int64, device=dev)
+        gpu.insert(empty)
+        gpu.insert_deterministic(empty)
+        gpu.query(empty, out=out)
+        assert from_dev(out).tolist() == [7, 7]
+        assert not gpu.download().any()
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("M,c,k,cost,n", SMALL_CONFIGS)
+def test_deterministic_insert_is_bit_exact(dev, M, c, k, cost, n):
+    ref, gpu = make_pair(M, c, k, cost, seed=3 * M + c + k)
+    try:
+        keys = workload.positive_keys(2 * M + k, n)
+        keys = np.concatenate([keys, keys[: n // 10]])  # repeats take the already-present rule
+        ref.insert(keys)
+        split = len(keys) // 3
+        gpu.insert_deterministic(to_dev(keys[:split], dev))
+        gpu.insert_deterministic(to_dev(keys[split:], dev))
+        got = gpu.download()
+        assert np.array_equal(got, ref.words)
+    finally:
+        gpu.close()
+
+
+def test_deterministic_insert_default_parameters_match_oracle_derivation(dev):
+    """bbfc_create draws multipliers from SplitMix64 seed 0; the oracle
+    derives its own from the same published generator."""
+    M, c, k = 3000, 3, 8
+    gpu = bbfc.Filter(M, c, k, "mix")
+    try:
+        bm, am = oracle.derive_multipliers(0, M, c, k)
+        assert list(gpu.params.block_mult) == bm and list(gpu.params.bit_mult) == am
+        assert gpu.params.cost_param == oracle.default_param(oracle.COST_MIX, k)
+        ref = oracle.OracleFilter(M, c, k, oracle.COST_MIX, None, seed=0)
+        keys = workload.positive_keys(77, 50000)
+        ref.insert(keys)
+        gpu.insert_deterministic(to_dev(keys, dev))
+        assert np.array_equal(gpu.download(), ref.words)
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("M", [1, 64, 1 << 16, 3000, 1001])
+def test_one_choice_racing_insert_is_bit_exact(dev, M):
+    ref, gpu = make_pair(M, 1, 10, "none", seed=M)
+    try:
+        keys = workload.positive_keys(M, 200_000)
+        ref.insert(keys)
+        gpu.insert(to_dev(keys, dev))
+        assert np.array_equal(gpu.download(), ref.words)
+    finally:
+        gpu.close()
+
+
+def _fpr_gate(ref, gpu_words, n_keys, seed, dev, gpu):
+    """Conditional FPR (low variance) within 2% and raw FP counts within 4
+    binomial sigma, over 2^24 disjoint negatives."""
+    n_neg = 1 << 24
+    neg_d = workload.device_keys(seed, n_keys, n_neg, device=dev)
+    neg = from_dev(neg_d)
+    est_gpu = ref.conditional_fpr(neg, words=gpu_words)
+    est_ref = ref.conditional_fpr(neg)
+    rel = abs(est_gpu - est_ref) / est_ref
+    hits_gpu = int(bbfc.unpack_bits(from_dev(gpu.query(neg_d)), n_neg).sum())
+    hits_ref = ref.count_hits(neg)
+    sd = math.sqrt(hits_gpu + hits_ref)
+    print(f"conditional FPR gpu={est_gpu:.4e} oracle={est_ref:.4e} rel={rel:.4%}; "
+          f"raw FP gpu={hits_gpu} oracle={hits_ref} ({(hits_gpu - hits_ref) / max(sd, 1):+.2f} sigma)", flush=True)
+    assert rel < 0.02
+    assert abs(hits_gpu - hits_ref) < 4 * sd
+    return est_gpu, est_ref
+
+
+@pytest.mark.parametrize("M,c,k,cost,n", [
+    (1 << 15, 2, 14, "la", 1 << 20),     # 2^20 keys, 16 bits/key, LA
+    (1 << 14, 3, 8, "mix", 3 << 18),    # three choices, MIX, ~10.7 bits/key
+    (3000, 2, 11, "exp", 3000 * 32),    # even non-power-of-two M, EXP
+])
+def test_racing_insert_invariants_and_fpr(dev, M, c, k, cost, n):
+    ref, gpu = make_pair(M, c, k, cost, seed=c * k + M)
+    try:
+        keys_d = workload.device_keys(M, 0, n, device=dev)
+        keys = from_dev(keys_d)
+        ref.insert(keys)
+        gpu.insert(keys_d)
+        hits = bbfc.unpack_bits(from_dev(gpu.query(keys_d)), n)
+        assert hits.all(), f"{(~hits).sum()} false negatives"
+        words = gpu.download()
+        env = ref.envelope(keys)
+        assert not np.any(words & ~env), "a set bit no key could have set"
+        # the oracle's own query on the downloaded filter agrees (sampled)
+        sample = keys[:: max(1, n // 4096)]
+        chk = oracle.OracleFilter(M, c, k, COSTS[cost], None, ref.block_mult, ref.bit_mult)
+        chk.words[:] = words
+        assert chk.query(sample).all()
+        _fpr_gate(ref, words, n, M + 1, dev, gpu)
+    finally:
+        gpu.close()
+
+
+def test_upload_download_clear_roundtrip(dev):
+    gpu = bbfc.Filter(513, 2, 9, "exp", seed=3)
+    try:
+        w = workload.splitmix64_keys(1, 0, 8 * 513)
+        gpu.upload(w)
+        assert np.array_equal(gpu.download(), w)
+        gpu.clear()
+        assert not gpu.download().any()
+    finally:
+        gpu.close()
+
+
+def test_stream_ordering_on_side_stream(dev):
+    ref, gpu = make_pair(1 << 12, 2, 12, "la", seed=5)
+    try:
+        keys = workload.positive_keys(5, 40000)
+        ref.insert(keys)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            kd = to_dev(keys, dev)
+            gpu.insert_deterministic(kd)
+            out = gpu.query(kd)
+        s.synchronize()
+        assert bbfc.unpack_bits(out.cpu().numpy(), len(keys)).all()
+        assert np.array_equal(gpu.download(), ref.words)
+    finally:
+        gpu.close()
+
+
+def test_overlapping_output_rejected(dev):
+    gpu = bbfc.Filter(64, 2, 8, "la", seed=1)
+    try:
+        buf = torch.zeros(1024, dtype=torch.int64, device=dev)
+        with pytest.raises(bbfc.BBFCError, match="overlaps"):
+            gpu.query(buf[:512], out=buf[500:])
+    finally:
+        gpu.close()
+
+
+def test_probes_run(dev):
+    buf = torch.zeros(8 * (1 << 16), dtype=torch.int64, device=dev)
+    sink = torch.zeros(1 << 16, dtype=torch.int64, device=dev)
+    bbfc.probe_gather64(buf, 1 << 18, 1, sink)
+    bbfc.probe_atomic64(buf, 1 << 18, 2)
+    dst = torch.empty_like(buf)
+    bbfc.probe_copy(buf, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(buf, dst)
+    assert int(buf.ne(0).sum()) > 0

@@ -107,3 +107,52 @@ def draw_multipliers(seed: int, count: int, coprime_to: int = 2) -> list[int]:
         if a >= (1 << 32) and math.gcd(a, coprime_to) == 1:
             out.append(a)
     return out
+
+
+# ----------------------------------------------------- device-side generator
+
+import ctypes as _ctypes
+import os as _os
+import subprocess as _subprocess
+
+_HERE = _os.path.dirname(_os.path.abspath(__file__))
+_DEV_SRC = _os.path.join(_HERE, "csrc", "keygen.hip")
+_DEV_LIB = _os.path.join(_HERE, "libworkload.so")
+_dev = None
+
+
+def build_device(arch: str = "gfx950") -> str:
+    """Compile the device key generator with hipcc (in-tree)."""
+    cmd = ["hipcc", f"--offload-arch={arch}", "-O3", "-fPIC", "-shared",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-o", _DEV_LIB + ".tmp", _DEV_SRC]
+    _subprocess.run(cmd, check=True, stderr=_subprocess.DEVNULL)
+    _os.replace(_DEV_LIB + ".tmp", _DEV_LIB)
+    return _DEV_LIB
+
+
+def _device_lib():
+    global _dev
+    if _dev is None:
+        if not _os.path.exists(_DEV_LIB):
+            raise RuntimeError(f"{_DEV_LIB} is missing; run workload.build_device()")
+        L = _ctypes.CDLL(_DEV_LIB)
+        L.wl_splitmix64_keys.argtypes = [_ctypes.c_uint64] * 3 + [_ctypes.c_void_p] * 2
+        L.wl_splitmix64_keys.restype = _ctypes.c_int
+        _dev = L
+    return _dev
+
+
+def device_keys(seed: int, start: int, n: int, device="cuda", out=None, stream=None):
+    """key(seed, start .. start+n-1) generated on the GPU into an int64 tensor
+    (the same 64-bit patterns as ``splitmix64_keys``)."""
+    import torch
+
+    if out is None:
+        out = torch.empty(n, dtype=torch.int64, device=device)
+    if stream is None:
+        stream = torch.cuda.current_stream(out.device)
+    rc = _device_lib().wl_splitmix64_keys(seed & MASK64, start, n, out.data_ptr(), _ctypes.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"device key generation failed ({rc})")
+    return out
