@@ -48,7 +48,59 @@ def parse_args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="target seconds per oracle leg")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="only run the random-64-byte read and atomic-OR probes and exit")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain 1 GiB copy kernel (calibrates the traffic counters) and exit")
     return ap.parse_args()
+
+
+def run_probes(stream=None):
+    """Random 64-byte line reads and random 64-bit atomic ORs (eight lanes per
+    line) over a 4 GiB buffer, beyond the Infinity Cache."""
+    import torch
+
+    import paper_2501_18977_amd as bbfc
+
+    dev = torch.device("cuda:0")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = {}
+    lines = 1 << 26
+    buf = torch.zeros(lines * 8, dtype=torch.int64, device=dev)
+    sink = torch.zeros(1 << 16, dtype=torch.int64, device=dev)
+    for name, fn, acc in (
+        ("rand64_read", lambda a: bbfc.probe_gather(buf, a, 7, sink, 64, stream), 1 << 28),
+        ("rand64_atomic_or", lambda a: bbfc.probe_atomic64(buf, a, 9, stream), 1 << 27),
+    ):
+        fn(acc >> 4)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(acc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[name + "_GBs"] = round(acc * 64 / (ms / 1e3) / 1e9, 1)
+        out[name + "_Glines_s"] = round(acc / (ms / 1e3) / 1e9, 2)
+    del buf
+    return out
+
+
+def copy_calibration():
+    """Three launches of a streaming copy of 2^27 words (1 GiB read, 1 GiB
+    written), so FETCH_SIZE and WRITE_SIZE can be scaled to bytes."""
+    import torch
+
+    import paper_2501_18977_amd as bbfc
+
+    dev = torch.device("cuda:0")
+    src = torch.ones(1 << 27, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        bbfc.probe_copy(src, dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
+                      "launches": 3, "ok": bool(torch.equal(src, dst))}), flush=True)
 
 
 def kernel_source_sha() -> str:
@@ -122,6 +174,12 @@ def main():
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.probe_only:
+        print(json.dumps(run_probes()), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -199,24 +257,7 @@ def main():
 
     probe = None
     if not args.no_probe:
-        probe = {}
-        lines = 1 << 26  # 4 GiB buffer, beyond the Infinity Cache
-        buf = torch.zeros(lines * 8, dtype=torch.int64, device=dev)
-        sink = torch.zeros(1 << 16, dtype=torch.int64, device=dev)
-        for name, fn, acc in (
-            ("rand64_read", lambda a: bbfc.probe_gather64(buf, a, 7, sink, stream), 1 << 28),
-            ("rand64_atomic_or", lambda a: bbfc.probe_atomic64(buf, a, 9, stream), 1 << 27),
-        ):
-            fn(acc >> 4)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            fn(acc)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            probe[name + "_GBs"] = round(acc * 64 / (ms / 1e3) / 1e9, 1)
-            probe[name + "_Glines_s"] = round(acc / (ms / 1e3) / 1e9, 2)
-        del buf
+        probe = run_probes(stream)
         # fraction of the measured random-64-byte ceiling
         ceil = probe["rand64_read_GBs"] if dom == "query" else probe["rand64_atomic_or_GBs"]
         probe["dominant_frac_of_probe"] = round(achieved / ceil, 4) if ceil else None

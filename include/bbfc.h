@@ -119,7 +119,7 @@ bbfc_status bbfc_destroy(bbfc_handle h);
  * call decide on block contents that may miss the bits of keys still in
  * flight, so the filter may differ from a one-key-at-a-time build; the
  * library bounds the keys in flight to a fraction of n_blocks (see
- * bbfc_set_insert_inflight) so that the false-positive rate stays that of
+ * BBFC_OPT_INSERT_INFLIGHT) so that the false-positive rate stays that of
  * the sequential build. With choices == 1 the result equals the sequential
  * build bit for bit. n == 0 is a no-op. Errors: EINVAL (null handle, null
  * keys with n > 0), EHIP. */
@@ -159,11 +159,23 @@ bbfc_status bbfc_get_params(bbfc_handle h, uint64_t *n_blocks, uint32_t *choices
  * library, valid until bbfc_destroy). */
 bbfc_status bbfc_get_words(bbfc_handle h, uint64_t **d_words);
 
-/* Upper bound on keys a racing insert keeps in flight. 0 restores the
- * default, n_blocks/32 keys (at least one wavefront of 64); a larger bound
- * is faster on small filters, at the price of decisions on staler block
- * contents. */
-bbfc_status bbfc_set_insert_inflight(bbfc_handle h, uint64_t max_keys);
+/* Launch options of one filter (all have defaults; none changes a result
+ * except where stated):
+ *   BBFC_OPT_INSERT_INFLIGHT  upper bound on keys a racing insert keeps in
+ *       flight; 0 (default) means n_blocks/32, at least one wavefront of 64.
+ *       A larger bound is faster on small filters, at the price of
+ *       decisions on staler block contents (the filter can differ, its
+ *       false-positive rate drifts upwards; zero false negatives holds).
+ *   BBFC_OPT_QUERY_EARLY_EXIT  1 (default): a query reads candidate i+1
+ *       only for keys that candidates 1..i did not answer; 0: every
+ *       candidate is read. Answers are identical either way.
+ * Errors: EINVAL (null handle or pointer, unknown option, negative value). */
+typedef enum {
+    BBFC_OPT_INSERT_INFLIGHT = 1,
+    BBFC_OPT_QUERY_EARLY_EXIT = 2
+} bbfc_option;
+bbfc_status bbfc_set_option(bbfc_handle h, int32_t option, int64_t value);
+bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value);
 
 /* Number of blocks for n_keys keys at `space_bits_per_key` bits per key:
  * ceil(n_keys * space_bits_per_key / 512), at least 1 (App. C sizes a
@@ -185,12 +197,13 @@ const char *bbfc_last_error(void);
 /* not touch any filter.                                                  */
 /* ------------------------------------------------------------------ */
 
-/* Random 64-byte gathers: n_access reads of whole 64-byte lines at
- * pseudo-random 64-byte-aligned positions of d_buf (n_lines lines, a power
- * of two), eight lanes per line, as the filter kernels read blocks. Writes
- * one checksum word per workgroup into d_sink (>= 65536 words). */
-bbfc_status bbfc_probe_gather64(const uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
-                                uint64_t *d_sink, hipStream_t stream);
+/* Random line gathers: n_access reads of whole lines of access_bytes (64
+ * or 128) bytes at pseudo-random access_bytes-aligned positions of d_buf,
+ * which holds n_lines64 64-byte lines (a power of two, >= 2), access_bytes/8
+ * lanes per line, as the filter kernels read blocks (64). Writes at most
+ * one word per workgroup into d_sink (>= 65536 words). */
+bbfc_status bbfc_probe_gather(const uint64_t *d_buf, uint64_t n_lines64, uint32_t access_bytes, uint64_t n_access,
+                              uint64_t seed, uint64_t *d_sink, hipStream_t stream);
 
 /* Random 64-bit atomic ORs: n_access lines, eight lanes each ORing one
  * word of the line, as the insert kernel writes (n_lines a power of two). */

@@ -28,13 +28,14 @@ __all__ = [
     "host_bit_hash",
     "lib",
     "library_path",
-    "probe_gather64",
+    "probe_gather",
     "probe_atomic64",
     "probe_copy",
     "unpack_bits",
 ]
 
 COST_NONE, COST_MIX, COST_LA, COST_EXP = 0, 1, 2, 3
+OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT = 1, 2
 _COST_BY_NAME = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -86,12 +87,13 @@ def lib() -> ctypes.CDLL:
         "bbfc_download": (_st, [_vp, _vp, _vp]),
         "bbfc_get_params": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
         "bbfc_get_words": (_st, [_vp, _vp]),
-        "bbfc_set_insert_inflight": (_st, [_vp, _u64]),
+        "bbfc_set_option": (_st, [_vp, ctypes.c_int32, ctypes.c_int64]),
+        "bbfc_get_option": (_st, [_vp, ctypes.c_int32, _vp]),
         "bbfc_blocks_for": (_u64, [_u64, ctypes.c_double]),
         "bbfc_rank_table": (_st, [_Cost, _u32, _vp]),
         "bbfc_status_string": (ctypes.c_char_p, [_st]),
         "bbfc_last_error": (ctypes.c_char_p, []),
-        "bbfc_probe_gather64": (_st, [_vp, _u64, _u64, _u64, _vp, _vp]),
+        "bbfc_probe_gather": (_st, [_vp, _u64, _u32, _u64, _u64, _vp, _vp]),
         "bbfc_probe_atomic64": (_st, [_vp, _u64, _u64, _u64, _vp]),
         "bbfc_probe_copy": (_st, [_vp, _vp, _u64, _vp]),
         "bbfc_host_block_hash": (_u64, [_u64, _u64, _u64]),
@@ -217,8 +219,13 @@ class Filter:
         _check(lib().bbfc_get_words(self.handle, ctypes.byref(p)))
         return int(p.value)
 
-    def set_insert_inflight(self, max_keys: int) -> None:
-        _check(lib().bbfc_set_insert_inflight(self.handle, max_keys))
+    def set_option(self, option: int, value: int) -> None:
+        _check(lib().bbfc_set_option(self.handle, option, int(value)))
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int64()
+        _check(lib().bbfc_get_option(self.handle, option, ctypes.byref(v)))
+        return int(v.value)
 
     # -------------------------------------------------------------- ops
     def insert(self, keys, stream=None) -> None:
@@ -285,14 +292,14 @@ class Filter:
 
 # ------------------------------------------------------- measurement hooks
 
-def probe_gather64(buf, n_access: int, seed: int, sink, stream=None) -> None:
+def probe_gather(buf, n_access: int, seed: int, sink, access_bytes: int = 64, stream=None) -> None:
     if sink.numel() < 65536:
         raise ValueError("probe sink needs at least 65536 words")
     n_lines = buf.numel() // 8
-    if n_lines & (n_lines - 1):
-        raise ValueError("probe buffer must hold a power-of-two number of 64-byte lines")
-    _check(lib().bbfc_probe_gather64(buf.data_ptr(), n_lines, n_access, seed, sink.data_ptr(),
-                                     _stream_handle(stream)))
+    if n_lines & (n_lines - 1) or n_lines < 2:
+        raise ValueError("probe buffer must hold a power-of-two number (>= 2) of 64-byte lines")
+    _check(lib().bbfc_probe_gather(buf.data_ptr(), n_lines, access_bytes, n_access, seed, sink.data_ptr(),
+                                   _stream_handle(stream)))
 
 
 def probe_atomic64(buf, n_access: int, seed: int, stream=None) -> None:

@@ -394,12 +394,40 @@ bbfc_status bbfc_get_words(bbfc_handle h, uint64_t **d_words)
     return BBFC_OK;
 }
 
-bbfc_status bbfc_set_insert_inflight(bbfc_handle h, uint64_t max_keys)
+bbfc_status bbfc_set_option(bbfc_handle h, int32_t option, int64_t value)
 {
     if (h == nullptr)
         return fail(BBFC_EINVAL, "null handle");
-    h->max_inflight = max_keys;
-    return BBFC_OK;
+    if (value < 0)
+        return fail(BBFC_EINVAL, "option values are non-negative");
+    switch (option) {
+    case BBFC_OPT_INSERT_INFLIGHT:
+        h->max_inflight = (uint64_t)value;
+        return BBFC_OK;
+    case BBFC_OPT_QUERY_EARLY_EXIT:
+        if (value > 1)
+            return fail(BBFC_EINVAL, "BBFC_OPT_QUERY_EARLY_EXIT takes 0 or 1");
+        h->query_early_exit = (int)value;
+        return BBFC_OK;
+    default:
+        return fail(BBFC_EINVAL, "unknown option %d", (int)option);
+    }
+}
+
+bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value)
+{
+    if (h == nullptr || value == nullptr)
+        return fail(BBFC_EINVAL, "null handle or output");
+    switch (option) {
+    case BBFC_OPT_INSERT_INFLIGHT:
+        *value = (int64_t)h->max_inflight;
+        return BBFC_OK;
+    case BBFC_OPT_QUERY_EARLY_EXIT:
+        *value = h->query_early_exit;
+        return BBFC_OK;
+    default:
+        return fail(BBFC_EINVAL, "unknown option %d", (int)option);
+    }
 }
 
 uint64_t bbfc_blocks_for(uint64_t n_keys, double space_bits_per_key)
@@ -446,12 +474,14 @@ const char *bbfc_last_error(void)
     return g_last_error.c_str();
 }
 
-bbfc_status bbfc_probe_gather64(const uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
-                                uint64_t *d_sink, hipStream_t stream)
+bbfc_status bbfc_probe_gather(const uint64_t *d_buf, uint64_t n_lines64, uint32_t access_bytes, uint64_t n_access,
+                              uint64_t seed, uint64_t *d_sink, hipStream_t stream)
 {
-    if (d_buf == nullptr || d_sink == nullptr || !is_pow2(n_lines))
-        return fail(BBFC_EINVAL, "probe needs buffers and a power-of-two line count");
-    hipError_t e = bbfc::launch_probe_gather64(d_buf, n_lines, n_access, seed, d_sink, stream);
+    if (d_buf == nullptr || d_sink == nullptr || !is_pow2(n_lines64) || n_lines64 < 2)
+        return fail(BBFC_EINVAL, "probe needs buffers and a power-of-two line count >= 2");
+    if (access_bytes != 64 && access_bytes != 128)
+        return fail(BBFC_EINVAL, "access_bytes must be 64 or 128");
+    hipError_t e = bbfc::launch_probe_gather(d_buf, n_lines64, access_bytes, n_access, seed, d_sink, stream);
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching gather probe");
 }
 

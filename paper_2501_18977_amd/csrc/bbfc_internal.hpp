@@ -24,6 +24,7 @@ struct bbfc_filter {
     int device = 0;
     int num_cus = 0;
     uint64_t max_inflight = 0;    // 0: n_blocks/32
+    int query_early_exit = 1;     // load choice i+1 only for keys still unanswered
 };
 
 namespace bbfc {
@@ -39,8 +40,8 @@ hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, 
                         hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s);
 
-hipError_t launch_probe_gather64(const uint64_t *buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
-                                 uint64_t *sink, hipStream_t s);
+hipError_t launch_probe_gather(const uint64_t *buf, uint64_t n_lines64, uint32_t access_bytes, uint64_t n_access,
+                               uint64_t seed, uint64_t *sink, hipStream_t s);
 hipError_t launch_probe_atomic64(uint64_t *buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
                                  hipStream_t s);
 hipError_t launch_probe_copy(const uint64_t *src, uint64_t *dst, uint64_t n_words, hipStream_t s);

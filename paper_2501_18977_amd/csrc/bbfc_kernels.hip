@@ -106,7 +106,9 @@ __device__ inline uint64_t mask_word(const uint32_t *smask, uint32_t t, uint32_t
 
 // ------------------------------------------------------------------ query
 
-template <int C, int MODE>
+// EARLY: choice i+1 is loaded only by groups whose key none of the choices
+// 1..i answered (the answer is the same; fewer random lines are read).
+template <int C, int MODE, bool EARLY>
 __global__ __launch_bounds__(kWGSize) void query_kernel(KParams p, const uint64_t *__restrict__ keys, uint64_t n,
                                                         uint64_t *__restrict__ out, uint64_t n_tiles)
 {
@@ -126,36 +128,61 @@ __global__ __launch_bounds__(kWGSize) void query_kernel(KParams p, const uint64_
         wave_sync();
 
         uint64_t m[8];
-        uint64_t B[8][C];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const uint32_t t = g * 8 + r;
-            m[r] = mask_word(smask, t, w);
-            // Keys past n were hashed as key 0, whose blocks are in range,
-            // so the loads need no guard; their answers are masked below.
+        for (int r = 0; r < 8; ++r)
+            m[r] = mask_word(smask, g * 8 + r, w);
+        // Bit 8g + r of `found`: tile key 8g + r is in some block tested so far.
+        // Keys past n were hashed as key 0, whose blocks are in range, so the
+        // loads need no guard; their answers are masked at the end.
+        uint64_t found = 0;
+        if constexpr (!EARLY || C == 1) {
+            uint64_t B[8][C];
 #pragma unroll
-            for (int i = 0; i < C; ++i)
-                B[r][i] = p.words[sblk[t * C + i] * 8 + w];
-        }
-        uint64_t out_word = 0;
+            for (int r = 0; r < 8; ++r)
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            uint64_t hit = 0;
+                for (int i = 0; i < C; ++i)
+                    B[r][i] = p.words[sblk[(g * 8 + r) * C + i] * 8 + w];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                uint64_t hit = 0;
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    uint64_t b = __ballot((B[r][i] & m[r]) == m[r]);
+                    b &= b >> 1; // bit 8g: AND of the group's eight lanes after three steps
+                    b &= b >> 2;
+                    b &= b >> 4;
+                    hit |= b;
+                }
+                found |= (hit & kGroupLsb) << r;
+            }
+        } else {
+            uint64_t B[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                B[r] = p.words[sblk[(g * 8 + r) * C] * 8 + w];
 #pragma unroll
             for (int i = 0; i < C; ++i) {
-                uint64_t b = __ballot((B[r][i] & m[r]) == m[r]);
-                b &= b >> 1; // bit 8g: AND of the group's eight lanes after three steps
-                b &= b >> 2;
-                b &= b >> 4;
-                hit |= b;
+                if (i > 0) {
+#pragma unroll
+                    for (int r = 0; r < 8; ++r)
+                        if (!((found >> (g * 8 + r)) & 1))
+                            B[r] = p.words[sblk[(g * 8 + r) * C + i] * 8 + w];
+                }
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    uint64_t b = __ballot((B[r] & m[r]) == m[r]);
+                    b &= b >> 1;
+                    b &= b >> 2;
+                    b &= b >> 4;
+                    found |= (b & kGroupLsb) << r;
+                }
             }
-            out_word |= (hit & kGroupLsb) << r;
         }
         const uint64_t rem = n - base;
         if (rem < 64)
-            out_word &= (1ull << rem) - 1;
+            found &= (1ull << rem) - 1;
         if (lane == 0)
-            out[tile] = out_word;
+            out[tile] = found;
         wave_sync();
     }
 }
@@ -435,18 +462,26 @@ hipError_t insert_det_impl(const bbfc_filter &f, const uint64_t *keys, uint64_t 
     return hipGetLastError();
 }
 
-template <int C, int MODE>
-hipError_t query_impl(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
+template <int C, int MODE, bool EARLY>
+hipError_t query_launch(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
 {
     const uint64_t n_tiles = (n + kTile - 1) / kTile;
-    uint64_t wgs = resident_wgs(query_kernel<C, MODE>, 0, f.num_cus);
+    uint64_t wgs = resident_wgs(query_kernel<C, MODE, EARLY>, 0, f.num_cus);
     const uint64_t need = (n_tiles + kWavesPerWG - 1) / kWavesPerWG;
     wgs = wgs < need ? wgs : need;
     if (wgs < 1)
         wgs = 1;
-    hipLaunchKernelGGL((query_kernel<C, MODE>), dim3((uint32_t)wgs), dim3(kWGSize), 0, s, make_kparams(f), keys, n,
-                       out, n_tiles);
+    hipLaunchKernelGGL((query_kernel<C, MODE, EARLY>), dim3((uint32_t)wgs), dim3(kWGSize), 0, s, make_kparams(f),
+                       keys, n, out, n_tiles);
     return hipGetLastError();
+}
+
+template <int C, int MODE>
+hipError_t query_impl(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
+{
+    if (C > 1 && f.query_early_exit)
+        return query_launch<C, MODE, true>(f, keys, n, out, s);
+    return query_launch<C, MODE, false>(f, keys, n, out, s);
 }
 
 // Dispatch on (choices, hash mode) to a template instance.

@@ -24,26 +24,28 @@ __device__ inline uint64_t probe_line(uint64_t seed, uint64_t i)
     return z ^ (z >> 31);
 }
 
-// Each wavefront handles 64 accesses per iteration: lane (g, w) reads word w
-// of line 8g + r in round r, with all eight rounds in flight at once.
-__global__ __launch_bounds__(kProbeWG) void probe_gather64_kernel(const uint64_t *__restrict__ buf, uint64_t line_mask,
-                                                                  uint64_t n_access, uint64_t seed,
-                                                                  uint64_t *__restrict__ sink)
+// Each wavefront handles 64 / LPL * 8 accesses per iteration: LPL lanes read
+// one line of 8 * LPL bytes (lane w reads word w), eight rounds in flight.
+template <int LPL>
+__global__ __launch_bounds__(kProbeWG) void probe_gather_kernel(const uint64_t *__restrict__ buf, uint64_t line_mask,
+                                                                uint64_t n_access, uint64_t seed,
+                                                                uint64_t *__restrict__ sink)
 {
+    constexpr int kGroups = 64 / LPL;
     const uint32_t lane = threadIdx.x & 63;
-    const uint32_t g = lane >> 3;
-    const uint32_t w = lane & 7;
+    const uint32_t g = lane / LPL;
+    const uint32_t w = lane % LPL;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
     uint64_t acc = 0;
-    for (uint64_t base = wave * 64; base < n_access; base += n_waves * 64) {
+    for (uint64_t base = wave * kGroups * 8; base < n_access; base += n_waves * kGroups * 8) {
         uint64_t v[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const uint64_t a = base + g * 8 + r;
             v[r] = 0;
             if (a < n_access)
-                v[r] = buf[(probe_line(seed, a) & line_mask) * 8 + w];
+                v[r] = buf[(probe_line(seed, a) & line_mask) * LPL + w];
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r)
@@ -98,14 +100,21 @@ uint32_t probe_grid(const void *kernel)
 
 } // namespace
 
-hipError_t launch_probe_gather64(const uint64_t *buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
-                                 uint64_t *sink, hipStream_t s)
+hipError_t launch_probe_gather(const uint64_t *buf, uint64_t n_lines64, uint32_t access_bytes, uint64_t n_access,
+                               uint64_t seed, uint64_t *sink, hipStream_t s)
 {
-    uint32_t grid = probe_grid((const void *)probe_gather64_kernel);
+    const void *k = access_bytes == 128 ? (const void *)probe_gather_kernel<16> : (const void *)probe_gather_kernel<8>;
+    uint32_t grid = probe_grid(k);
     const uint64_t need = (n_access + 255) / 256;
     if (need < grid)
         grid = (uint32_t)(need ? need : 1);
-    hipLaunchKernelGGL(probe_gather64_kernel, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_access, seed, sink);
+    const uint64_t lines = access_bytes == 128 ? n_lines64 / 2 : n_lines64;
+    if (access_bytes == 128)
+        hipLaunchKernelGGL(probe_gather_kernel<16>, dim3(grid), dim3(kProbeWG), 0, s, buf, lines - 1, n_access, seed,
+                           sink);
+    else
+        hipLaunchKernelGGL(probe_gather_kernel<8>, dim3(grid), dim3(kProbeWG), 0, s, buf, lines - 1, n_access, seed,
+                           sink);
     return hipGetLastError();
 }
 

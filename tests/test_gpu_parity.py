@@ -74,10 +74,13 @@ def test_device_keys_match_numpy_generator(dev):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("early", [1, 0])
 @pytest.mark.parametrize("M,c,k,cost,n", SMALL_CONFIGS)
-def test_query_bits_match_oracle_on_oracle_built_filter(dev, M, c, k, cost, n):
+def test_query_bits_match_oracle_on_oracle_built_filter(dev, M, c, k, cost, n, early):
     ref, gpu = make_pair(M, c, k, cost, seed=M + 31 * c + k)
     try:
+        gpu.set_option(bbfc.OPT_QUERY_EARLY_EXIT, early)
+        assert gpu.get_option(bbfc.OPT_QUERY_EARLY_EXIT) == early
         keys = workload.positive_keys(M + k, n)
         ref.insert(keys)
         gpu.upload(ref.words)
@@ -243,6 +246,19 @@ def test_stream_ordering_on_side_stream(dev):
         gpu.close()
 
 
+def test_option_validation(dev):
+    gpu = bbfc.Filter(64, 2, 8, "la", seed=1)
+    try:
+        assert gpu.get_option(bbfc.OPT_INSERT_INFLIGHT) == 0
+        gpu.set_option(bbfc.OPT_INSERT_INFLIGHT, 4096)
+        assert gpu.get_option(bbfc.OPT_INSERT_INFLIGHT) == 4096
+        for opt, val in ((bbfc.OPT_QUERY_EARLY_EXIT, 2), (bbfc.OPT_INSERT_INFLIGHT, -1), (99, 0)):
+            with pytest.raises(bbfc.BBFCError):
+                gpu.set_option(opt, val)
+    finally:
+        gpu.close()
+
+
 def test_overlapping_output_rejected(dev):
     gpu = bbfc.Filter(64, 2, 8, "la", seed=1)
     try:
@@ -256,7 +272,8 @@ def test_overlapping_output_rejected(dev):
 def test_probes_run(dev):
     buf = torch.zeros(8 * (1 << 16), dtype=torch.int64, device=dev)
     sink = torch.zeros(1 << 16, dtype=torch.int64, device=dev)
-    bbfc.probe_gather64(buf, 1 << 18, 1, sink)
+    bbfc.probe_gather(buf, 1 << 18, 1, sink)
+    bbfc.probe_gather(buf, 1 << 18, 1, sink, access_bytes=128)
     bbfc.probe_atomic64(buf, 1 << 18, 2)
     dst = torch.empty_like(buf)
     bbfc.probe_copy(buf, dst)
