@@ -169,10 +169,23 @@ bbfc_status bbfc_get_words(bbfc_handle h, uint64_t **d_words);
  *   BBFC_OPT_QUERY_EARLY_EXIT  1 (default): a query reads candidate i+1
  *       only for keys that candidates 1..i did not answer; 0: every
  *       candidate is read. Answers are identical either way.
- * Errors: EINVAL (null handle or pointer, unknown option, negative value). */
+ *   BBFC_OPT_LANES_PER_KEY  8 (default) or 4 lanes of a wavefront share
+ *       one key's block reads (8 bytes or 16 bytes per lane per block).
+ *   BBFC_OPT_TILES_PER_WAVE  1 (default) or 2 tiles of 64 keys held by a
+ *       wavefront at once (more reads in flight per wavefront; an insert
+ *       falls back to 1 where two tiles and the rank table exceed LDS).
+ *   BBFC_OPT_WGS_PER_CU  cap on resident workgroups per CU, 0 (default)
+ *       for as many as fit.
+ * Answers and the deterministic insert do not depend on the last three; a
+ * racing insert's filter may (it is schedule dependent anyway).
+ * Errors: EINVAL (null handle or pointer, unknown option, value out of
+ * range). */
 typedef enum {
     BBFC_OPT_INSERT_INFLIGHT = 1,
-    BBFC_OPT_QUERY_EARLY_EXIT = 2
+    BBFC_OPT_QUERY_EARLY_EXIT = 2,
+    BBFC_OPT_LANES_PER_KEY = 3,
+    BBFC_OPT_TILES_PER_WAVE = 4,
+    BBFC_OPT_WGS_PER_CU = 5
 } bbfc_option;
 bbfc_status bbfc_set_option(bbfc_handle h, int32_t option, int64_t value);
 bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value);
@@ -191,6 +204,86 @@ bbfc_status bbfc_rank_table(bbfc_cost cost, uint32_t bits_per_key, uint16_t *out
 
 const char *bbfc_status_string(bbfc_status s);
 const char *bbfc_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* Batches: many filters of uneven sizes built or queried in one          */
+/* persistent launch (insert and query as above, filter by filter).       */
+/* ------------------------------------------------------------------ */
+
+typedef struct bbfc_batch *bbfc_batch_handle;
+
+/* A plan over n_filters filters (one device, one number of choices) in
+ * which filter f receives n_keys[f] keys per call (host array, copied).
+ * Layout of every call on the plan: filter f's keys are
+ * d_keys[o_f .. o_f + n_keys[f]) with o_f = n_keys[0] + ... + n_keys[f-1];
+ * its packed answers (bbfc_batch_query) start at word
+ * ceil(n_keys[0]/64) + ... + ceil(n_keys[f-1]/64), in bbfc_query's layout.
+ * Filters with no keys are allowed. The filters must outlive the plan and
+ * every graph captured from it. Errors: EINVAL (null pointers,
+ * n_filters == 0, mixed devices or choices), EHIP. */
+bbfc_status bbfc_batch_create(const bbfc_handle *filters, const uint64_t *n_keys, uint32_t n_filters,
+                              bbfc_batch_handle *out);
+bbfc_status bbfc_batch_destroy(bbfc_batch_handle b);
+
+/* Total keys and answer words of the plan's layout (either may be null). */
+bbfc_status bbfc_batch_layout(bbfc_batch_handle b, uint64_t *total_keys, uint64_t *total_out_words);
+
+/* Racing insert of every filter's keys in one persistent launch. Each
+ * filter keeps at most its own cap of keys in flight
+ * (BBFC_OPT_INSERT_INFLIGHT of that filter), as bbfc_insert does. */
+bbfc_status bbfc_batch_insert(bbfc_batch_handle b, const uint64_t *d_keys, hipStream_t stream);
+
+/* Query of every filter's keys in one persistent launch; the answers of
+ * filter f equal bbfc_query's on the same keys. The output must not overlap
+ * the keys. */
+bbfc_status bbfc_batch_query(bbfc_batch_handle b, const uint64_t *d_keys, uint64_t *d_out_bits, hipStream_t stream);
+
+/* Launch shape of a plan's persistent kernel for one operation: lanes per
+ * key (8 or 4), 64-key tiles per wavefront (1 or 2) and a cap on resident
+ * workgroups per CU (0 = as many as fit). ms is filled by the tuner. */
+typedef struct {
+    int32_t lanes_per_key;
+    int32_t tiles_per_wave;
+    int32_t wgs_per_cu;
+    float ms;
+} bbfc_launch_shape;
+
+#define BBFC_OP_INSERT 0
+#define BBFC_OP_QUERY 1
+
+bbfc_status bbfc_batch_set_shape(bbfc_batch_handle b, int32_t op, bbfc_launch_shape shape);
+bbfc_status bbfc_batch_get_shape(bbfc_batch_handle b, int32_t op, bbfc_launch_shape *shape);
+
+/* Autotuner: times every candidate shape (lanes per key 8|4, tiles per
+ * wavefront 1|2, workgroups per CU unbounded|2) of the plan's persistent
+ * kernel for `op` on the caller's keys, `reps` timed runs each after one
+ * warm-up, keeps the fastest in the plan and returns it in *best (may be
+ * null). Insert trials run on a snapshot: the filters' words are copied
+ * aside (device memory equal to their size is allocated for the duration)
+ * and restored before every trial and at the end, so the filters are
+ * unchanged on return. Synchronises `stream`. */
+bbfc_status bbfc_batch_tune(bbfc_batch_handle b, int32_t op, const uint64_t *d_keys, uint64_t *d_out_bits,
+                            uint32_t reps, hipStream_t stream, bbfc_launch_shape *best);
+
+/* ------------------------------------------------------------------ */
+/* Graphs: batch launches captured once and replayed.                    */
+/* ------------------------------------------------------------------ */
+
+typedef struct bbfc_graph *bbfc_graph_handle;
+
+/* Captures into one executable hipGraph the launches of
+ * bbfc_batch_insert(insert_plan, d_insert_keys) followed by
+ * bbfc_batch_query(query_plan, d_query_keys, d_out_bits); either plan may
+ * be null (not both). The graph keeps its own copy of the plans' tables as
+ * of capture time (later shape changes do not affect it) and records the
+ * buffer addresses, which must stay valid while the graph is used. The
+ * captured kernels contain no memset nodes. */
+bbfc_status bbfc_graph_create(bbfc_batch_handle insert_plan, const uint64_t *d_insert_keys,
+                              bbfc_batch_handle query_plan, const uint64_t *d_query_keys, uint64_t *d_out_bits,
+                              bbfc_graph_handle *out);
+bbfc_status bbfc_graph_launch(bbfc_graph_handle g, hipStream_t stream);
+/* Synchronises the device, then frees the graph and its tables. */
+bbfc_status bbfc_graph_destroy(bbfc_graph_handle g);
 
 /* ------------------------------------------------------------------ */
 /* Measurement hooks: the kernels that calibrate the roofline. They do   */

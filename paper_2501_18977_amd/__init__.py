@@ -22,6 +22,8 @@ __all__ = [
     "COST_LA",
     "COST_EXP",
     "Filter",
+    "Batch",
+    "Graph",
     "blocks_for",
     "rank_table",
     "host_block_hash",
@@ -35,7 +37,8 @@ __all__ = [
 ]
 
 COST_NONE, COST_MIX, COST_LA, COST_EXP = 0, 1, 2, 3
-OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT = 1, 2
+OP_INSERT, OP_QUERY = 0, 1
+OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT, OPT_LANES_PER_KEY, OPT_TILES_PER_WAVE, OPT_WGS_PER_CU = 1, 2, 3, 4, 5
 _COST_BY_NAME = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -50,6 +53,11 @@ class BBFCError(RuntimeError):
 
 class _Cost(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("param", ctypes.c_double)]
+
+
+class _Shape(ctypes.Structure):
+    _fields_ = [("lanes_per_key", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
+                ("wgs_per_cu", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 _lib = None
@@ -96,6 +104,17 @@ def lib() -> ctypes.CDLL:
         "bbfc_probe_gather": (_st, [_vp, _u64, _u32, _u64, _u64, _vp, _vp]),
         "bbfc_probe_atomic64": (_st, [_vp, _u64, _u64, _u64, _vp]),
         "bbfc_probe_copy": (_st, [_vp, _vp, _u64, _vp]),
+        "bbfc_batch_create": (_st, [_vp, _vp, _u32, _vp]),
+        "bbfc_batch_destroy": (_st, [_vp]),
+        "bbfc_batch_layout": (_st, [_vp, _vp, _vp]),
+        "bbfc_batch_insert": (_st, [_vp, _vp, _vp]),
+        "bbfc_batch_query": (_st, [_vp, _vp, _vp, _vp]),
+        "bbfc_batch_set_shape": (_st, [_vp, ctypes.c_int32, _Shape]),
+        "bbfc_batch_get_shape": (_st, [_vp, ctypes.c_int32, _vp]),
+        "bbfc_batch_tune": (_st, [_vp, ctypes.c_int32, _vp, _vp, _u32, _vp, _vp]),
+        "bbfc_graph_create": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
+        "bbfc_graph_launch": (_st, [_vp, _vp]),
+        "bbfc_graph_destroy": (_st, [_vp]),
         "bbfc_host_block_hash": (_u64, [_u64, _u64, _u64]),
         "bbfc_host_bit_hash": (_u32, [_u64, _u64]),
     }
@@ -282,6 +301,121 @@ class Filter:
 
     def __exit__(self, *exc):
         self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _shape_dict(sh: _Shape) -> dict:
+    return {"lanes_per_key": sh.lanes_per_key, "tiles_per_wave": sh.tiles_per_wave,
+            "wgs_per_cu": sh.wgs_per_cu, "ms": sh.ms}
+
+
+class Batch:
+    """A plan over several filters, each receiving a fixed number of keys per
+    call; keys and answers are concatenated filter after filter (answers of
+    each filter start at a 64-bit word)."""
+
+    def __init__(self, filters, n_keys):
+        if len(filters) != len(n_keys) or not filters:
+            raise ValueError("one key count per filter, at least one filter")
+        self._filters = list(filters)  # keep the filters alive
+        self.n_keys = [int(v) for v in n_keys]
+        hs = (ctypes.c_void_p * len(filters))(*[f.handle.value for f in filters])
+        ns = (ctypes.c_uint64 * len(filters))(*self.n_keys)
+        h = ctypes.c_void_p()
+        _check(lib().bbfc_batch_create(hs, ns, len(filters), ctypes.byref(h)))
+        self._h = h
+        tk, tw = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().bbfc_batch_layout(h, ctypes.byref(tk), ctypes.byref(tw)))
+        self.total_keys, self.total_out_words = tk.value, tw.value
+        self.key_offsets, self.out_offsets = [], []
+        ko = wo = 0
+        for n in self.n_keys:
+            self.key_offsets.append(ko)
+            self.out_offsets.append(wo)
+            ko += n
+            wo += (n + 63) // 64
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("batch is closed")
+        return self._h
+
+    def insert(self, keys, stream=None) -> None:
+        keys = _device_u64(keys, "keys")
+        if keys.numel() < self.total_keys:
+            raise ValueError("fewer keys than the plan's layout")
+        _check(lib().bbfc_batch_insert(self.handle, keys.data_ptr(), _stream_handle(stream)))
+
+    def query(self, keys, out=None, stream=None):
+        import torch
+
+        keys = _device_u64(keys, "keys")
+        if keys.numel() < self.total_keys:
+            raise ValueError("fewer keys than the plan's layout")
+        if out is None:
+            out = torch.empty(max(self.total_out_words, 1), dtype=torch.int64, device=keys.device)
+        elif out.numel() < self.total_out_words:
+            raise ValueError("output too small")
+        _check(lib().bbfc_batch_query(self.handle, keys.data_ptr(), out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def set_shape(self, op: int, lanes_per_key: int = 8, tiles_per_wave: int = 1, wgs_per_cu: int = 0) -> None:
+        _check(lib().bbfc_batch_set_shape(self.handle, op, _Shape(lanes_per_key, tiles_per_wave, wgs_per_cu, 0.0)))
+
+    def get_shape(self, op: int) -> dict:
+        sh = _Shape()
+        _check(lib().bbfc_batch_get_shape(self.handle, op, ctypes.byref(sh)))
+        return _shape_dict(sh)
+
+    def tune(self, op: int, keys, out=None, reps: int = 3, stream=None) -> dict:
+        keys = _device_u64(keys, "keys")
+        optr = out.data_ptr() if out is not None else None
+        sh = _Shape()
+        _check(lib().bbfc_batch_tune(self.handle, op, keys.data_ptr(), optr, reps, _stream_handle(stream),
+                                     ctypes.byref(sh)))
+        return _shape_dict(sh)
+
+    def close(self) -> None:
+        if self._h is not None:
+            _check(lib().bbfc_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured batch insert and/or batch query, replayed with launch()."""
+
+    def __init__(self, insert_batch=None, insert_keys=None, query_batch=None, query_keys=None, out=None):
+        self._keep = (insert_batch, insert_keys, query_batch, query_keys, out)
+        h = ctypes.c_void_p()
+        _check(lib().bbfc_graph_create(
+            insert_batch.handle if insert_batch is not None else None,
+            insert_keys.data_ptr() if insert_keys is not None else None,
+            query_batch.handle if query_batch is not None else None,
+            query_keys.data_ptr() if query_keys is not None else None,
+            out.data_ptr() if out is not None else None, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        if self._h is None:
+            raise ValueError("graph is closed")
+        _check(lib().bbfc_graph_launch(self._h, _stream_handle(stream)))
+
+    def close(self) -> None:
+        if self._h is not None:
+            _check(lib().bbfc_graph_destroy(self._h))
+            self._h = None
 
     def __del__(self):
         try:

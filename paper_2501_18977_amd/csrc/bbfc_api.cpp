@@ -16,11 +16,11 @@
 #include "bbfc_common.hpp"
 #include "bbfc_internal.hpp"
 
+namespace bbfc {
+
 namespace {
-
 thread_local std::string g_last_error;
-
-bbfc_status fail(bbfc_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+}
 
 bbfc_status fail(bbfc_status s, const char *fmt, ...)
 {
@@ -38,24 +38,30 @@ bbfc_status hip_fail(hipError_t e, const char *what)
     return fail(BBFC_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Makes the filter's device current for the scope of a call.
-class DeviceGuard {
-  public:
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev_) == hipSuccess && prev_ != dev && hipSetDevice(dev) == hipSuccess)
-            switched_ = true;
-    }
-    ~DeviceGuard()
-    {
-        if (switched_)
-            (void)hipSetDevice(prev_);
-    }
+const char *last_error()
+{
+    return g_last_error.c_str();
+}
 
-  private:
-    int prev_ = -1;
-    bool switched_ = false;
-};
+DeviceGuard::DeviceGuard(int dev)
+{
+    if (hipGetDevice(&prev_) == hipSuccess && prev_ != dev && hipSetDevice(dev) == hipSuccess)
+        switched_ = true;
+}
+
+DeviceGuard::~DeviceGuard()
+{
+    if (switched_)
+        (void)hipSetDevice(prev_);
+}
+
+} // namespace bbfc
+
+namespace {
+
+using bbfc::DeviceGuard;
+using bbfc::fail;
+using bbfc::hip_fail;
 
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): golden-gamma increment and
 // the variant-13 finaliser.
@@ -193,6 +199,11 @@ bbfc_status create_impl(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_co
     hipError_t e = hipGetDevice(&f->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&f->num_cus, hipDeviceAttributeMultiprocessorCount, f->device);
+    int max_lds = 0;
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, f->device);
+    if (e == hipSuccess && max_lds > 0)
+        f->max_lds = (size_t)max_lds;
     if (e != hipSuccess) {
         delete f;
         return hip_fail(e, "querying the current device");
@@ -409,6 +420,21 @@ bbfc_status bbfc_set_option(bbfc_handle h, int32_t option, int64_t value)
             return fail(BBFC_EINVAL, "BBFC_OPT_QUERY_EARLY_EXIT takes 0 or 1");
         h->query_early_exit = (int)value;
         return BBFC_OK;
+    case BBFC_OPT_LANES_PER_KEY:
+        if (value != 4 && value != 8)
+            return fail(BBFC_EINVAL, "BBFC_OPT_LANES_PER_KEY takes 4 or 8");
+        h->lanes_per_key = (int)value;
+        return BBFC_OK;
+    case BBFC_OPT_TILES_PER_WAVE:
+        if (value != 1 && value != 2)
+            return fail(BBFC_EINVAL, "BBFC_OPT_TILES_PER_WAVE takes 1 or 2");
+        h->tiles_per_wave = (int)value;
+        return BBFC_OK;
+    case BBFC_OPT_WGS_PER_CU:
+        if (value > 64)
+            return fail(BBFC_EINVAL, "BBFC_OPT_WGS_PER_CU takes 0..64");
+        h->wgs_per_cu = (int)value;
+        return BBFC_OK;
     default:
         return fail(BBFC_EINVAL, "unknown option %d", (int)option);
     }
@@ -424,6 +450,15 @@ bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value)
         return BBFC_OK;
     case BBFC_OPT_QUERY_EARLY_EXIT:
         *value = h->query_early_exit;
+        return BBFC_OK;
+    case BBFC_OPT_LANES_PER_KEY:
+        *value = h->lanes_per_key;
+        return BBFC_OK;
+    case BBFC_OPT_TILES_PER_WAVE:
+        *value = h->tiles_per_wave;
+        return BBFC_OK;
+    case BBFC_OPT_WGS_PER_CU:
+        *value = h->wgs_per_cu;
         return BBFC_OK;
     default:
         return fail(BBFC_EINVAL, "unknown option %d", (int)option);
@@ -471,7 +506,7 @@ const char *bbfc_status_string(bbfc_status s)
 
 const char *bbfc_last_error(void)
 {
-    return g_last_error.c_str();
+    return bbfc::last_error();
 }
 
 bbfc_status bbfc_probe_gather(const uint64_t *d_buf, uint64_t n_lines64, uint32_t access_bytes, uint64_t n_access,

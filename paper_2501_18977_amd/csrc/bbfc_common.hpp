@@ -76,9 +76,29 @@ struct KParams {
     uint32_t fm_sh2;
     uint32_t pow2_shift;    // 64 - log2(M) (mode Pow2)
     uint32_t k;
+    uint32_t mode;          // HashMode of M
+    uint32_t c;             // choices (informational; kernels take C as a template)
     uint64_t block_mult[BBFC_MAX_CHOICES];
     uint64_t bit_mult[BBFC_MAX_BITS_PER_KEY];
 };
+
+template <int MODE>
+__host__ __device__ inline uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x);
+
+// The hash mode read from the parameters (uniform across a wavefront).
+__host__ __device__ inline uint64_t block_hash_rt(const KParams &p, uint64_t a, uint64_t x)
+{
+    switch (p.mode) {
+    case kModeOne:
+        return block_hash<kModeOne>(p, a, x);
+    case kModePow2:
+        return block_hash<kModePow2>(p, a, x);
+    case kModeEven:
+        return block_hash<kModeEven>(p, a, x);
+    default:
+        return block_hash<kModeOdd>(p, a, x);
+    }
+}
 
 template <int MODE>
 __host__ __device__ inline uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x)

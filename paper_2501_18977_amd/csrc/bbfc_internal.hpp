@@ -25,11 +25,36 @@ struct bbfc_filter {
     int num_cus = 0;
     uint64_t max_inflight = 0;    // 0: n_blocks/32
     int query_early_exit = 1;     // load choice i+1 only for keys still unanswered
+    int lanes_per_key = 8;        // 8 or 4 lanes share one key's block reads
+    int tiles_per_wave = 1;       // 64-key tiles a wavefront holds at once (1 or 2)
+    int wgs_per_cu = 0;           // cap on resident workgroups per CU (0: as many as fit)
+    size_t max_lds = 65536;       // LDS bytes a workgroup may use on this device
 };
 
 namespace bbfc {
 
+// Records a message for bbfc_last_error() and returns s.
+bbfc_status fail(bbfc_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+bbfc_status hip_fail(hipError_t e, const char *what);
+const char *last_error();
+
+// Makes a device current for the scope of a call.
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+    DeviceGuard(const DeviceGuard &) = delete;
+    DeviceGuard &operator=(const DeviceGuard &) = delete;
+
+  private:
+    int prev_ = -1;
+    bool switched_ = false;
+};
+
 KParams make_kparams(const bbfc_filter &f);
+
+// Dynamic LDS of the insert kernels: the cost rank table (none for c = 1).
+size_t rank_lds_bytes(uint32_t c, uint32_t k);
 
 // Keys in flight for a racing insert on this filter.
 uint64_t insert_inflight(const bbfc_filter &f);
