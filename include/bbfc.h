@@ -219,7 +219,9 @@ typedef struct bbfc_batch *bbfc_batch_handle;
  * its packed answers (bbfc_batch_query) start at word
  * ceil(n_keys[0]/64) + ... + ceil(n_keys[f-1]/64), in bbfc_query's layout.
  * Filters with no keys are allowed. The filters must outlive the plan and
- * every graph captured from it. Errors: EINVAL (null pointers,
+ * every graph captured from it. Each call on a plan resets and uses the
+ * plan's work counter, so calls on one plan must not overlap (enqueue them
+ * on one stream). Errors: EINVAL (null pointers,
  * n_filters == 0, mixed devices or choices), EHIP. */
 bbfc_status bbfc_batch_create(const bbfc_handle *filters, const uint64_t *n_keys, uint32_t n_filters,
                               bbfc_batch_handle *out);
@@ -239,12 +241,18 @@ bbfc_status bbfc_batch_insert(bbfc_batch_handle b, const uint64_t *d_keys, hipSt
 bbfc_status bbfc_batch_query(bbfc_batch_handle b, const uint64_t *d_keys, uint64_t *d_out_bits, hipStream_t stream);
 
 /* Launch shape of a plan's persistent kernel for one operation: lanes per
- * key (8 or 4), 64-key tiles per wavefront (1 or 2) and a cap on resident
- * workgroups per CU (0 = as many as fit). ms is filled by the tuner. */
+ * key (8 or 4), 64-key tiles per wavefront (1 or 2), a cap on resident
+ * workgroups per CU (0 = as many as fit) and, for queries, the schedule:
+ * units_per_grab == 0 strides units of tiles_per_wave tiles statically over
+ * the wavefronts; 1..4096 hands them out in order, that many per atomic
+ * grab (inserts always grab one slot at a time; the field is ignored).
+ * Defaults: insert {8, 1, 0, 1}, query {8, 1, 0, 0}. ms is filled by the
+ * tuner. Shapes change speed only, never answers. */
 typedef struct {
     int32_t lanes_per_key;
     int32_t tiles_per_wave;
     int32_t wgs_per_cu;
+    int32_t units_per_grab;
     float ms;
 } bbfc_launch_shape;
 
@@ -255,7 +263,8 @@ bbfc_status bbfc_batch_set_shape(bbfc_batch_handle b, int32_t op, bbfc_launch_sh
 bbfc_status bbfc_batch_get_shape(bbfc_batch_handle b, int32_t op, bbfc_launch_shape *shape);
 
 /* Autotuner: times every candidate shape (lanes per key 8|4, tiles per
- * wavefront 1|2, workgroups per CU unbounded|2) of the plan's persistent
+ * wavefront 1|2, workgroups per CU unbounded|2, and for queries a static
+ * stride or ordered grabs of 16 units) of the plan's persistent
  * kernel for `op` on the caller's keys, `reps` timed runs each after one
  * warm-up, keeps the fastest in the plan and returns it in *best (may be
  * null). Insert trials run on a snapshot: the filters' words are copied

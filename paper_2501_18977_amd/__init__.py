@@ -57,7 +57,7 @@ class _Cost(ctypes.Structure):
 
 class _Shape(ctypes.Structure):
     _fields_ = [("lanes_per_key", ctypes.c_int32), ("tiles_per_wave", ctypes.c_int32),
-                ("wgs_per_cu", ctypes.c_int32), ("ms", ctypes.c_float)]
+                ("wgs_per_cu", ctypes.c_int32), ("units_per_grab", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 _lib = None
@@ -311,7 +311,7 @@ class Filter:
 
 def _shape_dict(sh: _Shape) -> dict:
     return {"lanes_per_key": sh.lanes_per_key, "tiles_per_wave": sh.tiles_per_wave,
-            "wgs_per_cu": sh.wgs_per_cu, "ms": sh.ms}
+            "wgs_per_cu": sh.wgs_per_cu, "units_per_grab": sh.units_per_grab, "ms": sh.ms}
 
 
 class Batch:
@@ -365,8 +365,12 @@ class Batch:
         _check(lib().bbfc_batch_query(self.handle, keys.data_ptr(), out.data_ptr(), _stream_handle(stream)))
         return out
 
-    def set_shape(self, op: int, lanes_per_key: int = 8, tiles_per_wave: int = 1, wgs_per_cu: int = 0) -> None:
-        _check(lib().bbfc_batch_set_shape(self.handle, op, _Shape(lanes_per_key, tiles_per_wave, wgs_per_cu, 0.0)))
+    def set_shape(self, op: int, lanes_per_key: int = 8, tiles_per_wave: int = 1, wgs_per_cu: int = 0,
+                  units_per_grab: int | None = None) -> None:
+        if units_per_grab is None:
+            units_per_grab = 1 if op == OP_INSERT else 0
+        _check(lib().bbfc_batch_set_shape(self.handle, op, _Shape(lanes_per_key, tiles_per_wave, wgs_per_cu,
+                                                                  units_per_grab, 0.0)))
 
     def get_shape(self, op: int) -> dict:
         sh = _Shape()

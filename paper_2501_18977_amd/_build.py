@@ -42,13 +42,30 @@ def sources() -> list[str]:
 
 
 def build(extra_flags: list[str] | None = None, out: str | None = None, verbose: bool = False) -> str:
-    """Compile every source into ``libbbfc.so`` (always rebuilds)."""
+    """Compile every source (in parallel) and link ``libbbfc.so``; always rebuilds."""
+    from concurrent.futures import ThreadPoolExecutor
+
     out = out or LIB
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    common = [hipcc(), *HIP_FLAGS, *(extra_flags or []), "-I", os.path.join(ROOT, "include")]
+    compile_flags = [f for f in common if f != "-shared"]
+
+    def compile_one(src: str) -> str:
+        obj = os.path.join(objdir, os.path.basename(src) + ".o")
+        cmd = [*compile_flags, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, sources()))
     tmp = out + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, *(extra_flags or []), "-I", os.path.join(ROOT, "include"), "-o", tmp, *sources()]
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, out)
     return out
 

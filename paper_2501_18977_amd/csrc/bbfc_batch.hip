@@ -57,41 +57,73 @@ __device__ inline uint32_t wave_index()
     return (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
 }
 
+// The first active lane's 64-bit value, as a wave-uniform value.
+__device__ inline uint64_t first_lane_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Two schedules, chosen per launch: grab == 0 strides units statically over
+// the resident wavefronts; grab > 0 hands out units in increasing order,
+// `grab` at a time, from an atomic counter, which keeps the units in flight
+// in one moving window (fewer filters read at once, better cache reuse) at
+// the price of one counter atomic per grab.
 template <int C, int LPK, int T, bool EARLY>
 __global__ __launch_bounds__(kWGSize) void batch_query_kernel(const BatchFilter *__restrict__ filt, uint32_t n_filters,
-                                                              uint64_t total_units, const uint64_t *__restrict__ keys,
+                                                              uint64_t total_units, uint32_t grab,
+                                                              unsigned long long *counter,
+                                                              const uint64_t *__restrict__ keys,
                                                               uint64_t *__restrict__ out)
 {
     __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
     __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = wave_index();
-    const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerWG;
     uint32_t f = 0;
-    for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerWG + wv; u < total_units; u += n_waves) {
+    auto unit = [&](uint64_t u) {
         while (f + 1 < n_filters && filt[f + 1].unit_off <= u)
             ++f;
         const BatchFilter &bf = filt[f];
         const uint64_t lu = u - bf.unit_off;
         query_tiles<C, LPK, T, EARLY>(bf.p, keys + bf.key_off, bf.n, lu * T * kTile, out + bf.out_off + lu * T, lane,
                                       s_mask[wv], s_blk[wv]);
+    };
+    if (grab == 0) {
+        const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerWG;
+        for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerWG + wv; u < total_units; u += n_waves)
+            unit(u);
+        return;
+    }
+    for (;;) {
+        unsigned long long first = 0;
+        if (lane == 0)
+            first = atomicAdd(counter, (unsigned long long)grab);
+        first = first_lane_u64(first);
+        if (first >= total_units)
+            break;
+        const uint64_t last = first + grab < total_units ? first + grab : total_units;
+        for (uint64_t u = first; u < last; ++u)
+            unit(u);
     }
 }
 
 template <int C, int LPK, int T>
 __global__ __launch_bounds__(kWGSize) void batch_insert_kernel(const BatchFilter *__restrict__ filt,
                                                                const BatchSlot *__restrict__ slots, uint32_t n_slots,
-                                                               uint32_t *counter, const uint64_t *__restrict__ keys)
+                                                               unsigned long long *counter,
+                                                               const uint64_t *__restrict__ keys)
 {
     __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
     __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = wave_index();
     for (;;) {
-        uint32_t s = 0;
+        unsigned long long s = 0;
         if (lane == 0)
-            s = atomicAdd(counter, 1u);
-        s = (uint32_t)__builtin_amdgcn_readfirstlane(s);
+            s = atomicAdd(counter, 1ull);
+        s = first_lane_u64(s);
         if (s >= n_slots)
             break;
         const BatchSlot sl = slots[s];
@@ -102,7 +134,9 @@ __global__ __launch_bounds__(kWGSize) void batch_insert_kernel(const BatchFilter
     }
 }
 
-__global__ void reset_counter_kernel(uint32_t *counter)
+// Zeroes the persistent kernels' work counters (a kernel rather than a
+// memset, so that graphs replay it correctly).
+__global__ void reset_counter_kernel(unsigned long long *counter)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0)
         *counter = 0;
@@ -150,7 +184,7 @@ uint64_t resident_wgs(K kernel, int num_cus, int wgs_per_cu)
 bool valid_shape(const bbfc_launch_shape &s)
 {
     return (s.lanes_per_key == 4 || s.lanes_per_key == 8) && (s.tiles_per_wave == 1 || s.tiles_per_wave == 2) &&
-           s.wgs_per_cu >= 0 && s.wgs_per_cu <= 64;
+           s.wgs_per_cu >= 0 && s.wgs_per_cu <= 64 && s.units_per_grab >= 0 && s.units_per_grab <= 4096;
 }
 
 } // namespace
@@ -162,7 +196,7 @@ namespace {
 struct Tables {
     BatchFilter *d_filt = nullptr;
     BatchSlot *d_slots = nullptr;
-    uint32_t *d_counter = nullptr;
+    unsigned long long *d_counter = nullptr;
     uint32_t n_filters = 0;
     uint32_t n_slots = 0;
     uint64_t total_units = 0;
@@ -179,7 +213,7 @@ struct bbfc_batch {
     int num_cus = 0;
     uint64_t total_keys = 0;
     uint64_t total_words = 0;
-    bbfc_launch_shape shape[2] = {{8, 1, 0, 0.0f}, {8, 1, 0, 0.0f}}; // [BBFC_OP_INSERT], [BBFC_OP_QUERY]
+    bbfc_launch_shape shape[2] = {{8, 1, 0, 1, 0.0f}, {8, 1, 0, 0, 0.0f}}; // [BBFC_OP_INSERT], [BBFC_OP_QUERY]
     // device tables, rebuilt when a shape changes (graphs keep their own copies)
     bbfc::Tables t;
     int tables_tpw_query = 0;
@@ -228,7 +262,7 @@ hipError_t copy_tables(const Tables &src, Tables &dst)
     if (e == hipSuccess)
         e = hipMalloc(&dst.d_slots, src.slot_bytes);
     if (e == hipSuccess)
-        e = hipMalloc(&dst.d_counter, sizeof(uint32_t));
+        e = hipMalloc(&dst.d_counter, sizeof(unsigned long long));
     if (e == hipSuccess)
         e = hipMemcpy(dst.d_filt, src.d_filt, src.n_filters * sizeof(BatchFilter), hipMemcpyDeviceToDevice);
     if (e == hipSuccess)
@@ -306,6 +340,13 @@ hipError_t launch_batch_query(const Tables &t, uint32_t c, int num_cus, const bb
 {
     if (t.total_units == 0)
         return hipSuccess;
+    const uint32_t grab = (uint32_t)sh.units_per_grab;
+    if (grab > 0) {
+        hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, t.d_counter);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     return with_choices(c, [&](auto Cc) {
         constexpr int C = decltype(Cc)::value;
         return with_shape(sh.lanes_per_key, sh.tiles_per_wave, [&](auto L, auto Tt) {
@@ -314,10 +355,11 @@ hipError_t launch_batch_query(const Tables &t, uint32_t c, int num_cus, const bb
             constexpr bool EARLY = C > 1;
             auto kern = batch_query_kernel<C, LPK, T, EARLY>;
             uint64_t wgs = resident_wgs(kern, num_cus, sh.wgs_per_cu);
-            const uint64_t need = (t.total_units + kWavesPerWG - 1) / kWavesPerWG;
+            const uint64_t chunks = (t.total_units + (grab ? grab : 1) - 1) / (grab ? grab : 1);
+            const uint64_t need = (chunks + kWavesPerWG - 1) / kWavesPerWG;
             wgs = std::max<uint64_t>(1, std::min(wgs, need));
             hipLaunchKernelGGL(kern, dim3((uint32_t)wgs), dim3(kWGSize), 0, s, t.d_filt, t.n_filters, t.total_units,
-                               keys, out);
+                               grab, t.d_counter, keys, out);
             return hipGetLastError();
         });
     });
@@ -397,7 +439,7 @@ bbfc_status bbfc_batch_create(const bbfc_handle *filters, const uint64_t *n_keys
         b->total_words += (n_keys[f] + 63) / 64;
     }
     bbfc::DeviceGuard guard(b->device);
-    hipError_t e = hipMalloc(&b->t.d_counter, sizeof(uint32_t));
+    hipError_t e = hipMalloc(&b->t.d_counter, sizeof(unsigned long long));
     if (e != hipSuccess) {
         delete b;
         return hip_fail(e, "allocating the batch counter");
@@ -537,42 +579,48 @@ bbfc_status bbfc_batch_tune(bbfc_batch_handle b, int32_t op, const uint64_t *d_k
 
     bbfc_launch_shape winner = saved;
     float best_ms = -1.0f;
-    const int lpks[2] = {8, 4};
-    const int tpws[2] = {1, 2};
-    const int occs[2] = {0, 2};
-    for (int li = 0; li < 2 && e == hipSuccess && st == BBFC_OK; ++li)
-        for (int ti = 0; ti < 2 && e == hipSuccess && st == BBFC_OK; ++ti)
-            for (int oi = 0; oi < 2 && e == hipSuccess && st == BBFC_OK; ++oi) {
-                b->shape[op] = bbfc_launch_shape{lpks[li], tpws[ti], occs[oi], 0.0f};
-                st = bbfc::build_tables(*b);
-                if (st != BBFC_OK)
-                    break;
-                float total = 0.0f;
-                for (uint32_t r = 0; r <= reps && e == hipSuccess; ++r) { // r == 0 warms up
-                    if (op == BBFC_OP_INSERT)
-                        e = restore();
-                    if (e == hipSuccess)
-                        e = hipEventRecord(ev0, stream);
-                    if (e == hipSuccess)
-                        e = op == BBFC_OP_INSERT ? bbfc::plan_insert(*b, d_keys, stream)
-                                                 : bbfc::plan_query(*b, d_keys, d_out_bits, stream);
-                    if (e == hipSuccess)
-                        e = hipEventRecord(ev1, stream);
-                    if (e == hipSuccess)
-                        e = hipEventSynchronize(ev1);
-                    float ms = 0.0f;
-                    if (e == hipSuccess)
-                        e = hipEventElapsedTime(&ms, ev0, ev1);
-                    if (r > 0)
-                        total += ms;
+    // Candidates: lanes per key x tiles per wavefront x occupancy cap, and
+    // for queries the schedule (static stride, or ordered grabs of 16 units).
+    std::vector<bbfc_launch_shape> cands;
+    for (int lpk : {8, 4})
+        for (int tpw : {1, 2})
+            for (int occ : {0, 2})
+                for (int grab : {0, 16}) {
+                    if (op == BBFC_OP_INSERT && grab == 16)
+                        continue; // inserts always take whole slots, one per grab
+                    cands.push_back(bbfc_launch_shape{lpk, tpw, occ, op == BBFC_OP_INSERT ? 1 : grab, 0.0f});
                 }
-                const float avg = total / (float)reps;
-                if (e == hipSuccess && (best_ms < 0.0f || avg < best_ms)) {
-                    best_ms = avg;
-                    winner = b->shape[op];
-                    winner.ms = avg;
-                }
-            }
+    for (size_t ci = 0; ci < cands.size() && e == hipSuccess && st == BBFC_OK; ++ci) {
+        b->shape[op] = cands[ci];
+        st = bbfc::build_tables(*b);
+        if (st != BBFC_OK)
+            break;
+        float total = 0.0f;
+        for (uint32_t r = 0; r <= reps && e == hipSuccess; ++r) { // r == 0 warms up
+            if (op == BBFC_OP_INSERT)
+                e = restore();
+            if (e == hipSuccess)
+                e = hipEventRecord(ev0, stream);
+            if (e == hipSuccess)
+                e = op == BBFC_OP_INSERT ? bbfc::plan_insert(*b, d_keys, stream)
+                                         : bbfc::plan_query(*b, d_keys, d_out_bits, stream);
+            if (e == hipSuccess)
+                e = hipEventRecord(ev1, stream);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(ev1);
+            float ms = 0.0f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, ev0, ev1);
+            if (r > 0)
+                total += ms;
+        }
+        const float avg = total / (float)reps;
+        if (e == hipSuccess && (best_ms < 0.0f || avg < best_ms)) {
+            best_ms = avg;
+            winner = b->shape[op];
+            winner.ms = avg;
+        }
+    }
     if (e == hipSuccess && op == BBFC_OP_INSERT)
         e = restore();
     if (e == hipSuccess)

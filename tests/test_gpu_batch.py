@@ -26,7 +26,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 COSTS = {"none": oracle.COST_NONE, "mix": oracle.COST_MIX, "la": oracle.COST_LA, "exp": oracle.COST_EXP}
-SHAPES = list(itertools.product([8, 4], [1, 2], [0, 2]))
+SHAPES = list(itertools.product([8, 4], [1, 2], [0, 2], [0, 3]))
 
 
 @pytest.fixture(scope="module")
@@ -83,15 +83,15 @@ def split_answers(out_words, counts):
     return res
 
 
-@pytest.mark.parametrize("lpk,tpw,occ", SHAPES)
-def test_batch_query_matches_oracle_for_every_shape(dev, lpk, tpw, occ):
+@pytest.mark.parametrize("lpk,tpw,occ,grab", SHAPES)
+def test_batch_query_matches_oracle_for_every_shape(dev, lpk, tpw, occ, grab):
     refs, gpus, ns = build_set(2, "exp", 11, dev)
     for i, (r, g) in enumerate(zip(refs, gpus)):
         r.insert(workload.positive_keys(11 + i, ns[i]))
         g.upload(r.words)
     qn = [2 * n for n in ns]
     plan = bbfc.Batch(gpus, qn)
-    plan.set_shape(bbfc.OP_QUERY, lpk, tpw, occ)
+    plan.set_shape(bbfc.OP_QUERY, lpk, tpw, occ, grab)
     keys = keys_for(ns, 11, negatives=True)
     out = torch.full((plan.total_out_words + 2,), -1, dtype=torch.int64, device=dev)
     plan.query(to_dev(keys, dev), out=out)

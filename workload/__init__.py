@@ -109,6 +109,19 @@ def draw_multipliers(seed: int, count: int, coprime_to: int = 2) -> list[int]:
     return out
 
 
+def batch_specs(seed: int, count: int, log2_lo: float = 10.0, log2_hi: float = 24.0,
+                bits_lo: int = 10, bits_hi: int = 16) -> list[tuple[int, int]]:
+    """(keys, space bits per key) of `count` filters: keys = round(2^U) with
+    U uniform in [log2_lo, log2_hi], bits uniform in {bits_lo..bits_hi}."""
+    rng = SplitMix64(seed)
+    out = []
+    for _ in range(count):
+        u = log2_lo + (log2_hi - log2_lo) * ((rng.next() >> 11) / float(1 << 53))
+        b = bits_lo + rng.next() % (bits_hi - bits_lo + 1)
+        out.append((int(round(2.0 ** u)), int(b)))
+    return out
+
+
 # ----------------------------------------------------- device-side generator
 
 import ctypes as _ctypes
