@@ -169,26 +169,43 @@ bbfc_status bbfc_get_words(bbfc_handle h, uint64_t **d_words);
  *   BBFC_OPT_QUERY_EARLY_EXIT  1 (default): a query reads candidate i+1
  *       only for keys that candidates 1..i did not answer; 0: every
  *       candidate is read. Answers are identical either way.
- *   BBFC_OPT_LANES_PER_KEY  8 (default) or 4 lanes of a wavefront share
- *       one key's block reads (8 bytes or 16 bytes per lane per block).
- *   BBFC_OPT_TILES_PER_WAVE  1 (default) or 2 tiles of 64 keys held by a
- *       wavefront at once (more reads in flight per wavefront; an insert
- *       falls back to 1 where two tiles and the rank table exceed LDS).
- *   BBFC_OPT_WGS_PER_CU  cap on resident workgroups per CU, 0 (default)
- *       for as many as fit.
- * Answers and the deterministic insert do not depend on the last three; a
- * racing insert's filter may (it is schedule dependent anyway).
  * Errors: EINVAL (null handle or pointer, unknown option, value out of
  * range). */
 typedef enum {
     BBFC_OPT_INSERT_INFLIGHT = 1,
-    BBFC_OPT_QUERY_EARLY_EXIT = 2,
-    BBFC_OPT_LANES_PER_KEY = 3,
-    BBFC_OPT_TILES_PER_WAVE = 4,
-    BBFC_OPT_WGS_PER_CU = 5
+    BBFC_OPT_QUERY_EARLY_EXIT = 2
 } bbfc_option;
 bbfc_status bbfc_set_option(bbfc_handle h, int32_t option, int64_t value);
 bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value);
+
+/* Launch shape of the kernels for one operation (a filter and a batch plan
+ * hold one per operation): lanes per key (8 or 4: 8 or 16 bytes per lane
+ * per block read), 64-key tiles per wavefront (1 or 2: more reads in
+ * flight per wavefront; an insert falls back to 1 where two tiles and the
+ * rank table exceed a workgroup's LDS), a cap on resident workgroups per
+ * CU (0 = as many as fit) and, for a batch plan's queries, the schedule:
+ * units_per_grab == 0 strides units of tiles_per_wave tiles statically over
+ * the wavefronts; 1..4096 hands them out in order, that many per atomic
+ * grab (single filters always stride; batch inserts always grab one slot
+ * at a time). Defaults {8, 1, 0, 0} (batch inserts {8, 1, 0, 1}). ms is
+ * filled by the tuners. Shapes change speed only, never answers, and never
+ * the deterministic insert; a racing insert's filter is schedule dependent
+ * anyway. */
+typedef struct {
+    int32_t lanes_per_key;
+    int32_t tiles_per_wave;
+    int32_t wgs_per_cu;
+    int32_t units_per_grab;
+    float ms;
+} bbfc_launch_shape;
+
+#define BBFC_OP_INSERT 0
+#define BBFC_OP_QUERY 1
+
+/* Shape of one filter's kernels for `op` (BBFC_OP_INSERT or
+ * BBFC_OP_QUERY); units_per_grab is ignored. Errors: EINVAL. */
+bbfc_status bbfc_set_shape(bbfc_handle h, int32_t op, bbfc_launch_shape shape);
+bbfc_status bbfc_get_shape(bbfc_handle h, int32_t op, bbfc_launch_shape *shape);
 
 /* Number of blocks for n_keys keys at `space_bits_per_key` bits per key:
  * ceil(n_keys * space_bits_per_key / 512), at least 1 (App. C sizes a
@@ -240,25 +257,6 @@ bbfc_status bbfc_batch_insert(bbfc_batch_handle b, const uint64_t *d_keys, hipSt
  * the keys. */
 bbfc_status bbfc_batch_query(bbfc_batch_handle b, const uint64_t *d_keys, uint64_t *d_out_bits, hipStream_t stream);
 
-/* Launch shape of a plan's persistent kernel for one operation: lanes per
- * key (8 or 4), 64-key tiles per wavefront (1 or 2), a cap on resident
- * workgroups per CU (0 = as many as fit) and, for queries, the schedule:
- * units_per_grab == 0 strides units of tiles_per_wave tiles statically over
- * the wavefronts; 1..4096 hands them out in order, that many per atomic
- * grab (inserts always grab one slot at a time; the field is ignored).
- * Defaults: insert {8, 1, 0, 1}, query {8, 1, 0, 0}. ms is filled by the
- * tuner. Shapes change speed only, never answers. */
-typedef struct {
-    int32_t lanes_per_key;
-    int32_t tiles_per_wave;
-    int32_t wgs_per_cu;
-    int32_t units_per_grab;
-    float ms;
-} bbfc_launch_shape;
-
-#define BBFC_OP_INSERT 0
-#define BBFC_OP_QUERY 1
-
 bbfc_status bbfc_batch_set_shape(bbfc_batch_handle b, int32_t op, bbfc_launch_shape shape);
 bbfc_status bbfc_batch_get_shape(bbfc_batch_handle b, int32_t op, bbfc_launch_shape *shape);
 
@@ -273,6 +271,19 @@ bbfc_status bbfc_batch_get_shape(bbfc_batch_handle b, int32_t op, bbfc_launch_sh
  * unchanged on return. Synchronises `stream`. */
 bbfc_status bbfc_batch_tune(bbfc_batch_handle b, int32_t op, const uint64_t *d_keys, uint64_t *d_out_bits,
                             uint32_t reps, hipStream_t stream, bbfc_launch_shape *best);
+
+/* Autotuner of one filter's kernels: times each shape (lanes per key 8|4,
+ * tiles per wavefront 1|2, workgroups per CU unbounded|2) of `op` on
+ * d_keys[0..n), `reps` timed runs each after one warm-up, and makes the
+ * fastest the filter's shape for `op` (returned in *best, may be null);
+ * the shape in force is kept unless another is more than 2% faster.
+ * Insert trials run on a snapshot (8*n_blocks words of device memory for
+ * the duration), restored before every trial and at the end, so the
+ * filter is unchanged on return; query trials write d_out_bits. The same
+ * call sequence the tuner times is what a later bbfc_insert/bbfc_query
+ * launches. Synchronises `stream`. */
+bbfc_status bbfc_tune(bbfc_handle h, int32_t op, const uint64_t *d_keys, uint64_t n, uint64_t *d_out_bits,
+                      uint32_t reps, hipStream_t stream, bbfc_launch_shape *best);
 
 /* ------------------------------------------------------------------ */
 /* Graphs: batch launches captured once and replayed.                    */

@@ -38,7 +38,7 @@ __all__ = [
 
 COST_NONE, COST_MIX, COST_LA, COST_EXP = 0, 1, 2, 3
 OP_INSERT, OP_QUERY = 0, 1
-OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT, OPT_LANES_PER_KEY, OPT_TILES_PER_WAVE, OPT_WGS_PER_CU = 1, 2, 3, 4, 5
+OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT = 1, 2
 _COST_BY_NAME = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -112,6 +112,9 @@ def lib() -> ctypes.CDLL:
         "bbfc_batch_set_shape": (_st, [_vp, ctypes.c_int32, _Shape]),
         "bbfc_batch_get_shape": (_st, [_vp, ctypes.c_int32, _vp]),
         "bbfc_batch_tune": (_st, [_vp, ctypes.c_int32, _vp, _vp, _u32, _vp, _vp]),
+        "bbfc_set_shape": (_st, [_vp, ctypes.c_int32, _Shape]),
+        "bbfc_get_shape": (_st, [_vp, ctypes.c_int32, _vp]),
+        "bbfc_tune": (_st, [_vp, ctypes.c_int32, _vp, _u64, _vp, _u32, _vp, _vp]),
         "bbfc_graph_create": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "bbfc_graph_launch": (_st, [_vp, _vp]),
         "bbfc_graph_destroy": (_st, [_vp]),
@@ -245,6 +248,24 @@ class Filter:
         v = ctypes.c_int64()
         _check(lib().bbfc_get_option(self.handle, option, ctypes.byref(v)))
         return int(v.value)
+
+    def set_shape(self, op: int, lanes_per_key: int = 8, tiles_per_wave: int = 1, wgs_per_cu: int = 0) -> None:
+        _check(lib().bbfc_set_shape(self.handle, op, _Shape(lanes_per_key, tiles_per_wave, wgs_per_cu, 0, 0.0)))
+
+    def get_shape(self, op: int) -> dict:
+        sh = _Shape()
+        _check(lib().bbfc_get_shape(self.handle, op, ctypes.byref(sh)))
+        return _shape_dict(sh)
+
+    def tune(self, op: int, keys, out=None, reps: int = 2, stream=None) -> dict:
+        """Time the launch shapes of `op` on these keys and keep the fastest
+        (the filter's words are unchanged afterwards)."""
+        keys = _device_u64(keys, "keys")
+        optr = out.data_ptr() if out is not None else None
+        sh = _Shape()
+        _check(lib().bbfc_tune(self.handle, op, keys.data_ptr(), keys.numel(), optr, reps, _stream_handle(stream),
+                               ctypes.byref(sh)))
+        return _shape_dict(sh)
 
     # -------------------------------------------------------------- ops
     def insert(self, keys, stream=None) -> None:

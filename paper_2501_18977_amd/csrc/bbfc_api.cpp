@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <string>
 #include <utility>
 #include <vector>
@@ -420,21 +421,6 @@ bbfc_status bbfc_set_option(bbfc_handle h, int32_t option, int64_t value)
             return fail(BBFC_EINVAL, "BBFC_OPT_QUERY_EARLY_EXIT takes 0 or 1");
         h->query_early_exit = (int)value;
         return BBFC_OK;
-    case BBFC_OPT_LANES_PER_KEY:
-        if (value != 4 && value != 8)
-            return fail(BBFC_EINVAL, "BBFC_OPT_LANES_PER_KEY takes 4 or 8");
-        h->lanes_per_key = (int)value;
-        return BBFC_OK;
-    case BBFC_OPT_TILES_PER_WAVE:
-        if (value != 1 && value != 2)
-            return fail(BBFC_EINVAL, "BBFC_OPT_TILES_PER_WAVE takes 1 or 2");
-        h->tiles_per_wave = (int)value;
-        return BBFC_OK;
-    case BBFC_OPT_WGS_PER_CU:
-        if (value > 64)
-            return fail(BBFC_EINVAL, "BBFC_OPT_WGS_PER_CU takes 0..64");
-        h->wgs_per_cu = (int)value;
-        return BBFC_OK;
     default:
         return fail(BBFC_EINVAL, "unknown option %d", (int)option);
     }
@@ -451,18 +437,118 @@ bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value)
     case BBFC_OPT_QUERY_EARLY_EXIT:
         *value = h->query_early_exit;
         return BBFC_OK;
-    case BBFC_OPT_LANES_PER_KEY:
-        *value = h->lanes_per_key;
-        return BBFC_OK;
-    case BBFC_OPT_TILES_PER_WAVE:
-        *value = h->tiles_per_wave;
-        return BBFC_OK;
-    case BBFC_OPT_WGS_PER_CU:
-        *value = h->wgs_per_cu;
-        return BBFC_OK;
     default:
         return fail(BBFC_EINVAL, "unknown option %d", (int)option);
     }
+}
+
+bbfc_status bbfc_set_shape(bbfc_handle h, int32_t op, bbfc_launch_shape shape)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (op != BBFC_OP_INSERT && op != BBFC_OP_QUERY)
+        return fail(BBFC_EINVAL, "op must be BBFC_OP_INSERT or BBFC_OP_QUERY");
+    if ((shape.lanes_per_key != 4 && shape.lanes_per_key != 8) ||
+        (shape.tiles_per_wave != 1 && shape.tiles_per_wave != 2) || shape.wgs_per_cu < 0 || shape.wgs_per_cu > 64)
+        return fail(BBFC_EINVAL, "shape: lanes_per_key 4|8, tiles_per_wave 1|2, wgs_per_cu 0..64");
+    shape.units_per_grab = 0;
+    shape.ms = 0.0f;
+    h->shape[op] = shape;
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_get_shape(bbfc_handle h, int32_t op, bbfc_launch_shape *shape)
+{
+    if (h == nullptr || shape == nullptr)
+        return fail(BBFC_EINVAL, "null handle or output");
+    if (op != BBFC_OP_INSERT && op != BBFC_OP_QUERY)
+        return fail(BBFC_EINVAL, "op must be BBFC_OP_INSERT or BBFC_OP_QUERY");
+    *shape = h->shape[op];
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_tune(bbfc_handle h, int32_t op, const uint64_t *d_keys, uint64_t n, uint64_t *d_out_bits,
+                      uint32_t reps, hipStream_t stream, bbfc_launch_shape *best)
+{
+    if (h == nullptr || d_keys == nullptr || n == 0 || (op == BBFC_OP_QUERY && d_out_bits == nullptr))
+        return fail(BBFC_EINVAL, "null handle, keys or output, or no keys");
+    if (op != BBFC_OP_INSERT && op != BBFC_OP_QUERY)
+        return fail(BBFC_EINVAL, "op must be BBFC_OP_INSERT or BBFC_OP_QUERY");
+    if (reps == 0)
+        reps = 1;
+    DeviceGuard guard(h->device);
+    const int saved[3] = {h->shape[op].lanes_per_key, h->shape[op].tiles_per_wave, h->shape[op].wgs_per_cu};
+    uint64_t *snap = nullptr;
+    hipError_t e = hipSuccess;
+    if (op == BBFC_OP_INSERT) {
+        e = hipMalloc(&snap, h->M * 64);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(snap, h->d_words, h->M * 64, hipMemcpyDeviceToDevice, stream);
+    }
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (e == hipSuccess)
+        e = hipEventCreate(&ev0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&ev1);
+    bbfc_launch_shape winner{saved[0], saved[1], saved[2], 0, 0.0f};
+    float best_ms = -1.0f;
+    std::vector<std::array<int, 3>> cands = {{saved[0], saved[1], saved[2]}};
+    for (int lpk : {8, 4})
+        for (int tpw : {1, 2})
+            for (int occ : {0, 2})
+                if (!(lpk == saved[0] && tpw == saved[1] && occ == saved[2]))
+                    cands.push_back({lpk, tpw, occ});
+    for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
+        const int lpk = cands[ci][0], tpw = cands[ci][1], occ = cands[ci][2];
+        h->shape[op] = bbfc_launch_shape{lpk, tpw, occ, 0, 0.0f};
+        float total = 0.0f;
+        for (uint32_t r = 0; r <= reps && e == hipSuccess; ++r) { // r == 0 warms up
+            if (op == BBFC_OP_INSERT)
+                e = hipMemcpyAsync(h->d_words, snap, h->M * 64, hipMemcpyDeviceToDevice, stream);
+            if (e == hipSuccess)
+                e = hipEventRecord(ev0, stream);
+            if (e == hipSuccess)
+                e = op == BBFC_OP_INSERT ? bbfc::launch_insert(*h, d_keys, n, stream)
+                                         : bbfc::launch_query(*h, d_keys, n, d_out_bits, stream);
+            if (e == hipSuccess)
+                e = hipEventRecord(ev1, stream);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(ev1);
+            float ms = 0.0f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, ev0, ev1);
+            if (r > 0)
+                total += ms;
+        }
+        const float avg = total / (float)reps;
+        // the shape in force before tuning (candidate 0) keeps its place
+        // unless another is more than 2% faster
+        const bool winner_is_current = ci > 0 && winner.lanes_per_key == saved[0] &&
+                                       winner.tiles_per_wave == saved[1] && winner.wgs_per_cu == saved[2];
+        const float margin = winner_is_current ? 0.98f : 1.0f;
+        if (e == hipSuccess && (best_ms < 0.0f || avg < best_ms * margin)) {
+            best_ms = avg;
+            winner = bbfc_launch_shape{lpk, tpw, occ, 0, avg};
+        }
+    }
+    if (e == hipSuccess && snap)
+        e = hipMemcpyAsync(h->d_words, snap, h->M * 64, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(stream);
+    if (snap)
+        (void)hipFree(snap);
+    if (ev0)
+        (void)hipEventDestroy(ev0);
+    if (ev1)
+        (void)hipEventDestroy(ev1);
+    if (e != hipSuccess) {
+        h->shape[op] = bbfc_launch_shape{saved[0], saved[1], saved[2], 0, 0.0f};
+        return hip_fail(e, "autotuning");
+    }
+    h->shape[op] = winner;
+    if (best)
+        *best = winner;
+    return BBFC_OK;
 }
 
 uint64_t bbfc_blocks_for(uint64_t n_keys, double space_bits_per_key)

@@ -181,6 +181,12 @@ uint64_t resident_wgs(K kernel, int num_cus, int wgs_per_cu)
     return (uint64_t)per_cu * (uint64_t)(num_cus > 0 ? num_cus : 1);
 }
 
+bool same_shape(const bbfc_launch_shape &a, const bbfc_launch_shape &b)
+{
+    return a.lanes_per_key == b.lanes_per_key && a.tiles_per_wave == b.tiles_per_wave &&
+           a.wgs_per_cu == b.wgs_per_cu && a.units_per_grab == b.units_per_grab;
+}
+
 bool valid_shape(const bbfc_launch_shape &s)
 {
     return (s.lanes_per_key == 4 || s.lanes_per_key == 8) && (s.tiles_per_wave == 1 || s.tiles_per_wave == 2) &&
@@ -581,14 +587,16 @@ bbfc_status bbfc_batch_tune(bbfc_batch_handle b, int32_t op, const uint64_t *d_k
     float best_ms = -1.0f;
     // Candidates: lanes per key x tiles per wavefront x occupancy cap, and
     // for queries the schedule (static stride, or ordered grabs of 16 units).
-    std::vector<bbfc_launch_shape> cands;
+    std::vector<bbfc_launch_shape> cands = {saved}; // the shape in force is tried first
     for (int lpk : {8, 4})
         for (int tpw : {1, 2})
             for (int occ : {0, 2})
                 for (int grab : {0, 16}) {
                     if (op == BBFC_OP_INSERT && grab == 16)
                         continue; // inserts always take whole slots, one per grab
-                    cands.push_back(bbfc_launch_shape{lpk, tpw, occ, op == BBFC_OP_INSERT ? 1 : grab, 0.0f});
+                    const bbfc_launch_shape c{lpk, tpw, occ, op == BBFC_OP_INSERT ? 1 : grab, 0.0f};
+                    if (!bbfc::same_shape(c, saved))
+                        cands.push_back(c);
                 }
     for (size_t ci = 0; ci < cands.size() && e == hipSuccess && st == BBFC_OK; ++ci) {
         b->shape[op] = cands[ci];
@@ -615,7 +623,10 @@ bbfc_status bbfc_batch_tune(bbfc_batch_handle b, int32_t op, const uint64_t *d_k
                 total += ms;
         }
         const float avg = total / (float)reps;
-        if (e == hipSuccess && (best_ms < 0.0f || avg < best_ms)) {
+        // the shape in force (tried first) keeps its place unless another is
+        // more than 2% faster
+        const float margin = (ci > 0 && bbfc::same_shape(winner, saved)) ? 0.98f : 1.0f;
+        if (e == hipSuccess && (best_ms < 0.0f || avg < best_ms * margin)) {
             best_ms = avg;
             winner = b->shape[op];
             winner.ms = avg;

@@ -25,9 +25,8 @@ struct bbfc_filter {
     int num_cus = 0;
     uint64_t max_inflight = 0;    // 0: n_blocks/32
     int query_early_exit = 1;     // load choice i+1 only for keys still unanswered
-    int lanes_per_key = 8;        // 8 or 4 lanes share one key's block reads
-    int tiles_per_wave = 1;       // 64-key tiles a wavefront holds at once (1 or 2)
-    int wgs_per_cu = 0;           // cap on resident workgroups per CU (0: as many as fit)
+    // launch shape per operation, [BBFC_OP_INSERT] and [BBFC_OP_QUERY]
+    bbfc_launch_shape shape[2] = {{8, 1, 0, 0, 0.0f}, {8, 1, 0, 0, 0.0f}};
     size_t max_lds = 65536;       // LDS bytes a workgroup may use on this device
 };
 

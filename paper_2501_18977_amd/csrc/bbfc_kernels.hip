@@ -202,7 +202,7 @@ hipError_t insert_launch(const bbfc_filter &f, const uint64_t *keys, uint64_t n,
     uint64_t need = (n_units + kWavesPerWG - 1) / kWavesPerWG;
     if (cap_wgs < need)
         need = cap_wgs;
-    const uint64_t wgs = grid_for(insert_kernel<C, LPK, T>, lds, f.num_cus, f.wgs_per_cu, need);
+    const uint64_t wgs = grid_for(insert_kernel<C, LPK, T>, lds, f.num_cus, f.shape[BBFC_OP_INSERT].wgs_per_cu, need);
     hipLaunchKernelGGL((insert_kernel<C, LPK, T>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s, make_kparams(f), keys, n,
                        n_units);
     return hipGetLastError();
@@ -213,7 +213,7 @@ hipError_t query_launch(const bbfc_filter &f, const uint64_t *keys, uint64_t n, 
 {
     const uint64_t n_units = (n + (uint64_t)T * kTile - 1) / ((uint64_t)T * kTile);
     const uint64_t need = (n_units + kWavesPerWG - 1) / kWavesPerWG;
-    const uint64_t wgs = grid_for(query_kernel<C, LPK, T, EARLY>, 0, f.num_cus, f.wgs_per_cu, need);
+    const uint64_t wgs = grid_for(query_kernel<C, LPK, T, EARLY>, 0, f.num_cus, f.shape[BBFC_OP_QUERY].wgs_per_cu, need);
     hipLaunchKernelGGL((query_kernel<C, LPK, T, EARLY>), dim3((uint32_t)wgs), dim3(kWGSize), 0, s, make_kparams(f),
                        keys, n, out, n_units);
     return hipGetLastError();
@@ -229,10 +229,10 @@ template <int C>
 hipError_t insert_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
     // two tiles per wave only where their LDS and the rank table fit a workgroup
-    int tpw = f.tiles_per_wave;
+    int tpw = f.shape[BBFC_OP_INSERT].tiles_per_wave;
     if (tpw == 2 && insert_static_lds(C, 2) + rank_lds_bytes(f.c, f.k) > f.max_lds)
         tpw = 1;
-    return with_shape(f.lanes_per_key, tpw, [&](auto L, auto T) {
+    return with_shape(f.shape[BBFC_OP_INSERT].lanes_per_key, tpw, [&](auto L, auto T) {
         return insert_launch<C, decltype(L)::value, decltype(T)::value>(f, keys, n, s);
     });
 }
@@ -240,7 +240,8 @@ hipError_t insert_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipS
 template <int C>
 hipError_t query_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
 {
-    return with_shape(f.lanes_per_key, f.tiles_per_wave, [&](auto L, auto T) {
+    const bbfc_launch_shape &sh = f.shape[BBFC_OP_QUERY];
+    return with_shape(sh.lanes_per_key, sh.tiles_per_wave, [&](auto L, auto T) {
         if constexpr (C > 1) {
             if (f.query_early_exit)
                 return query_launch<C, decltype(L)::value, decltype(T)::value, true>(f, keys, n, out, s);

@@ -246,6 +246,48 @@ def test_stream_ordering_on_side_stream(dev):
         gpu.close()
 
 
+@pytest.mark.parametrize("op", [bbfc.OP_QUERY, bbfc.OP_INSERT])
+def test_single_filter_tuner(dev, op):
+    ref, gpu = make_pair(1 << 14, 2, 11, "la", seed=9)
+    try:
+        keys = workload.positive_keys(9, 1 << 18)
+        ref.insert(keys)
+        gpu.upload(ref.words)
+        probe = np.concatenate([keys, workload.negative_keys(9, 1 << 18, 1 << 18)])
+        pd = to_dev(probe, dev)
+        out = torch.empty((len(probe) + 63) // 64, dtype=torch.int64, device=dev)
+        best = gpu.tune(op, pd if op == bbfc.OP_QUERY else to_dev(keys, dev), out=out, reps=1)
+        assert best["lanes_per_key"] in (4, 8) and best["tiles_per_wave"] in (1, 2) and best["ms"] > 0
+        assert gpu.get_shape(op)["lanes_per_key"] == best["lanes_per_key"]
+        assert gpu.get_shape(op)["tiles_per_wave"] == best["tiles_per_wave"]
+        other = bbfc.OP_INSERT if op == bbfc.OP_QUERY else bbfc.OP_QUERY
+        assert gpu.get_shape(other)["lanes_per_key"] == 8 and gpu.get_shape(other)["tiles_per_wave"] == 1
+        assert np.array_equal(gpu.download(), ref.words), "tuning changed the filter"
+        assert np.array_equal(from_dev(gpu.query(pd)), ref.query_bits(probe))
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("lpk,tpw", [(8, 1), (8, 2), (4, 1), (4, 2)])
+def test_query_and_deterministic_parity_in_every_shape(dev, lpk, tpw):
+    for M, c, k, cost, n in SMALL_CONFIGS[:6]:
+        ref, gpu = make_pair(M, c, k, cost, seed=M + lpk + tpw)
+        try:
+            gpu.set_shape(bbfc.OP_QUERY, lpk, tpw)
+            gpu.set_shape(bbfc.OP_INSERT, lpk, tpw)
+            keys = workload.positive_keys(M + 3, n)
+            ref.insert(keys)
+            gpu.upload(ref.words)
+            probe = np.concatenate([keys, workload.negative_keys(M + 3, n, n + 77)])
+            assert np.array_equal(from_dev(gpu.query(to_dev(probe, dev))), ref.query_bits(probe))
+            if c == 1:
+                gpu.clear()
+                gpu.insert(to_dev(keys, dev))
+                assert np.array_equal(gpu.download(), ref.words)
+        finally:
+            gpu.close()
+
+
 def test_option_validation(dev):
     gpu = bbfc.Filter(64, 2, 8, "la", seed=1)
     try:
