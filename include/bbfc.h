@@ -49,7 +49,8 @@ typedef enum {
     BBFC_EINVAL = -1,      /* bad argument; nothing was enqueued             */
     BBFC_ENOMEM = -2,      /* device allocation failed                       */
     BBFC_EHIP = -3,        /* a HIP runtime call or kernel launch failed     */
-    BBFC_EUNSUPPORTED = -4 /* valid request this build does not implement    */
+    BBFC_EUNSUPPORTED = -4, /* valid request this build does not implement   */
+    BBFC_EBUSY = -5         /* not now: admission full or not finished yet    */
 } bbfc_status;
 
 /* Cost functions for block selection (App. A; Section 3.2):
@@ -304,6 +305,71 @@ bbfc_status bbfc_graph_create(bbfc_batch_handle insert_plan, const uint64_t *d_i
 bbfc_status bbfc_graph_launch(bbfc_graph_handle g, hipStream_t stream);
 /* Synchronises the device, then frees the graph and its tables. */
 bbfc_status bbfc_graph_destroy(bbfc_graph_handle g);
+
+/* ------------------------------------------------------------------ */
+/* Serving: query requests of mixed sizes from host memory, continuously  */
+/* batched against one resident filter.                                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct bbfc_server *bbfc_server_handle;
+
+/* n_slots: batches that may be in flight at once, each on its own stream
+ *     (1..16); max_batch_keys: keys one batch stages (a multiple of 64,
+ *     64..2^30; pinned host and device memory of 8 bytes per key plus
+ *     answers is allocated per slot); max_pending_keys: admission limit on
+ *     keys submitted but not yet staged (a request is still admitted when
+ *     nothing is pending, whatever its size); poll_us: scheduler poll period
+ *     while batches are in flight. Defaults (config == NULL): 4 slots,
+ *     2^20 keys per batch, 2^28 pending keys, 20 us. */
+typedef struct {
+    uint32_t n_slots;
+    uint64_t max_batch_keys;
+    uint64_t max_pending_keys;
+    uint32_t poll_us;
+} bbfc_server_config;
+
+/* Starts a scheduler thread serving queries on `filter`. Requests that
+ * arrive while others are in flight are admitted into the next batch as
+ * slots and memory free up: the oldest pending work fills a free slot's
+ * batch (each request's part starts on a 64-key boundary; a request larger
+ * than the room left continues in the next batch), and every batch is one
+ * key upload, one query launch (the filter's query shape) and one answer
+ * download on its slot's stream. Answers are those of bbfc_query on the
+ * same keys, whatever the mix. The filter must outlive the server;
+ * inserting into it while serving is allowed (queries see some subset of
+ * the in-flight inserts). Errors: EINVAL, EHIP. */
+bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *config, bbfc_server_handle *out);
+
+/* Waits for the admitted requests, stops the thread and frees the server. */
+bbfc_status bbfc_server_destroy(bbfc_server_handle s);
+
+/* Submits a query of h_keys[0..n) (host memory). On completion
+ * ceil(n/64) words of h_out_bits (host memory) hold the packed answers, as
+ * bbfc_query writes them. Both buffers must stay valid until the request
+ * is waited for. Thread-safe. Errors: EINVAL, EBUSY (admission: the
+ * pending keys would exceed max_pending_keys; retry later), EHIP (an
+ * earlier device error stopped the server). */
+bbfc_status bbfc_server_submit(bbfc_server_handle s, const uint64_t *h_keys, uint64_t n, uint64_t *h_out_bits,
+                               uint64_t *ticket);
+
+/* Waits for a request (timeout_s < 0: no limit) and forgets its ticket
+ * (wait once per ticket). *latency_us (may be null) receives the time from
+ * submission to answers in the caller's buffer. Errors: EINVAL (unknown
+ * ticket), EBUSY (timed out; the ticket stays valid), EHIP. */
+bbfc_status bbfc_server_wait(bbfc_server_handle s, uint64_t ticket, double timeout_s, double *latency_us);
+
+/* Batches launched, keys staged in them (with padding) and requests done. */
+bbfc_status bbfc_server_stats(bbfc_server_handle s, uint64_t *batches, uint64_t *batched_keys, uint64_t *completed);
+
+/* Measurement driver: submits request i = keys h_keys[req_offsets[i] ..
+ * req_offsets[i+1]) at arrival_s[i] seconds after the call (non-decreasing;
+ * busy-waits to each arrival; retries when admission is full), its answers
+ * to h_out_bits + out_offsets[i], then waits for all. latency_us[i] counts
+ * from the scheduled arrival, so admission waits are included. *wall_s (may
+ * be null) receives the time from the start to the last answer. */
+bbfc_status bbfc_server_replay(bbfc_server_handle s, const uint64_t *h_keys, const uint64_t *req_offsets,
+                               uint32_t n_requests, const double *arrival_s, uint64_t *h_out_bits,
+                               const uint64_t *out_offsets, double *latency_us, double *wall_s);
 
 /* ------------------------------------------------------------------ */
 /* Measurement hooks: the kernels that calibrate the roofline. They do   */

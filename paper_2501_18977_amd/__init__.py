@@ -24,6 +24,7 @@ __all__ = [
     "Filter",
     "Batch",
     "Graph",
+    "Server",
     "blocks_for",
     "rank_table",
     "host_block_hash",
@@ -53,6 +54,11 @@ class BBFCError(RuntimeError):
 
 class _Cost(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("param", ctypes.c_double)]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("n_slots", ctypes.c_uint32), ("max_batch_keys", ctypes.c_uint64),
+                ("max_pending_keys", ctypes.c_uint64), ("poll_us", ctypes.c_uint32)]
 
 
 class _Shape(ctypes.Structure):
@@ -118,6 +124,12 @@ def lib() -> ctypes.CDLL:
         "bbfc_graph_create": (_st, [_vp, _vp, _vp, _vp, _vp, _vp]),
         "bbfc_graph_launch": (_st, [_vp, _vp]),
         "bbfc_graph_destroy": (_st, [_vp]),
+        "bbfc_server_create": (_st, [_vp, _vp, _vp]),
+        "bbfc_server_destroy": (_st, [_vp]),
+        "bbfc_server_submit": (_st, [_vp, _vp, _u64, _vp, _vp]),
+        "bbfc_server_wait": (_st, [_vp, _u64, ctypes.c_double, _vp]),
+        "bbfc_server_stats": (_st, [_vp, _vp, _vp, _vp]),
+        "bbfc_server_replay": (_st, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
         "bbfc_host_block_hash": (_u64, [_u64, _u64, _u64]),
         "bbfc_host_bit_hash": (_u32, [_u64, _u64]),
     }
@@ -440,6 +452,73 @@ class Graph:
     def close(self) -> None:
         if self._h is not None:
             _check(lib().bbfc_graph_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching query server over one resident filter; requests
+    are numpy uint64 key arrays in host memory."""
+
+    def __init__(self, filt: Filter, n_slots: int = 4, max_batch_keys: int = 1 << 20,
+                 max_pending_keys: int = 1 << 28, poll_us: int = 20):
+        self._filter = filt
+        cfg = _ServerConfig(n_slots, max_batch_keys, max_pending_keys, poll_us)
+        h = ctypes.c_void_p()
+        _check(lib().bbfc_server_create(filt.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._live = {}  # ticket -> (keys, out) kept alive until waited for
+
+    def submit(self, keys) -> int:
+        import numpy as np
+
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        out = np.zeros(max(1, (len(keys) + 63) // 64), dtype=np.uint64)
+        t = ctypes.c_uint64()
+        _check(lib().bbfc_server_submit(self._h, keys.ctypes.data, len(keys), out.ctypes.data, ctypes.byref(t)))
+        self._live[t.value] = (keys, out)
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        """(packed answer words, latency in microseconds)."""
+        lat = ctypes.c_double()
+        _check(lib().bbfc_server_wait(self._h, ticket, timeout_s, ctypes.byref(lat)))
+        keys, out = self._live.pop(ticket)
+        return out[: (len(keys) + 63) // 64], lat.value
+
+    def stats(self) -> dict:
+        b, k, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().bbfc_server_stats(self._h, ctypes.byref(b), ctypes.byref(k), ctypes.byref(c)))
+        return {"batches": b.value, "batched_keys": k.value, "completed": c.value}
+
+    def replay(self, keys, req_offsets, arrival_s):
+        """Submit request i (keys[req_offsets[i]:req_offsets[i+1]]) at
+        arrival_s[i]; returns (answers per request, latencies in us, wall s)."""
+        import numpy as np
+
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        ro = np.ascontiguousarray(req_offsets, dtype=np.uint64)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        nreq = len(ro) - 1
+        words = (np.diff(ro) + 63) // 64
+        oo = np.zeros(nreq + 1, dtype=np.uint64)
+        oo[1:] = np.cumsum(words)
+        out = np.zeros(max(1, int(oo[-1])), dtype=np.uint64)
+        lat = np.zeros(nreq, dtype=np.float64)
+        wall = ctypes.c_double()
+        _check(lib().bbfc_server_replay(self._h, keys.ctypes.data, ro.ctypes.data, nreq, arr.ctypes.data,
+                                        out.ctypes.data, oo.ctypes.data, lat.ctypes.data, ctypes.byref(wall)))
+        answers = [out[int(oo[i]):int(oo[i + 1])] for i in range(nreq)]
+        return answers, lat, wall.value
+
+    def close(self) -> None:
+        if self._h is not None:
+            _check(lib().bbfc_server_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -585,6 +585,8 @@ const char *bbfc_status_string(bbfc_status s)
         return "HIP runtime error";
     case BBFC_EUNSUPPORTED:
         return "unsupported";
+    case BBFC_EBUSY:
+        return "busy";
     default:
         return "unknown status";
     }

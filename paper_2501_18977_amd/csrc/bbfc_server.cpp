@@ -1,0 +1,448 @@
+// Query serving with continuous batching over one resident filter.
+//
+// Clients submit requests (host keys, host answer buffer). A scheduler
+// thread keeps a FIFO of admitted requests and a fixed set of slots, each
+// with its own stream and pinned and device staging of max_batch_keys keys.
+// Whenever a slot is free it packs the oldest pending work into one fused
+// batch (each request's piece starts on a 64-key boundary, so its answer
+// words can be copied out whole; a request larger than what is left of the
+// slot continues in the next batch), and enqueues key upload, one query
+// launch and answer download on the slot's stream. Batches of different
+// slots overlap on the device. Completed batches (polled with events) hand
+// their answer words back to their requests; a request is done when all its
+// pieces are. Admission is by memory: at most max_pending_keys keys are
+// queued (submit answers BBFC_EBUSY beyond that), and a batch never holds
+// more than a slot's staging.
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include <hip/hip_runtime.h>
+
+#include "bbfc_common.hpp"
+#include "bbfc_internal.hpp"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    uint64_t ticket = 0;
+    const uint64_t *keys = nullptr;
+    uint64_t n = 0;
+    uint64_t *out = nullptr;
+    uint64_t next = 0;        // first key not yet placed in a batch
+    uint64_t answered = 0;    // keys whose answers are back
+    Clock::time_point t_submit;
+    Clock::time_point t_done;
+    bool done = false;
+};
+
+struct Piece {
+    std::shared_ptr<Request> req;
+    uint64_t key_off; // first key of the piece within the request (multiple of 64)
+    uint64_t n;
+    uint64_t word_off; // first answer word of the piece in the slot's staging
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    uint64_t *h_keys = nullptr; // pinned
+    uint64_t *h_out = nullptr;  // pinned
+    uint64_t *d_keys = nullptr;
+    uint64_t *d_out = nullptr;
+    hipEvent_t done = nullptr;
+    std::vector<Piece> pieces;
+    bool busy = false;
+};
+
+} // namespace
+
+struct bbfc_server {
+    bbfc_handle filter = nullptr;
+    bbfc_server_config cfg{};
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv_work; // scheduler: new requests or stop
+    std::condition_variable cv_done; // waiters: a request finished
+    std::deque<std::shared_ptr<Request>> pending;
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> by_ticket;
+    uint64_t next_ticket = 1;
+    uint64_t pending_keys = 0;
+    bool stop = false;
+    std::thread worker;
+    hipError_t error = hipSuccess;
+    // statistics
+    uint64_t batches = 0;
+    uint64_t batched_keys = 0;
+    uint64_t completed = 0;
+};
+
+namespace {
+
+// Takes the oldest pending work for a free slot (bookkeeping only). Called
+// with the lock held; returns the number of staged keys (0: nothing to do).
+uint64_t plan_slot(bbfc_server &s, Slot &slot)
+{
+    uint64_t used = 0;
+    const uint64_t cap = s.cfg.max_batch_keys;
+    slot.pieces.clear();
+    while (!s.pending.empty() && used < cap) {
+        std::shared_ptr<Request> r = s.pending.front();
+        const uint64_t room = cap - used;
+        const uint64_t left = r->n - r->next;
+        uint64_t take = std::min(left, room);
+        if (take < left)
+            take -= take % 64; // a continued request resumes on a 64-key boundary
+        if (take == 0)
+            break;
+        slot.pieces.push_back(Piece{r, r->next, take, used / 64});
+        r->next += take;
+        used += (take + 63) / 64 * 64;
+        if (r->next == r->n) {
+            s.pending.pop_front();
+            s.pending_keys -= r->n;
+        }
+    }
+    return used;
+}
+
+// Stages a planned slot's keys and enqueues upload, query and download.
+// Runs without the lock: only the scheduler touches slots, and the clients
+// keep their key buffers valid until their requests are done.
+hipError_t launch_slot(bbfc_server &s, Slot &slot, uint64_t used)
+{
+    for (const Piece &p : slot.pieces) {
+        memcpy(slot.h_keys + p.word_off * 64, p.req->keys + p.key_off, p.n * sizeof(uint64_t));
+        const uint64_t padded = (p.n + 63) / 64 * 64;
+        if (padded > p.n)
+            memset(slot.h_keys + p.word_off * 64 + p.n, 0, (padded - p.n) * sizeof(uint64_t));
+    }
+    hipError_t e = hipMemcpyAsync(slot.d_keys, slot.h_keys, used * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                  slot.stream);
+    if (e == hipSuccess)
+        e = bbfc::launch_query(*s.filter, slot.d_keys, used, slot.d_out, slot.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(slot.h_out, slot.d_out, used / 64 * sizeof(uint64_t), hipMemcpyDeviceToHost, slot.stream);
+    if (e == hipSuccess)
+        e = hipEventRecord(slot.done, slot.stream);
+    return e;
+}
+
+// Copies a finished slot's answers into its requests' buffers (no lock).
+void copy_answers(Slot &slot)
+{
+    for (const Piece &p : slot.pieces) {
+        const uint64_t words = (p.n + 63) / 64;
+        memcpy(p.req->out + p.key_off / 64, slot.h_out + p.word_off, words * sizeof(uint64_t));
+        if (p.n % 64) // the request's last word: keep only its own answers
+            p.req->out[p.key_off / 64 + words - 1] &= (1ull << (p.n % 64)) - 1;
+    }
+}
+
+// Marks answered pieces and finished requests. Called with the lock held.
+void finish_slot(bbfc_server &s, Slot &slot, Clock::time_point now)
+{
+    for (Piece &p : slot.pieces) {
+        p.req->answered += p.n;
+        if (p.req->answered == p.req->n) {
+            p.req->done = true;
+            p.req->t_done = now;
+            s.completed++;
+        }
+    }
+    slot.pieces.clear();
+    slot.busy = false;
+}
+
+void scheduler(bbfc_server *sp)
+{
+    bbfc_server &s = *sp;
+    bbfc::DeviceGuard guard(s.filter->device);
+    std::vector<Slot *> finished, planned;
+    std::vector<uint64_t> planned_keys;
+    std::unique_lock<std::mutex> lk(s.mu);
+    for (;;) {
+        // 1. batches whose answers are back
+        finished.clear();
+        for (Slot &slot : s.slots) {
+            if (!slot.busy)
+                continue;
+            const hipError_t q = hipEventQuery(slot.done);
+            if (q == hipSuccess) {
+                finished.push_back(&slot);
+            } else if (q != hipErrorNotReady) {
+                s.error = q;
+                finished.push_back(&slot);
+            }
+        }
+        if (!finished.empty()) {
+            lk.unlock();
+            for (Slot *slot : finished)
+                copy_answers(*slot);
+            const Clock::time_point now = Clock::now();
+            lk.lock();
+            for (Slot *slot : finished)
+                finish_slot(s, *slot, now);
+            s.cv_done.notify_all();
+        }
+        // 2. new batches for free slots
+        planned.clear();
+        planned_keys.clear();
+        for (Slot &slot : s.slots) {
+            if (slot.busy || s.pending.empty())
+                continue;
+            const uint64_t used = plan_slot(s, slot);
+            if (used) {
+                slot.busy = true;
+                planned.push_back(&slot);
+                planned_keys.push_back(used);
+            }
+        }
+        if (!planned.empty()) {
+            lk.unlock();
+            hipError_t err = hipSuccess;
+            for (size_t i = 0; i < planned.size(); ++i) {
+                const hipError_t e = launch_slot(s, *planned[i], planned_keys[i]);
+                if (e != hipSuccess && err == hipSuccess)
+                    err = e;
+            }
+            lk.lock();
+            for (size_t i = 0; i < planned.size(); ++i) {
+                s.batches++;
+                s.batched_keys += planned_keys[i];
+            }
+            if (err != hipSuccess) {
+                s.error = err;
+                s.cv_done.notify_all();
+            }
+        }
+        bool any_busy = false;
+        for (const Slot &slot : s.slots)
+            any_busy |= slot.busy;
+        if (s.stop && s.pending.empty() && !any_busy)
+            break;
+        if (any_busy) {
+            // poll the device; clients submit meanwhile
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(s.cfg.poll_us));
+            lk.lock();
+        } else if (s.pending.empty() && !s.stop) {
+            s.cv_work.wait(lk);
+        }
+    }
+}
+
+bbfc_status submit_at(bbfc_server_handle s, const uint64_t *h_keys, uint64_t n, uint64_t *h_out_bits,
+                      uint64_t *ticket, Clock::time_point t_arrival)
+{
+    if (s == nullptr || ticket == nullptr || (n > 0 && (h_keys == nullptr || h_out_bits == nullptr)))
+        return bbfc::fail(BBFC_EINVAL, "null server, ticket, keys or output");
+    auto r = std::make_shared<Request>();
+    r->keys = h_keys;
+    r->n = n;
+    r->out = h_out_bits;
+    r->t_submit = t_arrival;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop)
+            return bbfc::fail(BBFC_EINVAL, "server is stopping");
+        if (s->error != hipSuccess)
+            return bbfc::hip_fail(s->error, "server failed earlier");
+        if (n > 0 && s->pending_keys + n > s->cfg.max_pending_keys && !s->pending.empty())
+            return bbfc::fail(BBFC_EBUSY, "admission: %llu keys already pending",
+                              (unsigned long long)s->pending_keys);
+        r->ticket = s->next_ticket++;
+        s->by_ticket[r->ticket] = r;
+        if (n == 0) {
+            r->done = true;
+            r->t_done = r->t_submit;
+            s->completed++;
+        } else {
+            s->pending.push_back(r);
+            s->pending_keys += n;
+        }
+        *ticket = r->ticket;
+    }
+    s->cv_work.notify_one();
+    return BBFC_OK;
+}
+
+} // namespace
+
+using bbfc::fail;
+using bbfc::hip_fail;
+
+extern "C" {
+
+bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *config, bbfc_server_handle *out)
+{
+    if (filter == nullptr || out == nullptr)
+        return fail(BBFC_EINVAL, "null filter or output handle");
+    bbfc_server_config cfg{4, 1u << 20, 1ull << 28, 20};  // defaults
+    if (config)
+        cfg = *config;
+    if (cfg.n_slots < 1 || cfg.n_slots > 16)
+        return fail(BBFC_EINVAL, "n_slots must be in [1, 16]");
+    if (cfg.max_batch_keys < 64 || cfg.max_batch_keys % 64 || cfg.max_batch_keys > (1ull << 30))
+        return fail(BBFC_EINVAL, "max_batch_keys must be a multiple of 64 in [64, 2^30]");
+    if (cfg.max_pending_keys < 1)
+        return fail(BBFC_EINVAL, "max_pending_keys must be >= 1");
+    if (cfg.poll_us > 100000)
+        return fail(BBFC_EINVAL, "poll_us must be <= 100000");
+    auto *s = new bbfc_server();
+    s->filter = filter;
+    s->cfg = cfg;
+    s->slots.resize(cfg.n_slots);
+    bbfc::DeviceGuard guard(filter->device);
+    hipError_t e = hipSuccess;
+    for (Slot &slot : s->slots) {
+        const size_t kb = cfg.max_batch_keys * sizeof(uint64_t);
+        const size_t ob = cfg.max_batch_keys / 64 * sizeof(uint64_t);
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&slot.h_keys, kb, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&slot.h_out, ob, hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipMalloc(&slot.d_keys, kb);
+        if (e == hipSuccess)
+            e = hipMalloc(&slot.d_out, ob);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
+        bbfc_server_destroy(s);
+        return hip_fail(e, "allocating server slots");
+    }
+    s->worker = std::thread(scheduler, s);
+    *out = s;
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_server_destroy(bbfc_server_handle s)
+{
+    if (s == nullptr)
+        return fail(BBFC_EINVAL, "null server");
+    if (s->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+        }
+        s->cv_work.notify_all();
+        s->worker.join();
+    }
+    bbfc::DeviceGuard guard(s->filter->device);
+    for (Slot &slot : s->slots) {
+        if (slot.stream)
+            (void)hipStreamSynchronize(slot.stream);
+        if (slot.done)
+            (void)hipEventDestroy(slot.done);
+        if (slot.d_keys)
+            (void)hipFree(slot.d_keys);
+        if (slot.d_out)
+            (void)hipFree(slot.d_out);
+        if (slot.h_keys)
+            (void)hipHostFree(slot.h_keys);
+        if (slot.h_out)
+            (void)hipHostFree(slot.h_out);
+        if (slot.stream)
+            (void)hipStreamDestroy(slot.stream);
+    }
+    delete s;
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_server_submit(bbfc_server_handle s, const uint64_t *h_keys, uint64_t n, uint64_t *h_out_bits,
+                               uint64_t *ticket)
+{
+    return submit_at(s, h_keys, n, h_out_bits, ticket, Clock::now());
+}
+
+bbfc_status bbfc_server_wait(bbfc_server_handle s, uint64_t ticket, double timeout_s, double *latency_us)
+{
+    if (s == nullptr)
+        return fail(BBFC_EINVAL, "null server");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->by_ticket.find(ticket);
+    if (it == s->by_ticket.end())
+        return fail(BBFC_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    std::shared_ptr<Request> r = it->second;
+    const auto pred = [&] { return r->done || s->error != hipSuccess; };
+    if (timeout_s < 0) {
+        s->cv_done.wait(lk, pred);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) {
+        return fail(BBFC_EBUSY, "request %llu not done yet", (unsigned long long)ticket);
+    }
+    if (!r->done)
+        return hip_fail(s->error, "serving");
+    if (latency_us)
+        *latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+    s->by_ticket.erase(it);
+    return s->error == hipSuccess ? BBFC_OK : hip_fail(s->error, "serving");
+}
+
+bbfc_status bbfc_server_stats(bbfc_server_handle s, uint64_t *batches, uint64_t *batched_keys, uint64_t *completed)
+{
+    if (s == nullptr)
+        return fail(BBFC_EINVAL, "null server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (batches)
+        *batches = s->batches;
+    if (batched_keys)
+        *batched_keys = s->batched_keys;
+    if (completed)
+        *completed = s->completed;
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_server_replay(bbfc_server_handle s, const uint64_t *h_keys, const uint64_t *req_offsets,
+                               uint32_t n_requests, const double *arrival_s, uint64_t *h_out_bits,
+                               const uint64_t *out_offsets, double *latency_us, double *wall_s)
+{
+    if (s == nullptr || h_keys == nullptr || req_offsets == nullptr || arrival_s == nullptr ||
+        h_out_bits == nullptr || out_offsets == nullptr || latency_us == nullptr)
+        return fail(BBFC_EINVAL, "null argument");
+    for (uint32_t i = 0; i + 1 < n_requests; ++i)
+        if (arrival_s[i + 1] < arrival_s[i])
+            return fail(BBFC_EINVAL, "arrival times must be non-decreasing");
+    std::vector<uint64_t> tickets(n_requests, 0);
+    const Clock::time_point t0 = Clock::now();
+    for (uint32_t i = 0; i < n_requests; ++i) {
+        const Clock::time_point due = t0 + std::chrono::duration_cast<Clock::duration>(
+                                               std::chrono::duration<double>(arrival_s[i]));
+        while (Clock::now() < due) {
+        }
+        for (;;) {
+            // latency counts from the scheduled arrival, also while admission waits
+            const bbfc_status st = submit_at(s, h_keys + req_offsets[i], req_offsets[i + 1] - req_offsets[i],
+                                             h_out_bits + out_offsets[i], &tickets[i], due);
+            if (st == BBFC_OK)
+                break;
+            if (st != BBFC_EBUSY)
+                return st;
+            std::this_thread::sleep_for(std::chrono::microseconds(10)); // admission: retry when memory frees
+        }
+    }
+    for (uint32_t i = 0; i < n_requests; ++i) {
+        const bbfc_status st = bbfc_server_wait(s, tickets[i], -1.0, &latency_us[i]);
+        if (st != BBFC_OK)
+            return st;
+    }
+    if (wall_s)
+        *wall_s = std::chrono::duration<double>(Clock::now() - t0).count();
+    return BBFC_OK;
+}
+
+} // extern "C"

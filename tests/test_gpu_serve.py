@@ -1,0 +1,144 @@
+"""Continuous-batching query server (GPU only).
+
+Every request's answers must be the same when it is served alone, when it
+is served in a mix with many other requests (packed into shared batches,
+split across batches, overlapping on several streams), and when the
+oracle answers the same keys.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2501_18977_amd as bbfc
+import workload
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+@pytest.fixture(scope="module")
+def served(dev):
+    """An oracle-built filter uploaded to the device, and its keys."""
+    M, c, k = 1 << 14, 2, 11
+    bm = workload.draw_multipliers(5, c, coprime_to=M)
+    am = workload.draw_multipliers(6, k)
+    ref = oracle.OracleFilter(M, c, k, oracle.COST_LA, None, bm, am)
+    n = 1 << 18
+    keys = workload.positive_keys(5, n)
+    ref.insert(keys)
+    f = bbfc.Filter(M, c, k, "la", block_mult=bm, bit_mult=am)
+    f.upload(ref.words)
+    yield ref, f, keys
+    f.close()
+
+
+SIZES = [1, 2, 63, 64, 65, 127, 1000, 4096, 5000, 70_000, 3, 200_000, 17, 64 * 7, 9999]
+
+
+def make_requests(keys, sizes, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i, s in enumerate(sizes):
+        pos = keys[rng.integers(0, len(keys), size=(s + 1) // 2)]
+        neg = workload.negative_keys(5, len(keys) + 1000 * i, s // 2)
+        r = np.concatenate([pos, neg])
+        rng.shuffle(r)
+        reqs.append(r)
+    return reqs
+
+
+def test_results_same_alone_in_mix_and_oracle(served):
+    ref, f, keys = served
+    reqs = make_requests(keys, SIZES, 1)
+    srv = bbfc.Server(f, n_slots=3, max_batch_keys=1 << 16)
+    try:
+        alone = []
+        for r in reqs:
+            t = srv.submit(r)
+            ans, lat = srv.wait(t)
+            assert lat > 0
+            alone.append(ans.copy())
+        b_alone = srv.stats()["batches"]
+        tickets = [srv.submit(r) for r in reqs]  # all in flight together
+        mixed = [srv.wait(t)[0].copy() for t in tickets]
+        b_mixed = srv.stats()["batches"] - b_alone
+    finally:
+        srv.close()
+    for r, a, m in zip(reqs, alone, mixed):
+        want = ref.query_bits(r)
+        assert np.array_equal(a, want)
+        assert np.array_equal(m, want)
+    # in the mix, requests shared batches
+    assert b_mixed < b_alone
+
+
+def test_large_requests_split_across_small_batches(served):
+    ref, f, keys = served
+    reqs = make_requests(keys, [100_000, 3, 50_001, 64], 2)
+    srv = bbfc.Server(f, n_slots=2, max_batch_keys=4096)
+    try:
+        tickets = [srv.submit(r) for r in reqs]
+        got = [srv.wait(t)[0].copy() for t in tickets]
+        assert srv.stats()["batches"] >= 100_000 // 4096
+    finally:
+        srv.close()
+    for r, g in zip(reqs, got):
+        assert np.array_equal(g, ref.query_bits(r))
+
+
+def test_zero_length_request(served):
+    _, f, _ = served
+    srv = bbfc.Server(f)
+    try:
+        t = srv.submit(np.zeros(0, dtype=np.uint64))
+        ans, lat = srv.wait(t)
+        assert len(ans) == 0 and lat >= 0
+    finally:
+        srv.close()
+
+
+def test_replay_under_tight_admission(served):
+    """A Poisson schedule replayed against a server that admits at most 5000
+    pending keys: requests wait for admission, all answers stay exact."""
+    ref, f, keys = served
+    sizes = [int(round(2 ** u)) for u in np.random.default_rng(3).uniform(0, 13, size=300)]
+    reqs = make_requests(keys, sizes, 3)
+    flat = np.concatenate(reqs)
+    offs = np.zeros(len(reqs) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(r) for r in reqs])
+    arrivals = np.cumsum(np.random.default_rng(4).exponential(20e-6, size=len(reqs)))
+    srv = bbfc.Server(f, n_slots=4, max_batch_keys=1 << 14, max_pending_keys=5000)
+    try:
+        answers, lat, wall = srv.replay(flat, offs, arrivals)
+    finally:
+        srv.close()
+    assert wall > 0 and np.all(lat > 0)
+    for r, a in zip(reqs, answers):
+        assert np.array_equal(a, ref.query_bits(r))
+
+
+def test_server_config_validation(served):
+    _, f, _ = served
+    for kw in ({"n_slots": 0}, {"n_slots": 17}, {"max_batch_keys": 100}, {"max_pending_keys": 0}):
+        with pytest.raises(bbfc.BBFCError):
+            bbfc.Server(f, **kw)
+
+
+def test_wait_unknown_ticket(served):
+    _, f, _ = served
+    srv = bbfc.Server(f)
+    try:
+        with pytest.raises(bbfc.BBFCError, match="unknown ticket"):
+            srv.wait(12345)
+    finally:
+        srv.close()

@@ -122,6 +122,26 @@ def batch_specs(seed: int, count: int, log2_lo: float = 10.0, log2_hi: float = 2
     return out
 
 
+def serve_requests(seed: int, count: int, n_pos: int, lo: int = 1, hi: int = 65536):
+    """A query-request mix: sizes log-uniform in [lo, hi]; each request
+    takes half its keys (rounded up) from the n_pos inserted keys (a
+    contiguous run of counters at a random start) and the rest from keys
+    never inserted (counters from n_pos on, one fresh run per request).
+    Returns (sizes, positive starts, negative starts)."""
+    rng = SplitMix64(seed)
+    sizes, pstart, nstart = [], [], []
+    nxt = n_pos
+    for _ in range(count):
+        u = math.log(lo) + (math.log(hi) - math.log(lo)) * ((rng.next() >> 11) / float(1 << 53))
+        s = max(lo, min(hi, int(round(math.exp(u)))))
+        npos = (s + 1) // 2
+        sizes.append(s)
+        pstart.append(rng.next() % max(1, n_pos - npos))
+        nstart.append(nxt)
+        nxt += s - npos
+    return sizes, pstart, nstart
+
+
 # ----------------------------------------------------- device-side generator
 
 import ctypes as _ctypes
