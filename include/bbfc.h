@@ -224,6 +224,43 @@ const char *bbfc_status_string(bbfc_status s);
 const char *bbfc_last_error(void);
 
 /* ------------------------------------------------------------------ */
+/* DNA q-grams (k-mers) as keys (Section 4.3: genomes and sequenced reads  */
+/* represented as sets of q-grams, usually 21 <= q <= 31).                */
+/* ------------------------------------------------------------------ */
+
+/* Sequences are 2-bit packed, A=0, C=1, G=2, T=3, 32 bases per 64-bit word,
+ * base i in bits 63-2(i mod 32) .. 62-2(i mod 32) of word i/32 (the earlier
+ * base in the higher bits). The sequence d_seq (device memory, at least
+ * ceil(n_segments*seg_len/32) words) is cut into n_segments segments of
+ * seg_len bases laid end to end (one genome: one segment; reads of one
+ * length: one segment per read). Every window of q consecutive bases
+ * inside a segment gives one key: its forward value (2q bits, first base
+ * most significant) or that of its reverse complement (bases complemented,
+ * b -> 3-b, and reversed), whichever is smaller (the canonical q-gram).
+ * Key t is the window at base s*seg_len + j, s = t / w, j = t mod w, with
+ * w = seg_len - q + 1 windows per segment (none if seg_len < q).
+ * 1 <= q <= 32. */
+
+/* Number of keys: n_segments * max(seg_len - q + 1, 0). */
+uint64_t bbfc_kmer_count(uint64_t n_segments, uint64_t seg_len, uint32_t q);
+
+/* Writes the bbfc_kmer_count keys to d_keys (device memory). Errors:
+ * EINVAL (null pointers with keys to write, q out of range, sequence
+ * longer than 2^62 bases), EHIP. */
+bbfc_status bbfc_kmer_keys(const uint64_t *d_seq, uint64_t n_segments, uint64_t seg_len, uint32_t q,
+                           uint64_t *d_keys, hipStream_t stream);
+
+/* bbfc_insert of the sequence's keys, computed inside the insert kernel
+ * from the packed bases (no key array is written). */
+bbfc_status bbfc_insert_kmers(bbfc_handle h, const uint64_t *d_seq, uint64_t n_segments, uint64_t seg_len, uint32_t q,
+                              hipStream_t stream);
+
+/* bbfc_query of the sequence's keys, computed inside the query kernel;
+ * the answer for key t is bit t mod 64 of d_out_bits[t/64]. */
+bbfc_status bbfc_query_kmers(bbfc_handle h, const uint64_t *d_seq, uint64_t n_segments, uint64_t seg_len, uint32_t q,
+                             uint64_t *d_out_bits, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
 /* Batches: many filters of uneven sizes built or queried in one          */
 /* persistent launch (insert and query as above, filter by filter).       */
 /* ------------------------------------------------------------------ */

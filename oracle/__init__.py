@@ -73,6 +73,8 @@ def _load():
     lib.bbo_block_loads.restype = None
     lib.bbo_conditional_fpr.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, u64]
     lib.bbo_conditional_fpr.restype = dbl
+    lib.bbo_qgrams.argtypes = [ctypes.c_void_p, u64, u64, u32, _u64p]
+    lib.bbo_qgrams.restype = u64
     _lib = lib
     return lib
 
@@ -103,6 +105,17 @@ def default_param(kind: int, k: int) -> float:
 
 def cost(kind: int, param: float, k: int, j: int, a: int) -> float:
     return float(_load().bbo_cost(kind, param, k, j, a))
+
+
+def qgrams(bases, n_segments: int, seg_len: int, q: int) -> np.ndarray:
+    """Canonical q-grams of a base sequence (uint8 values 0..3 = A, C, G, T)."""
+    b = np.ascontiguousarray(bases, dtype=np.uint8)
+    assert len(b) >= n_segments * seg_len
+    n = n_segments * max(0, seg_len - q + 1) if 1 <= q <= 32 else 0
+    out = np.zeros(max(1, n), dtype=np.uint64)
+    got = _load().bbo_qgrams(b.ctypes.data, n_segments, seg_len, q, _ptr(out))
+    assert got == n
+    return out[:n]
 
 
 def derive_multipliers(seed: int, M: int, c: int, k: int):

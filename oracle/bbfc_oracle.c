@@ -325,3 +325,31 @@ double bbo_conditional_fpr(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k
     }
     return n ? total / (double)n : 0.0;
 }
+
+/* ------------------------- DNA q-grams as keys ------------------------ */
+
+/* Canonical q-grams of a DNA sequence given one base per byte (A=0, C=1,
+ * G=2, T=3), cut into n_segments segments of seg_len bases (Section 4.3:
+ * genomes and reads represented by their q-grams). For every window of q
+ * bases inside a segment, in order, the forward value reads the bases as a
+ * base-4 number with the first base most significant; the reverse
+ * complement reads the complemented bases (b -> 3 - b) from the last to the
+ * first; the key is the smaller value. Returns the number of keys written. */
+uint64_t bbo_qgrams(const uint8_t *bases, uint64_t n_segments, uint64_t seg_len, uint32_t q, uint64_t *out)
+{
+    uint64_t t = 0;
+    if (q < 1 || q > 32 || seg_len < q)
+        return 0;
+    for (uint64_t s = 0; s < n_segments; s++) {
+        const uint8_t *seg = bases + s * seg_len;
+        for (uint64_t j = 0; j + q <= seg_len; j++) {
+            uint64_t fwd = 0, rc = 0;
+            for (uint32_t i = 0; i < q; i++)
+                fwd = fwd * 4 + seg[j + i];
+            for (uint32_t i = 0; i < q; i++)
+                rc = rc * 4 + (uint64_t)(3 - seg[j + q - 1 - i]);
+            out[t++] = fwd < rc ? fwd : rc;
+        }
+    }
+    return t;
+}

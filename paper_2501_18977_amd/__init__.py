@@ -28,6 +28,8 @@ __all__ = [
     "blocks_for",
     "rank_table",
     "host_block_hash",
+    "kmer_count",
+    "kmer_keys",
     "host_bit_hash",
     "lib",
     "library_path",
@@ -130,6 +132,10 @@ def lib() -> ctypes.CDLL:
         "bbfc_server_wait": (_st, [_vp, _u64, ctypes.c_double, _vp]),
         "bbfc_server_stats": (_st, [_vp, _vp, _vp, _vp]),
         "bbfc_server_replay": (_st, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
+        "bbfc_kmer_count": (_u64, [_u64, _u64, _u32]),
+        "bbfc_kmer_keys": (_st, [_vp, _u64, _u64, _u32, _vp, _vp]),
+        "bbfc_insert_kmers": (_st, [_vp, _vp, _u64, _u64, _u32, _vp]),
+        "bbfc_query_kmers": (_st, [_vp, _vp, _u64, _u64, _u32, _vp, _vp]),
         "bbfc_host_block_hash": (_u64, [_u64, _u64, _u64]),
         "bbfc_host_bit_hash": (_u32, [_u64, _u64]),
     }
@@ -183,6 +189,22 @@ def rank_table(cost, bits_per_key: int, param=None):
     out = np.empty((bits_per_key + 1) * 513, dtype=np.uint16)
     _check(lib().bbfc_rank_table(_cost_struct(cost, param), bits_per_key, out.ctypes.data))
     return out.reshape(bits_per_key + 1, 513)
+
+
+def kmer_count(n_segments: int, seg_len: int, q: int) -> int:
+    return int(lib().bbfc_kmer_count(n_segments, seg_len, q))
+
+
+def kmer_keys(seq, n_segments: int, seg_len: int, q: int = 31, out=None, stream=None):
+    """The canonical q-grams of a 2-bit packed sequence as an int64 GPU tensor."""
+    import torch
+
+    seq = _device_u64(seq, "seq")
+    n = kmer_count(n_segments, seg_len, q)
+    if out is None:
+        out = torch.empty(max(1, n), dtype=torch.int64, device=seq.device)
+    _check(lib().bbfc_kmer_keys(seq.data_ptr(), n_segments, seg_len, q, out.data_ptr(), _stream_handle(stream)))
+    return out[:n]
 
 
 def host_block_hash(n_blocks: int, a: int, x: int) -> int:
@@ -303,6 +325,23 @@ class Filter:
             if out.numel() < n_words:
                 raise ValueError("output too small")
         _check(lib().bbfc_query(self.handle, keys.data_ptr(), n, out.data_ptr(), _stream_handle(stream)))
+        return out
+
+    def insert_kmers(self, seq, n_segments: int, seg_len: int, q: int = 31, stream=None) -> None:
+        """Insert the canonical q-grams of a 2-bit packed sequence (int64/uint64
+        GPU tensor of words) cut into n_segments segments of seg_len bases."""
+        seq = _device_u64(seq, "seq")
+        _check(lib().bbfc_insert_kmers(self.handle, seq.data_ptr(), n_segments, seg_len, q, _stream_handle(stream)))
+
+    def query_kmers(self, seq, n_segments: int, seg_len: int, q: int = 31, out=None, stream=None):
+        import torch
+
+        seq = _device_u64(seq, "seq")
+        n = kmer_count(n_segments, seg_len, q)
+        if out is None:
+            out = torch.empty(max(1, (n + 63) // 64), dtype=torch.int64, device=seq.device)
+        _check(lib().bbfc_query_kmers(self.handle, seq.data_ptr(), n_segments, seg_len, q, out.data_ptr(),
+                                      _stream_handle(stream)))
         return out
 
     def clear(self, stream=None) -> None:

@@ -345,6 +345,70 @@ bbfc_status bbfc_query(bbfc_handle h, const uint64_t *d_keys, uint64_t n, uint64
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching query");
 }
 
+uint64_t bbfc_kmer_count(uint64_t n_segments, uint64_t seg_len, uint32_t q)
+{
+    if (q < 1 || q > 32 || seg_len < q)
+        return 0;
+    return n_segments * (seg_len - q + 1);
+}
+
+static bbfc_status check_seq(const uint64_t *d_seq, uint64_t n_segments, uint64_t seg_len, uint32_t q)
+{
+    if (q < 1 || q > 32)
+        return fail(BBFC_EINVAL, "q must be in [1, 32], got %u", q);
+    if (seg_len != 0 && n_segments > (1ull << 62) / seg_len)
+        return fail(BBFC_EINVAL, "sequence longer than 2^62 bases");
+    if (bbfc_kmer_count(n_segments, seg_len, q) > 0 && d_seq == nullptr)
+        return fail(BBFC_EINVAL, "null sequence");
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_kmer_keys(const uint64_t *d_seq, uint64_t n_segments, uint64_t seg_len, uint32_t q, uint64_t *d_keys,
+                           hipStream_t stream)
+{
+    bbfc_status st = check_seq(d_seq, n_segments, seg_len, q);
+    if (st != BBFC_OK)
+        return st;
+    if (bbfc_kmer_count(n_segments, seg_len, q) == 0)
+        return BBFC_OK;
+    if (d_keys == nullptr)
+        return fail(BBFC_EINVAL, "null key output");
+    hipError_t e = bbfc::launch_kmer_keys(d_seq, n_segments, seg_len, q, d_keys, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching q-gram extraction");
+}
+
+bbfc_status bbfc_insert_kmers(bbfc_handle h, const uint64_t *d_seq, uint64_t n_segments, uint64_t seg_len, uint32_t q,
+                              hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    bbfc_status st = check_seq(d_seq, n_segments, seg_len, q);
+    if (st != BBFC_OK)
+        return st;
+    if (bbfc_kmer_count(n_segments, seg_len, q) == 0)
+        return BBFC_OK;
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_insert_kmers(*h, d_seq, n_segments, seg_len, q, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching q-gram insert");
+}
+
+bbfc_status bbfc_query_kmers(bbfc_handle h, const uint64_t *d_seq, uint64_t n_segments, uint64_t seg_len, uint32_t q,
+                             uint64_t *d_out_bits, hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    bbfc_status st = check_seq(d_seq, n_segments, seg_len, q);
+    if (st != BBFC_OK)
+        return st;
+    if (bbfc_kmer_count(n_segments, seg_len, q) == 0)
+        return BBFC_OK;
+    if (d_out_bits == nullptr)
+        return fail(BBFC_EINVAL, "null output");
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_query_kmers(*h, d_seq, n_segments, seg_len, q, d_out_bits, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching q-gram query");
+}
+
 bbfc_status bbfc_clear(bbfc_handle h, hipStream_t stream)
 {
     if (h == nullptr)

@@ -87,8 +87,8 @@ __global__ __launch_bounds__(kWGSize) void batch_query_kernel(const BatchFilter 
             ++f;
         const BatchFilter &bf = filt[f];
         const uint64_t lu = u - bf.unit_off;
-        query_tiles<C, LPK, T, EARLY>(bf.p, keys + bf.key_off, bf.n, lu * T * kTile, out + bf.out_off + lu * T, lane,
-                                      s_mask[wv], s_blk[wv]);
+        query_tiles<C, LPK, T, EARLY>(bf.p, ArrayKeys{keys + bf.key_off}, bf.n, lu * T * kTile,
+                                      out + bf.out_off + lu * T, lane, s_mask[wv], s_blk[wv]);
     };
     if (grab == 0) {
         const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerWG;
@@ -129,8 +129,8 @@ __global__ __launch_bounds__(kWGSize) void batch_insert_kernel(const BatchFilter
         const BatchSlot sl = slots[s];
         const BatchFilter &bf = filt[sl.filter];
         for (uint64_t lu = sl.first_unit; lu < sl.units; lu += sl.stride)
-            insert_tiles<C, LPK, T>(bf.p, bf.p.rank, keys + bf.key_off, bf.n, lu * T * kTile, lane, s_mask[wv],
-                                    s_blk[wv]);
+            insert_tiles<C, LPK, T>(bf.p, bf.p.rank, ArrayKeys{keys + bf.key_off}, bf.n, lu * T * kTile, lane,
+                                    s_mask[wv], s_blk[wv]);
     }
 }
 

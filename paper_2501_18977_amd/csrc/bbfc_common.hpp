@@ -59,6 +59,12 @@ __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
 #endif
 }
 
+__host__ __device__ inline uint64_t fastdiv(uint64_t n, uint64_t magic, uint32_t sh1, uint32_t sh2)
+{
+    const uint64_t t = mulhi64(magic, n);
+    return (t + ((n - t) >> sh1)) >> sh2;
+}
+
 __host__ __device__ inline uint64_t fastmod(uint64_t n, uint64_t d, uint64_t magic, uint32_t sh1, uint32_t sh2)
 {
     uint64_t t = mulhi64(magic, n);

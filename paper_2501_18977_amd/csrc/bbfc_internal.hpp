@@ -64,6 +64,13 @@ hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, 
                         hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s);
 
+// Canonical q-grams of a 2-bit packed sequence cut into segments (see
+// bbfc_kmer_keys): fused insert and query, and the keys written out.
+hipError_t launch_insert_kmers(const bbfc_filter &f, const uint64_t *seq, uint64_t n_segments, uint64_t seg_len, uint32_t q, hipStream_t s);
+hipError_t launch_query_kmers(const bbfc_filter &f, const uint64_t *seq, uint64_t n_segments, uint64_t seg_len, uint32_t q, uint64_t *out, hipStream_t s);
+hipError_t launch_kmer_keys(const uint64_t *seq, uint64_t n_segments, uint64_t seg_len, uint32_t q, uint64_t *out,
+                            hipStream_t s);
+
 hipError_t launch_probe_gather(const uint64_t *buf, uint64_t n_lines64, uint32_t access_bytes, uint64_t n_access,
                                uint64_t seed, uint64_t *sink, hipStream_t s);
 hipError_t launch_probe_atomic64(uint64_t *buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,

@@ -29,9 +29,10 @@ __device__ inline void load_rank_table(const KParams &p, uint16_t *s_rank)
 }
 
 // Unit u = tiles u*T .. u*T+T-1; units are strided over the wavefronts.
-template <int C, int LPK, int T, bool EARLY>
-__global__ __launch_bounds__(kWGSize) void query_kernel(KParams p, const uint64_t *__restrict__ keys, uint64_t n,
-                                                        uint64_t *__restrict__ out, uint64_t n_units)
+// Src: where key t comes from (an array, or a k-mer of a packed sequence).
+template <int C, int LPK, int T, bool EARLY, typename Src>
+__global__ __launch_bounds__(kWGSize) void query_kernel(KParams p, Src keys, uint64_t n, uint64_t *__restrict__ out,
+                                                        uint64_t n_units)
 {
     __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
     __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
@@ -42,9 +43,8 @@ __global__ __launch_bounds__(kWGSize) void query_kernel(KParams p, const uint64_
         query_tiles<C, LPK, T, EARLY>(p, keys, n, u * T * kTile, out + u * T, lane, s_mask[wv], s_blk[wv]);
 }
 
-template <int C, int LPK, int T>
-__global__ __launch_bounds__(kWGSize) void insert_kernel(KParams p, const uint64_t *__restrict__ keys, uint64_t n,
-                                                         uint64_t n_units)
+template <int C, int LPK, int T, typename Src>
+__global__ __launch_bounds__(kWGSize) void insert_kernel(KParams p, Src keys, uint64_t n, uint64_t n_units)
 {
     __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
     __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kWave) void insert_det_kernel(KParams p, const uint
 
     for (uint64_t tile = 0; tile < n_tiles; ++tile) {
         const uint64_t base = tile * kTile;
-        phase_a<C>(p, keys, n, base, lane, smask, sblk);
+        phase_a<C>(p, ArrayKeys{keys}, n, base, lane, smask, sblk);
         wave_sync();
         const uint32_t in_tile = (uint32_t)((n - base) < (uint64_t)kTile ? (n - base) : (uint64_t)kTile);
         uint32_t pos = 0;
@@ -191,8 +191,8 @@ uint64_t grid_for(K kernel, size_t dyn_lds, int num_cus, int wgs_per_cu, uint64_
     return wgs < 1 ? 1 : wgs;
 }
 
-template <int C, int LPK, int T>
-hipError_t insert_launch(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+template <int C, int LPK, int T, typename Src>
+hipError_t insert_launch(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s)
 {
     const uint64_t n_units = (n + (uint64_t)T * kTile - 1) / ((uint64_t)T * kTile);
     const size_t lds = rank_lds_bytes(f.c, f.k);
@@ -202,19 +202,21 @@ hipError_t insert_launch(const bbfc_filter &f, const uint64_t *keys, uint64_t n,
     uint64_t need = (n_units + kWavesPerWG - 1) / kWavesPerWG;
     if (cap_wgs < need)
         need = cap_wgs;
-    const uint64_t wgs = grid_for(insert_kernel<C, LPK, T>, lds, f.num_cus, f.shape[BBFC_OP_INSERT].wgs_per_cu, need);
-    hipLaunchKernelGGL((insert_kernel<C, LPK, T>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s, make_kparams(f), keys, n,
-                       n_units);
+    const uint64_t wgs =
+        grid_for(insert_kernel<C, LPK, T, Src>, lds, f.num_cus, f.shape[BBFC_OP_INSERT].wgs_per_cu, need);
+    hipLaunchKernelGGL((insert_kernel<C, LPK, T, Src>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s, make_kparams(f),
+                       keys, n, n_units);
     return hipGetLastError();
 }
 
-template <int C, int LPK, int T, bool EARLY>
-hipError_t query_launch(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
+template <int C, int LPK, int T, bool EARLY, typename Src>
+hipError_t query_launch(const bbfc_filter &f, const Src &keys, uint64_t n, uint64_t *out, hipStream_t s)
 {
     const uint64_t n_units = (n + (uint64_t)T * kTile - 1) / ((uint64_t)T * kTile);
     const uint64_t need = (n_units + kWavesPerWG - 1) / kWavesPerWG;
-    const uint64_t wgs = grid_for(query_kernel<C, LPK, T, EARLY>, 0, f.num_cus, f.shape[BBFC_OP_QUERY].wgs_per_cu, need);
-    hipLaunchKernelGGL((query_kernel<C, LPK, T, EARLY>), dim3((uint32_t)wgs), dim3(kWGSize), 0, s, make_kparams(f),
+    const uint64_t wgs =
+        grid_for(query_kernel<C, LPK, T, EARLY, Src>, 0, f.num_cus, f.shape[BBFC_OP_QUERY].wgs_per_cu, need);
+    hipLaunchKernelGGL((query_kernel<C, LPK, T, EARLY, Src>), dim3((uint32_t)wgs), dim3(kWGSize), 0, s, make_kparams(f),
                        keys, n, out, n_units);
     return hipGetLastError();
 }
@@ -225,28 +227,28 @@ constexpr size_t insert_static_lds(int C, int T)
     return (size_t)kWavesPerWG * T * kTile * (kSlotDw * sizeof(uint32_t) + C * sizeof(uint64_t));
 }
 
-template <int C>
-hipError_t insert_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+template <int C, typename Src>
+hipError_t insert_c(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s)
 {
     // two tiles per wave only where their LDS and the rank table fit a workgroup
     int tpw = f.shape[BBFC_OP_INSERT].tiles_per_wave;
     if (tpw == 2 && insert_static_lds(C, 2) + rank_lds_bytes(f.c, f.k) > f.max_lds)
         tpw = 1;
     return with_shape(f.shape[BBFC_OP_INSERT].lanes_per_key, tpw, [&](auto L, auto T) {
-        return insert_launch<C, decltype(L)::value, decltype(T)::value>(f, keys, n, s);
+        return insert_launch<C, decltype(L)::value, decltype(T)::value, Src>(f, keys, n, s);
     });
 }
 
-template <int C>
-hipError_t query_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
+template <int C, typename Src>
+hipError_t query_c(const bbfc_filter &f, const Src &keys, uint64_t n, uint64_t *out, hipStream_t s)
 {
     const bbfc_launch_shape &sh = f.shape[BBFC_OP_QUERY];
     return with_shape(sh.lanes_per_key, sh.tiles_per_wave, [&](auto L, auto T) {
         if constexpr (C > 1) {
             if (f.query_early_exit)
-                return query_launch<C, decltype(L)::value, decltype(T)::value, true>(f, keys, n, out, s);
+                return query_launch<C, decltype(L)::value, decltype(T)::value, true, Src>(f, keys, n, out, s);
         }
-        return query_launch<C, decltype(L)::value, decltype(T)::value, false>(f, keys, n, out, s);
+        return query_launch<C, decltype(L)::value, decltype(T)::value, false, Src>(f, keys, n, out, s);
     });
 }
 
@@ -259,9 +261,8 @@ hipError_t insert_det_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, 
     return hipGetLastError();
 }
 
-} // namespace
-
-hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+template <typename Src>
+hipError_t insert_any(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s)
 {
     switch (f.c) {
     case 1:
@@ -275,6 +276,78 @@ hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n,
     default:
         return hipErrorInvalidValue;
     }
+}
+
+template <typename Src>
+hipError_t query_any(const bbfc_filter &f, const Src &keys, uint64_t n, uint64_t *out, hipStream_t s)
+{
+    switch (f.c) {
+    case 1:
+        return query_c<1>(f, keys, n, out, s);
+    case 2:
+        return query_c<2>(f, keys, n, out, s);
+    case 3:
+        return query_c<3>(f, keys, n, out, s);
+    case 4:
+        return query_c<4>(f, keys, n, out, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+// One thread per key: the canonical k-mers written out.
+__global__ void kmer_keys_kernel(KmerKeys src, uint64_t n, uint64_t *__restrict__ out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride)
+        out[t] = src.load(t);
+}
+
+KmerKeys make_kmer_src(const uint64_t *seq, uint64_t seg_len, uint32_t q)
+{
+    KmerKeys src{};
+    src.seq = seq;
+    src.seg_len = seg_len;
+    src.per_seg = seg_len >= q ? seg_len - q + 1 : 0;
+    const FastMod fm = make_fastmod(src.per_seg ? src.per_seg : 1);
+    src.fm_magic = fm.magic;
+    src.fm_sh1 = fm.sh1;
+    src.fm_sh2 = fm.sh2;
+    src.q = q;
+    return src;
+}
+
+} // namespace
+
+hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+{
+    return insert_any(f, ArrayKeys{keys}, n, s);
+}
+
+hipError_t launch_insert_kmers(const bbfc_filter &f, const uint64_t *seq, uint64_t n_segments, uint64_t seg_len, uint32_t q, hipStream_t s)
+{
+    const KmerKeys src = make_kmer_src(seq, seg_len, q);
+    return insert_any(f, src, n_segments * src.per_seg, s);
+}
+
+hipError_t launch_query_kmers(const bbfc_filter &f, const uint64_t *seq, uint64_t n_segments, uint64_t seg_len, uint32_t q, uint64_t *out, hipStream_t s)
+{
+    const KmerKeys src = make_kmer_src(seq, seg_len, q);
+    return query_any(f, src, n_segments * src.per_seg, out, s);
+}
+
+hipError_t launch_kmer_keys(const uint64_t *seq, uint64_t n_segments, uint64_t seg_len, uint32_t q, uint64_t *out,
+                            hipStream_t s)
+{
+    const KmerKeys src = make_kmer_src(seq, seg_len, q);
+    const uint64_t n = n_segments * src.per_seg;
+    if (n == 0)
+        return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 65536)
+        blocks = 65536;
+    hipLaunchKernelGGL(kmer_keys_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, src, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
@@ -295,18 +368,7 @@ hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_
 
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
 {
-    switch (f.c) {
-    case 1:
-        return query_c<1>(f, keys, n, out, s);
-    case 2:
-        return query_c<2>(f, keys, n, out, s);
-    case 3:
-        return query_c<3>(f, keys, n, out, s);
-    case 4:
-        return query_c<4>(f, keys, n, out, s);
-    default:
-        return hipErrorInvalidValue;
-    }
+    return query_any(f, ArrayKeys{keys}, n, out, s);
 }
 
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s)

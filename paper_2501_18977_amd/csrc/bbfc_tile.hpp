@@ -94,16 +94,60 @@ __device__ inline uint32_t popc64(uint64_t v)
     return (uint32_t)__popcll(v);
 }
 
+// Key sources: key t of a call, read from an array or computed in place.
+struct ArrayKeys {
+    const uint64_t *__restrict__ keys;
+    __device__ inline uint64_t load(uint64_t t) const { return keys[t]; }
+    __device__ inline ArrayKeys offset(uint64_t off) const { return ArrayKeys{keys + off}; }
+};
+
+// Canonical q-grams (k-mers of q bases) of a 2-bit packed sequence (A=0, C=1, G=2, T=3; base i in
+// bits 63-2(i%32) .. 62-2(i%32) of word i/32, so earlier bases sit higher)
+// cut into segments of seg_len bases: key t is the window at base
+// s*seg_len + j with s = t / per_seg, j = t % per_seg, per_seg = seg_len-q+1.
+// A window's forward value has its first base most significant; the reverse
+// complement complements each base (b -> 3-b) and reverses their order; the
+// key is the smaller of the two.
+struct KmerKeys {
+    const uint64_t *__restrict__ seq;
+    uint64_t seg_len;
+    uint64_t per_seg;
+    uint64_t fm_magic; // FastMod of per_seg
+    uint32_t fm_sh1;
+    uint32_t fm_sh2;
+    uint32_t q; // bases per window (1..32)
+    __device__ inline uint64_t load(uint64_t t) const
+    {
+        const uint64_t s = per_seg == 1 ? t : fastdiv(t, fm_magic, fm_sh1, fm_sh2);
+        const uint64_t pos = s * seg_len + (t - s * per_seg);
+        const uint64_t w = pos >> 5;
+        const uint32_t o = (uint32_t)(pos & 31);
+        uint64_t v = seq[w];
+        if (o != 0) {
+            v <<= 2 * o;
+            if (o + q > 32) // the window reaches into the next word
+                v |= seq[w + 1] >> (64 - 2 * o);
+        }
+        const uint64_t fwd = v >> (64 - 2 * q);
+        // bit reversal reverses the bases and the two bits of each base;
+        // swapping the bits of every pair back leaves the bases reversed
+        uint64_t r = __builtin_bitreverse64(~fwd);
+        r = ((r >> 1) & 0x5555555555555555ull) | ((r & 0x5555555555555555ull) << 1);
+        const uint64_t rc = r >> (64 - 2 * q);
+        return fwd < rc ? fwd : rc;
+    }
+};
+
 // Phase A: lane t handles key base + t; keys past n are hashed as key 0,
 // whose candidate blocks are in range, so later loads need no guard.
-template <int C>
-__device__ inline void phase_a(const KParams &p, const uint64_t *__restrict__ keys, uint64_t n, uint64_t base,
-                               uint32_t lane, uint32_t *smask, uint64_t *sblk)
+template <int C, typename Src>
+__device__ inline void phase_a(const KParams &p, const Src &src, uint64_t n, uint64_t base, uint32_t lane,
+                               uint32_t *smask, uint64_t *sblk)
 {
     const uint64_t idx = base + lane;
     uint64_t x = 0;
     if (idx < n)
-        x = keys[idx];
+        x = src.load(idx);
     uint32_t *slot = smask + lane * kSlotDw;
 #pragma unroll
     for (int d = 0; d < 16; ++d)
@@ -160,8 +204,8 @@ __device__ inline bool holds(const uint64_t (&B)[KW], const uint64_t (&m)[KW])
 // tile that holds at least one key. EARLY: candidate i+1 is read only by the
 // groups whose key candidates 1..i did not answer (same answers, fewer
 // random lines).
-template <int C, int LPK, int T, bool EARLY>
-__device__ inline void query_tiles(const KParams &p, const uint64_t *__restrict__ keys, uint64_t n, uint64_t base,
+template <int C, int LPK, int T, bool EARLY, typename Src>
+__device__ inline void query_tiles(const KParams &p, const Src &keys, uint64_t n, uint64_t base,
                                    uint64_t *__restrict__ out_tile, uint32_t lane, uint32_t *smask, uint64_t *sblk)
 {
     using L = Lanes<LPK>;
@@ -326,9 +370,9 @@ __device__ inline uint64_t pick(const uint64_t (&B)[C][KW], int i, int q)
 }
 
 // Racing insert of T consecutive tiles whose first key is keys[base].
-template <int C, int LPK, int T>
-__device__ inline void insert_tiles(const KParams &p, const uint16_t *rank, const uint64_t *__restrict__ keys,
-                                    uint64_t n, uint64_t base, uint32_t lane, uint32_t *smask, uint64_t *sblk)
+template <int C, int LPK, int T, typename Src>
+__device__ inline void insert_tiles(const KParams &p, const uint16_t *rank, const Src &keys, uint64_t n,
+                                    uint64_t base, uint32_t lane, uint32_t *smask, uint64_t *sblk)
 {
     using L = Lanes<LPK>;
     constexpr int R = L::kRounds;

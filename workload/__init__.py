@@ -142,6 +142,38 @@ def serve_requests(seed: int, count: int, n_pos: int, lo: int = 1, hi: int = 655
     return sizes, pstart, nstart
 
 
+# ------------------------------------------------------------- DNA inputs
+# Bases A, C, G, T are the values 0..3. A packed sequence holds 32 bases per
+# 64-bit word, base i in bits 63-2(i%32) .. 62-2(i%32) of word i/32.
+
+def genome_packed(seed: int, n_bases: int) -> np.ndarray:
+    """A uniform random genome: its packed words are the counter-based
+    SplitMix64 outputs key(seed, 0), key(seed, 1), ..."""
+    return splitmix64_keys(seed, 0, (n_bases + 31) // 32)
+
+
+def unpack_2bit(words, n_bases: int) -> np.ndarray:
+    """Packed words to one base (0..3) per byte."""
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    shifts = np.arange(62, -1, -2, dtype=np.uint64)
+    b = ((w[:, None] >> shifts[None, :]) & np.uint64(3)).astype(np.uint8).reshape(-1)
+    return b[:n_bases]
+
+
+def pack_2bit(bases) -> np.ndarray:
+    """One base (0..3) per byte to packed words (tail bases zero)."""
+    b = np.ascontiguousarray(bases, dtype=np.uint64)
+    n = len(b)
+    pad = np.zeros(((n + 31) // 32) * 32, dtype=np.uint64)
+    pad[:n] = b
+    shifts = np.arange(62, -1, -2, dtype=np.uint64)
+    return np.bitwise_or.reduce(pad.reshape(-1, 32) << shifts[None, :], axis=1)
+
+
+def random_bases(seed: int, n: int) -> np.ndarray:
+    return unpack_2bit(genome_packed(seed, n), n)
+
+
 # ----------------------------------------------------- device-side generator
 
 import ctypes as _ctypes
@@ -172,6 +204,8 @@ def _device_lib():
         L = _ctypes.CDLL(_DEV_LIB)
         L.wl_splitmix64_keys.argtypes = [_ctypes.c_uint64] * 3 + [_ctypes.c_void_p] * 2
         L.wl_splitmix64_keys.restype = _ctypes.c_int
+        L.wl_reads.argtypes = [_ctypes.c_void_p] + [_ctypes.c_uint64] * 5 + [_ctypes.c_void_p] * 2
+        L.wl_reads.restype = _ctypes.c_int
         _dev = L
     return _dev
 
@@ -188,4 +222,23 @@ def device_keys(seed: int, start: int, n: int, device="cuda", out=None, stream=N
     rc = _device_lib().wl_splitmix64_keys(seed & MASK64, start, n, out.data_ptr(), _ctypes.c_void_p(stream.cuda_stream))
     if rc != 0:
         raise RuntimeError(f"device key generation failed ({rc})")
+    return out
+
+
+def device_reads(genome, n_genome: int, n_reads: int, read_len: int, err: float, seed: int, out=None, stream=None):
+    """Packed reads sampled from a packed genome on the GPU (see
+    csrc/keygen.hip): uniform start, random strand, substitutions with
+    probability err per base."""
+    import torch
+
+    n_words = (n_reads * read_len + 31) // 32
+    if out is None:
+        out = torch.empty(max(1, n_words), dtype=torch.int64, device=genome.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(genome.device)
+    thr = min(int(err * 2.0 ** 64), MASK64)
+    rc = _device_lib().wl_reads(genome.data_ptr(), n_genome, n_reads, read_len, thr, seed & MASK64,
+                                out.data_ptr(), _ctypes.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"device read generation failed ({rc})")
     return out

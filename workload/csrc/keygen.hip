@@ -34,3 +34,80 @@ extern "C" int wl_splitmix64_keys(uint64_t seed, uint64_t start, uint64_t n, uin
     hipLaunchKernelGGL(splitmix_keys_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, seed, start, n, d_out);
     return hipGetLastError() == hipSuccess ? 0 : -3;
 }
+
+// Reads of read_len bases sampled from a packed genome (32 bases per word,
+// base i in bits 63-2(i%32) .. 62-2(i%32) of word i/32), concatenated and
+// packed the same way. Read r starts at mix(seed, r) mod (genome - read_len
+// + 1) and is the reverse complement when bit 0 of mix(seed ^ S1, r) is set;
+// base p of the output is replaced by one of the three other bases when
+// mix(seed ^ S2, p) < err_threshold (probability err_threshold / 2^64), the
+// replacement chosen by mix(seed ^ S3, p) mod 3. One thread writes one word.
+namespace {
+
+__device__ inline uint64_t wl_mix(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+constexpr uint64_t kStrandSalt = 0xA5A5A5A5A5A5A5A5ull;
+constexpr uint64_t kErrSalt = 0x5A5A5A5A5A5A5A5Aull;
+constexpr uint64_t kSubSalt = 0x3C3C3C3C3C3C3C3Cull;
+
+__global__ void reads_kernel(const uint64_t *__restrict__ genome, uint64_t n_genome, uint64_t n_reads,
+                             uint64_t read_len, uint64_t err_threshold, uint64_t seed, uint64_t *__restrict__ out,
+                             uint64_t n_words)
+{
+    const uint64_t total = n_reads * read_len;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words; w += stride) {
+        uint64_t p = w * 32;
+        uint64_t r = p / read_len;
+        uint64_t j = p - r * read_len;
+        uint64_t start = 0, strand = 0;
+        uint64_t cur = ~0ull;
+        uint64_t word = 0;
+        for (int b = 0; b < 32; ++b, ++p, ++j) {
+            if (j == read_len) {
+                j = 0;
+                ++r;
+            }
+            uint64_t base = 0;
+            if (p < total) {
+                if (r != cur) {
+                    start = wl_mix(seed, r) % (n_genome - read_len + 1);
+                    strand = wl_mix(seed ^ kStrandSalt, r) & 1;
+                    cur = r;
+                }
+                const uint64_t g = start + (strand ? read_len - 1 - j : j);
+                base = (genome[g >> 5] >> (62 - 2 * (g & 31))) & 3;
+                if (strand)
+                    base = 3 - base;
+                if (wl_mix(seed ^ kErrSalt, p) < err_threshold)
+                    base = (base + 1 + wl_mix(seed ^ kSubSalt, p) % 3) & 3;
+            }
+            word |= base << (62 - 2 * b);
+        }
+        out[w] = word;
+    }
+}
+
+} // namespace
+
+extern "C" int wl_reads(const uint64_t *d_genome, uint64_t n_genome, uint64_t n_reads, uint64_t read_len,
+                        uint64_t err_threshold, uint64_t seed, uint64_t *d_out, hipStream_t stream)
+{
+    if (n_reads == 0 || read_len == 0)
+        return 0;
+    if (d_genome == nullptr || d_out == nullptr || n_genome < read_len)
+        return -1;
+    const uint64_t n_words = (n_reads * read_len + 31) / 32;
+    uint64_t blocks = (n_words + 255) / 256;
+    if (blocks > 16384)
+        blocks = 16384;
+    hipLaunchKernelGGL(reads_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, d_genome, n_genome, n_reads,
+                       read_len, err_threshold, seed, d_out, n_words);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
