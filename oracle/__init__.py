@@ -57,22 +57,26 @@ def _load():
     lib.bbo_default_param.restype = dbl
     lib.bbo_cost.argtypes = [i32, dbl, u32, u32, u32]
     lib.bbo_cost.restype = dbl
-    lib.bbo_insert_one.argtypes = [_u64p, u64, u32, u32, i32, dbl, _u64p, _u64p, u64]
+    lib.bbo_insert_one.argtypes = [_u64p, u64, u32, u32, i32, i32, dbl, _u64p, _u64p, u64]
     lib.bbo_insert_one.restype = i32
-    lib.bbo_insert.argtypes = [_u64p, u64, u32, u32, i32, dbl, _u64p, _u64p, _u64p, u64]
+    lib.bbo_insert.argtypes = [_u64p, u64, u32, u32, i32, i32, dbl, _u64p, _u64p, _u64p, u64]
     lib.bbo_insert.restype = u64
-    lib.bbo_query_one.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, u64]
+    lib.bbo_query_one.argtypes = [_u64p, u64, u32, u32, i32, _u64p, _u64p, u64]
     lib.bbo_query_one.restype = i32
-    lib.bbo_query.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, _u64p, u64, _u64p]
+    lib.bbo_query.argtypes = [_u64p, u64, u32, u32, i32, _u64p, _u64p, _u64p, u64, _u64p]
     lib.bbo_query.restype = u64
-    lib.bbo_derive_multipliers.argtypes = [u64, u64, u32, u32, _u64p, _u64p]
+    lib.bbo_derive_multipliers.argtypes = [u64, u64, u32, u32, i32, _u64p, _u64p]
     lib.bbo_derive_multipliers.restype = None
-    lib.bbo_envelope.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, _u64p, u64]
+    lib.bbo_envelope.argtypes = [_u64p, u64, u32, u32, i32, _u64p, _u64p, _u64p, u64]
     lib.bbo_envelope.restype = None
     lib.bbo_block_loads.argtypes = [_u64p, u64, _u64p]
     lib.bbo_block_loads.restype = None
-    lib.bbo_conditional_fpr.argtypes = [_u64p, u64, u32, u32, _u64p, _u64p, u64]
+    lib.bbo_conditional_fpr.argtypes = [_u64p, u64, u32, u32, i32, _u64p, _u64p, u64]
     lib.bbo_conditional_fpr.restype = dbl
+    lib.bbo_distinct_positions.argtypes = [ctypes.c_void_p, u32, ctypes.c_void_p]
+    lib.bbo_distinct_positions.restype = None
+    lib.bbo_mask_distinct.argtypes = [_u64p, u32, u64, _u64p]
+    lib.bbo_mask_distinct.restype = None
     lib.bbo_qgrams.argtypes = [ctypes.c_void_p, u64, u64, u32, _u64p]
     lib.bbo_qgrams.restype = u64
     _lib = lib
@@ -92,11 +96,20 @@ def hash_(a: int, x: int, b: int) -> int:
     return int(_load().bbo_hash(a, x, b))
 
 
-def mask(bit_mult, x: int) -> np.ndarray:
+def mask(bit_mult, x: int, distinct: bool = False) -> np.ndarray:
     am = _u64(bit_mult)
     out = np.zeros(8, dtype=np.uint64)
-    _load().bbo_mask(_ptr(am), len(am), x, _ptr(out))
+    fn = _load().bbo_mask_distinct if distinct else _load().bbo_mask
+    fn(_ptr(am), len(am), x, _ptr(out))
     return out
+
+
+def distinct_positions(raw) -> list[int]:
+    """App. B procedure on raw values (raw[i] in [512 - i])."""
+    r = np.ascontiguousarray(raw, dtype=np.uint32)
+    out = np.zeros(max(1, len(r)), dtype=np.uint32)
+    _load().bbo_distinct_positions(r.ctypes.data, len(r), out.ctypes.data)
+    return [int(v) for v in out[:len(r)]]
 
 
 def default_param(kind: int, k: int) -> float:
@@ -118,10 +131,10 @@ def qgrams(bases, n_segments: int, seg_len: int, q: int) -> np.ndarray:
     return out[:n]
 
 
-def derive_multipliers(seed: int, M: int, c: int, k: int):
+def derive_multipliers(seed: int, M: int, c: int, k: int, distinct: bool = False):
     bm = np.zeros(c, dtype=np.uint64)
     am = np.zeros(k, dtype=np.uint64)
-    _load().bbo_derive_multipliers(seed, M, c, k, _ptr(bm), _ptr(am))
+    _load().bbo_derive_multipliers(seed, M, c, k, int(distinct), _ptr(bm), _ptr(am))
     return [int(v) for v in bm], [int(v) for v in am]
 
 
@@ -129,16 +142,18 @@ class OracleFilter:
     """A filter held in host memory and driven by the sequential oracle."""
 
     def __init__(self, n_blocks: int, choices: int, k: int, cost_kind: int = COST_NONE,
-                 cost_param: float | None = None, block_mult=None, bit_mult=None, seed: int = 0):
+                 cost_param: float | None = None, block_mult=None, bit_mult=None, seed: int = 0,
+                 distinct: bool = False):
         if choices < 1 or k < 1 or n_blocks < 1:
             raise ValueError("bad filter shape")
         self.M, self.c, self.k = int(n_blocks), int(choices), int(k)
+        self.distinct = int(bool(distinct))
         self.kind = int(cost_kind)
         if cost_param is None or (isinstance(cost_param, float) and np.isnan(cost_param)):
             cost_param = default_param(self.kind, self.k)
         self.param = float(cost_param)
         if block_mult is None or bit_mult is None:
-            dbm, dam = derive_multipliers(seed, self.M, self.c, self.k)
+            dbm, dam = derive_multipliers(seed, self.M, self.c, self.k, bool(self.distinct))
             block_mult = dbm if block_mult is None else block_mult
             bit_mult = dam if bit_mult is None else bit_mult
         self.block_mult = _u64(block_mult)
@@ -148,18 +163,18 @@ class OracleFilter:
 
     def insert(self, keys) -> int:
         keys = _u64(keys)
-        return int(_load().bbo_insert(_ptr(self.words), self.M, self.c, self.k, self.kind, self.param,
+        return int(_load().bbo_insert(_ptr(self.words), self.M, self.c, self.k, self.distinct, self.kind, self.param,
                                       _ptr(self.block_mult), _ptr(self.bit_mult), _ptr(keys), len(keys)))
 
     def insert_one(self, key: int) -> int:
-        return int(_load().bbo_insert_one(_ptr(self.words), self.M, self.c, self.k, self.kind,
+        return int(_load().bbo_insert_one(_ptr(self.words), self.M, self.c, self.k, self.distinct, self.kind,
                                           self.param, _ptr(self.block_mult), _ptr(self.bit_mult), key))
 
     def query_bits(self, keys) -> np.ndarray:
         """Packed answers: bit t of word t//64 (LSB first) for keys[t]."""
         keys = _u64(keys)
         out = np.zeros((len(keys) + 63) // 64, dtype=np.uint64)
-        _load().bbo_query(_ptr(self.words), self.M, self.c, self.k, _ptr(self.block_mult),
+        _load().bbo_query(_ptr(self.words), self.M, self.c, self.k, self.distinct, _ptr(self.block_mult),
                           _ptr(self.bit_mult), _ptr(keys), len(keys), _ptr(out))
         return out
 
@@ -171,17 +186,17 @@ class OracleFilter:
 
     def count_hits(self, keys) -> int:
         keys = _u64(keys)
-        return int(_load().bbo_query(_ptr(self.words), self.M, self.c, self.k, _ptr(self.block_mult),
+        return int(_load().bbo_query(_ptr(self.words), self.M, self.c, self.k, self.distinct, _ptr(self.block_mult),
                                      _ptr(self.bit_mult), _ptr(keys), len(keys), None))
 
     def query_one(self, key: int) -> bool:
-        return bool(_load().bbo_query_one(_ptr(self.words), self.M, self.c, self.k,
+        return bool(_load().bbo_query_one(_ptr(self.words), self.M, self.c, self.k, self.distinct,
                                           _ptr(self.block_mult), _ptr(self.bit_mult), key))
 
     def envelope(self, keys) -> np.ndarray:
         keys = _u64(keys)
         env = np.zeros_like(self.words)
-        _load().bbo_envelope(_ptr(env), self.M, self.c, self.k, _ptr(self.block_mult),
+        _load().bbo_envelope(_ptr(env), self.M, self.c, self.k, self.distinct, _ptr(self.block_mult),
                              _ptr(self.bit_mult), _ptr(keys), len(keys))
         return env
 
@@ -194,5 +209,5 @@ class OracleFilter:
     def conditional_fpr(self, keys, words: np.ndarray | None = None) -> float:
         w = self.words if words is None else _u64(words)
         keys = _u64(keys)
-        return float(_load().bbo_conditional_fpr(_ptr(w), self.M, self.c, self.k,
+        return float(_load().bbo_conditional_fpr(_ptr(w), self.M, self.c, self.k, self.distinct,
                                                  _ptr(self.block_mult), _ptr(keys), len(keys)))

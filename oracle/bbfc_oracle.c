@@ -127,15 +127,60 @@ static unsigned popc64(uint64_t v)
     return (unsigned)__builtin_popcountll(v);
 }
 
+/* Distinct bit selection (Section 3.3, App. B), on raw values: raw[i] lies
+ * in [512 - i] (i counted from 0); it is increased by one for every address
+ * already chosen that is at or below its current value, scanning the chosen
+ * addresses in increasing order, which are kept sorted. Writes the k
+ * distinct addresses, sorted, to out. */
+void bbo_distinct_positions(const uint32_t *raw, uint32_t k, uint32_t *out)
+{
+    uint32_t used = 0;
+    for (uint32_t i = 0; i < k; i++) {
+        uint32_t v = raw[i];
+        uint32_t pos = 0;
+        while (pos < used && out[pos] <= v) { /* every occupied address at or below v */
+            v++;
+            pos++;
+        }
+        for (uint32_t t = used; t > pos; t--) /* insertion keeps the addresses sorted */
+            out[t] = out[t - 1];
+        out[pos] = v;
+        used++;
+    }
+}
+
+/* F(x) under distinct bit selection: f_i hashed into [512 - i + 1]
+ * (modulus 513 - i for i = 1..k, the hash of Section 3.4), then made
+ * distinct as above. */
+void bbo_mask_distinct(const uint64_t *bit_mult, uint32_t k, uint64_t x, uint64_t m[8])
+{
+    uint32_t raw[32] = {0}, pos[32] = {0};
+    memset(m, 0, 8 * sizeof(uint64_t));
+    for (uint32_t i = 0; i < k; i++)
+        raw[i] = (uint32_t)bbo_hash(bit_mult[i], x, 512 - i);
+    bbo_distinct_positions(raw, k, pos);
+    for (uint32_t i = 0; i < k; i++)
+        m[pos[i] / 64] |= (uint64_t)1 << (pos[i] % 64);
+}
+
+/* F(x) as a mask under either strategy: 0 random (Section 3.3), 1 distinct. */
+static void bbo_mask_sel(int distinct, const uint64_t *bit_mult, uint32_t k, uint64_t x, uint64_t m[8])
+{
+    if (distinct)
+        bbo_mask_distinct(bit_mult, k, x, m);
+    else
+        bbo_mask(bit_mult, k, x, m);
+}
+
 /* Insert one key (Sections 3.1, 3.2). Returns the chosen choice index, or
  * -1 when some candidate already contains F(x). */
-int bbo_insert_one(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int kind, double param,
+int bbo_insert_one(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct, int kind, double param,
                    const uint64_t *block_mult, const uint64_t *bit_mult, uint64_t x)
 {
     uint64_t m[8];
     uint64_t blk[8];
     uint32_t j[8], a[8];
-    bbo_mask(bit_mult, k, x, m);
+    bbo_mask_sel(distinct, bit_mult, k, x, m);
     for (uint32_t i = 0; i < c; i++) {
         blk[i] = bbo_hash(block_mult[i], x, M);
         const uint64_t *B = W + 8 * blk[i];
@@ -169,23 +214,23 @@ int bbo_insert_one(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int kind, do
 
 /* Sequential insertion of keys[0..n) in order. Returns how many keys set
  * at least one bit. */
-uint64_t bbo_insert(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int kind, double param,
+uint64_t bbo_insert(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct, int kind, double param,
                     const uint64_t *block_mult, const uint64_t *bit_mult, const uint64_t *keys,
                     uint64_t n)
 {
     uint64_t written = 0;
     for (uint64_t t = 0; t < n; t++)
-        if (bbo_insert_one(W, M, c, k, kind, param, block_mult, bit_mult, keys[t]) >= 0)
+        if (bbo_insert_one(W, M, c, k, distinct, kind, param, block_mult, bit_mult, keys[t]) >= 0)
             written++;
     return written;
 }
 
 /* Query one key: F(x) subset of some candidate block (Section 3.1). */
-int bbo_query_one(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k,
+int bbo_query_one(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct,
                   const uint64_t *block_mult, const uint64_t *bit_mult, uint64_t x)
 {
     uint64_t m[8];
-    bbo_mask(bit_mult, k, x, m);
+    bbo_mask_sel(distinct, bit_mult, k, x, m);
     for (uint32_t i = 0; i < c; i++) {
         const uint64_t *B = W + 8 * bbo_hash(block_mult[i], x, M);
         int all = 1;
@@ -201,14 +246,14 @@ int bbo_query_one(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k,
 /* Queries keys[0..n); bit t of out_bits[t/64] (least significant first) is
  * the answer for keys[t]; bits past n in the last word are zero. Returns the
  * number of positive answers. */
-uint64_t bbo_query(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k, const uint64_t *block_mult,
+uint64_t bbo_query(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct, const uint64_t *block_mult,
                    const uint64_t *bit_mult, const uint64_t *keys, uint64_t n, uint64_t *out_bits)
 {
     uint64_t hits = 0;
     if (out_bits)
         memset(out_bits, 0, ((n + 63) / 64) * sizeof(uint64_t));
     for (uint64_t t = 0; t < n; t++) {
-        int h = bbo_query_one(W, M, c, k, block_mult, bit_mult, keys[t]);
+        int h = bbo_query_one(W, M, c, k, distinct, block_mult, bit_mult, keys[t]);
         hits += (uint64_t)h;
         if (h && out_bits)
             out_bits[t / 64] |= (uint64_t)1 << (t % 64);
@@ -241,8 +286,9 @@ static uint64_t gcd64(uint64_t a, uint64_t b)
  * "random large integer a, coprime with b"; reading R3): one SplitMix64
  * stream; each draw is made odd; draws below 2^32 or sharing a factor with
  * the modulus are skipped. Block multipliers come first (modulus M), then
- * bit multipliers (modulus 512). */
-void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint32_t c, uint32_t k, uint64_t *block_mult,
+ * bit multipliers (modulus 512, or 512 - i for the i-th with distinct bit
+ * selection, counting from 0). */
+void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint32_t c, uint32_t k, int distinct, uint64_t *block_mult,
                             uint64_t *bit_mult)
 {
     uint64_t st = seed;
@@ -253,7 +299,8 @@ void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint32_t c, uint32_t k, u
     }
     for (uint32_t i = 0; i < k;) {
         uint64_t a = splitmix_next(&st) | 1;
-        if (a >= ((uint64_t)1 << 32))
+        uint64_t b = distinct ? 512 - i : 512; /* modulus of bit hash i */
+        if (a >= ((uint64_t)1 << 32) && gcd64(a, b) == 1)
             bit_mult[i++] = a;
     }
 }
@@ -264,12 +311,12 @@ void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint32_t c, uint32_t k, u
  * these keys (sequential or with racing inserts) is bitwise contained in
  * this envelope, since bits only ever come from some key's mask placed in
  * one of its candidates. */
-void bbo_envelope(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, const uint64_t *block_mult,
+void bbo_envelope(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct, const uint64_t *block_mult,
                   const uint64_t *bit_mult, const uint64_t *keys, uint64_t n)
 {
     uint64_t m[8];
     for (uint64_t t = 0; t < n; t++) {
-        bbo_mask(bit_mult, k, keys[t], m);
+        bbo_mask_sel(distinct, bit_mult, k, keys[t], m);
         for (uint32_t i = 0; i < c; i++) {
             uint64_t *B = W + 8 * bbo_hash(block_mult[i], keys[t], M);
             for (int w = 0; w < 8; w++)
@@ -293,12 +340,13 @@ void bbo_block_loads(const uint64_t *W, uint64_t M, uint64_t *hist)
 
 /* Low-variance false-positive estimate over negative keys (the "FPR from
  * the block loads" that Section 4.1 mentions): for each key, the exact
- * probability that k independent uniform bit addresses all fall inside one
- * of its candidate blocks, given those blocks' actual contents, by
+ * probability that k independent uniform bit addresses (or, distinct, k
+ * distinct uniform ones) all fall inside one of its candidate blocks, given
+ * those blocks' actual contents, by
  * inclusion-exclusion over the non-empty subsets I of choices:
  *   sum_I (-1)^(|I|+1) (|intersection of S_i, i in I| / 512)^k.
  * Returns the mean over the keys. */
-double bbo_conditional_fpr(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k,
+double bbo_conditional_fpr(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct,
                            const uint64_t *block_mult, const uint64_t *keys, uint64_t n)
 {
     double total = 0.0;
@@ -318,7 +366,14 @@ double bbo_conditional_fpr(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k
             }
             for (uint32_t i = 0; i < c; i++)
                 size += (sub >> i) & 1u;
-            double term = pow((double)inter / 512.0, (double)k);
+            double term;
+            if (!distinct) {
+                term = pow((double)inter / 512.0, (double)k);
+            } else { /* k distinct uniform addresses: C(inter, k) / C(512, k) */
+                term = 1.0;
+                for (uint32_t i = 0; i < k; i++)
+                    term *= (inter > i) ? (double)(inter - i) / (double)(512 - i) : 0.0;
+            }
             p += (size & 1) ? term : -term;
         }
         total += p;

@@ -34,6 +34,17 @@ def bit_set(bit_mult, x: int) -> set[int]:
     return {lin_hash(a, x, 512) for a in bit_mult}
 
 
+def bit_set_distinct(bit_mult, x: int) -> set[int]:
+    """Distinct strategy (App. B) restated: the i-th raw value, hashed into
+    [512 - i], picks that element of the list of addresses still free
+    (the paper: a random value from [512] minus the earlier addresses)."""
+    free = list(range(512))
+    out = set()
+    for i, a in enumerate(bit_mult):
+        out.add(free.pop(lin_hash(a, x, 512 - i)))
+    return out
+
+
 def cost(kind: str, param: float, k: int, j: int, a: int) -> float:
     """App. A eqs. cost:mix, cost:la, cost:exp (same left-to-right order)."""
     if kind == "mix":
@@ -46,8 +57,10 @@ def cost(kind: str, param: float, k: int, j: int, a: int) -> float:
 
 
 class BruteFilter:
-    def __init__(self, M: int, c: int, k: int, kind: str, param: float, block_mult, bit_mult):
+    def __init__(self, M: int, c: int, k: int, kind: str, param: float, block_mult, bit_mult,
+                 distinct: bool = False):
         self.M, self.c, self.k, self.kind, self.param = M, c, k, kind, param
+        self.distinct = distinct
         self.block_mult = [int(v) for v in block_mult]
         self.bit_mult = [int(v) for v in bit_mult]
         self.blocks: list[set[int]] = [set() for _ in range(M)]
@@ -55,8 +68,11 @@ class BruteFilter:
     def candidates(self, x: int) -> list[int]:
         return [lin_hash(b, x, self.M) for b in self.block_mult]
 
+    def F(self, x: int) -> set[int]:
+        return bit_set_distinct(self.bit_mult, x) if self.distinct else bit_set(self.bit_mult, x)
+
     def insert(self, x: int) -> int:
-        F = bit_set(self.bit_mult, x)
+        F = self.F(x)
         cand = self.candidates(x)
         ja = []
         for b in cand:
@@ -72,7 +88,7 @@ class BruteFilter:
         return best
 
     def query(self, x: int) -> bool:
-        F = bit_set(self.bit_mult, x)
+        F = self.F(x)
         return any(F <= self.blocks[b] for b in self.candidates(x))
 
     def words(self) -> list[int]:

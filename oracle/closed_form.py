@@ -70,6 +70,39 @@ def occupancy_moments(max_keys: int, k: int) -> np.ndarray:
     return g
 
 
+def occupancy_moments_distinct(max_keys: int, k: int) -> np.ndarray:
+    """As occupancy_moments, for keys that set k distinct uniform addresses
+    (App. B): with P bits set, a key adds a ~ Hypergeometric(512, 512-P, k)
+    new bits; a negative key hits with probability C(P, k) / C(512, k)."""
+    from scipy import special
+
+    p = np.arange(BITS + 1)
+    hit = special.comb(p, k, exact=False) / special.comb(BITS, k, exact=False)
+    # transition T[P, P + a] = C(512-P, a) C(P, k-a) / C(512, k)
+    T = np.zeros((BITS + 1, BITS + 1))
+    for P in range(BITS + 1):
+        for a in range(0, k + 1):
+            if P + a <= BITS:
+                T[P, P + a] = stats.hypergeom.pmf(a, BITS, BITS - P, k)
+    dist = np.zeros(BITS + 1)
+    dist[0] = 1.0
+    g = np.empty(max_keys + 1)
+    g[0] = float(dist @ hit)
+    for i in range(1, max_keys + 1):
+        dist = dist @ T
+        g[i] = float(dist @ hit)
+    return g
+
+
+def blocked_fpr_distinct(n: int, M: int, k: int) -> float:
+    """Exact FPR of a one-choice Blocked Bloom filter with distinct bits."""
+    lam = n / M
+    imax = int(lam + 12.0 * math.sqrt(lam + 1.0) + 20)
+    g = occupancy_moments_distinct(imax, k)
+    w = stats.binom.pmf(np.arange(imax + 1), n, 1.0 / M)
+    return float(w @ g)
+
+
 def blocked_fpr(n: int, M: int, k: int) -> float:
     """Exact FPR of a one-choice Blocked Bloom filter with n keys in M blocks."""
     lam = n / M
