@@ -52,6 +52,8 @@ def parse_args():
     ap.add_argument("--reads", type=float, default=1e7, help="kmer workload: reads of 150 bp (and as many random)")
     ap.add_argument("--requests", type=int, default=20000, help="serve workload: requests per offered load")
     ap.add_argument("--log2-keys", type=int, default=30, help="keys to insert (2^n); blocks = keys/32")
+    ap.add_argument("--bits", choices=["random", "distinct"], default="random",
+                    help="plain workload: bit selection strategy (Section 3.3)")
     ap.add_argument("--filters", type=int, default=256, help="batch workload: number of filters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
@@ -114,7 +116,8 @@ def copy_calibration():
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for rel in ("paper_2501_18977_amd/csrc/bbfc_kernels.hip", "paper_2501_18977_amd/csrc/bbfc_common.hpp"):
+    for rel in ("paper_2501_18977_amd/csrc/bbfc_kernels.hip", "paper_2501_18977_amd/csrc/bbfc_common.hpp",
+                "paper_2501_18977_amd/csrc/bbfc_tile.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -134,14 +137,14 @@ def measured_traffic(kernel: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(n_blocks, c, k, target_s):
+def cpu_baseline(n_blocks, c, k, target_s, distinct=False):
     """The sequential oracle on a bounded sample of the same workload."""
     import numpy as np
 
     import oracle
     import workload
 
-    f = oracle.OracleFilter(n_blocks, c, k, oracle.COST_LA, None, seed=0)
+    f = oracle.OracleFilter(n_blocks, c, k, oracle.COST_LA, None, seed=0, distinct=distinct)
 
     def timed(fn, keys):
         t = time.perf_counter()
@@ -615,7 +618,7 @@ def main():
     workload.device_keys(0, 0, n, out=keys[:n])          # positives: counters [0, n)
     workload.device_keys(0, n, n, out=keys[n:])          # negatives: counters [n, 2n)
     out = torch.empty(n_q // 64, dtype=torch.int64, device=dev)
-    filt = bbfc.Filter(n_blocks, c, k, "la", seed=0)
+    filt = bbfc.Filter(n_blocks, c, k, "la", seed=0, bit_selection=args.bits)
     torch.cuda.synchronize()
 
     stream = torch.cuda.current_stream()
@@ -703,7 +706,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(n_blocks, c, k, args.cpu_seconds)
+        cpu = cpu_baseline(n_blocks, c, k, args.cpu_seconds, distinct=args.bits == "distinct")
 
     rec = {
         "metric": "Mkeys/s insert & query, 2-choice 512b blocks; % of random-access HBM peak",
@@ -721,7 +724,8 @@ def main():
         "config": {
             "workload": (f"plain filter: 2^{args.log2_keys} random 64-bit keys inserted into 2^"
                          f"{int(math.log2(n_blocks))} blocks of 512 bits, 2 choices, k=11, lookahead cost "
-                         f"mu=3.5; queries: the 2^{args.log2_keys} inserted + 2^{args.log2_keys} never inserted"),
+                         f"mu=3.5, {args.bits} bit selection; queries: the 2^{args.log2_keys} inserted + "
+                         f"2^{args.log2_keys} never inserted"),
             "n_keys": n,
             "n_queries": n_q,
             "n_blocks": n_blocks,
@@ -729,6 +733,7 @@ def main():
             "choices": c,
             "bits_per_key": k,
             "cost": "la",
+            "bit_selection": args.bits,
         },
         "insert_mkeys_s": round(n / (avg_ins / 1e3) / 1e6, 1),
         "query_mkeys_s": round(n_q / (avg_qry / 1e3) / 1e6, 1),

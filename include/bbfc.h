@@ -82,6 +82,32 @@ typedef struct {
 #define BBFC_MAX_CHOICES 4u
 #define BBFC_MAX_BITS_PER_KEY 32u
 
+/* How a key's k bit addresses F(x) are chosen (Section 3.3):
+ *   RANDOM    f_i(x), i = 1..k, are independent hashes into [512] (the top
+ *             9 bits of a_i * x); two of them may coincide, so a key can
+ *             set and test fewer than k distinct bits.
+ *   DISTINCT  App. B: f_i is hashed into [512 - i + 1] and names the f_i-th
+ *             address not taken by f_1..f_{i-1}, so every key sets exactly
+ *             k distinct bits, a uniform k-subset of [512]. The bit hash
+ *             multipliers must be coprime to their moduli 512 - i + 1. It
+ *             costs k(k-1)/2 compare steps per key in the hashing phase. */
+typedef enum {
+    BBFC_BITS_RANDOM = 0,
+    BBFC_BITS_DISTINCT = 1
+} bbfc_bit_selection;
+
+/* Everything that defines a filter, for bbfc_create_config. */
+typedef struct {
+    uint64_t n_blocks;
+    uint32_t choices;
+    uint32_t bits_per_key;
+    bbfc_cost cost;
+    int32_t bit_selection;      /* a bbfc_bit_selection */
+    uint64_t seed;              /* multiplier stream (see bbfc_create_seeded) */
+    const uint64_t *block_mult; /* host [choices], or null: drawn from seed */
+    const uint64_t *bit_mult;   /* host [bits_per_key], or null: drawn from seed */
+} bbfc_config;
+
 /* Create an empty filter of n_blocks 512-bit blocks (64 bytes each, the
  * allocation is 256-byte aligned) on the current HIP device, with `choices`
  * candidate blocks per key (c, Section 3.1) and `bits_per_key` bit hashes
@@ -110,6 +136,15 @@ bbfc_status bbfc_create_seeded(uint64_t n_blocks, uint32_t choices, uint32_t bit
 bbfc_status bbfc_create_with_multipliers(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key,
                                          bbfc_cost cost, const uint64_t *block_mult,
                                          const uint64_t *bit_mult, bbfc_handle *out);
+
+/* The general constructor: shape and cost as bbfc_create, the bit
+ * selection strategy, and multipliers given or drawn. Multipliers are drawn
+ * as in bbfc_create_seeded, except that with DISTINCT the i-th bit
+ * multiplier (i from 1) is drawn coprime to 512 - i + 1. Given arrays are
+ * checked (block multipliers coprime to n_blocks, bit multipliers coprime
+ * to their moduli) and copied. Errors: as bbfc_create, plus EINVAL for a
+ * null cfg or an unknown bit_selection. */
+bbfc_status bbfc_create_config(const bbfc_config *cfg, bbfc_handle *out);
 
 /* Synchronise the device, then free the filter. A null handle is EINVAL. */
 bbfc_status bbfc_destroy(bbfc_handle h);
@@ -155,6 +190,15 @@ bbfc_status bbfc_download(bbfc_handle h, uint64_t *h_words, hipStream_t stream);
  * cost->param receives the resolved value (never NaN). */
 bbfc_status bbfc_get_params(bbfc_handle h, uint64_t *n_blocks, uint32_t *choices, uint32_t *bits_per_key,
                             bbfc_cost *cost, uint64_t *block_mult, uint64_t *bit_mult);
+
+/* The filter's bbfc_bit_selection. */
+bbfc_status bbfc_get_bit_selection(bbfc_handle h, int32_t *bit_selection);
+
+/* Load histogram (App. C, the per-block load figure): d_hist[j], j = 0..512
+ * (device memory, 513 uint64, caller-owned) receives the number of blocks
+ * with exactly j bits set. The call overwrites d_hist with a fill kernel and
+ * accumulates with atomics, stream-ordered on `stream`. */
+bbfc_status bbfc_load_histogram(bbfc_handle h, uint64_t *d_hist, hipStream_t stream);
 
 /* Device address of the filter words (8*n_blocks uint64, owned by the
  * library, valid until bbfc_destroy). */
@@ -439,6 +483,13 @@ uint64_t bbfc_host_block_hash(uint64_t n_blocks, uint64_t a, uint64_t x);
 
 /* Bit address f(x) in [0, 512) for multiplier a (Section 3.4, b = 2^9). */
 uint32_t bbfc_host_bit_hash(uint64_t a, uint64_t x);
+
+/* The key's address set F(x) (Section 3.3, eq. bitset; App. B for
+ * DISTINCT) as a 512-bit mask: bit f is bit f%64 of out[f/64], out[8] host
+ * memory. bit_mult[k] are the bit multipliers. Errors: EINVAL for null
+ * pointers, k outside [1, 32] or an unknown bit_selection. */
+bbfc_status bbfc_host_key_mask(const uint64_t *bit_mult, uint32_t k, int32_t bit_selection, uint64_t x,
+                               uint64_t *out);
 
 #ifdef __cplusplus
 }

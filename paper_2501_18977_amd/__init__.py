@@ -31,6 +31,7 @@ __all__ = [
     "kmer_count",
     "kmer_keys",
     "host_bit_hash",
+    "host_key_mask",
     "lib",
     "library_path",
     "probe_gather",
@@ -40,6 +41,8 @@ __all__ = [
 ]
 
 COST_NONE, COST_MIX, COST_LA, COST_EXP = 0, 1, 2, 3
+BITS_RANDOM, BITS_DISTINCT = 0, 1
+_BITS_BY_NAME = {"random": BITS_RANDOM, "distinct": BITS_DISTINCT}
 OP_INSERT, OP_QUERY = 0, 1
 OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT = 1, 2
 _COST_BY_NAME = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
@@ -56,6 +59,12 @@ class BBFCError(RuntimeError):
 
 class _Cost(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("param", ctypes.c_double)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_uint64), ("choices", ctypes.c_uint32), ("bits_per_key", ctypes.c_uint32),
+                ("cost", _Cost), ("bit_selection", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("block_mult", ctypes.c_void_p), ("bit_mult", ctypes.c_void_p)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -94,6 +103,10 @@ def lib() -> ctypes.CDLL:
         "bbfc_create": (_st, [_u64, _u32, _u32, _Cost, _vp]),
         "bbfc_create_seeded": (_st, [_u64, _u32, _u32, _Cost, _u64, _vp]),
         "bbfc_create_with_multipliers": (_st, [_u64, _u32, _u32, _Cost, _vp, _vp, _vp]),
+        "bbfc_create_config": (_st, [_vp, _vp]),
+        "bbfc_get_bit_selection": (_st, [_vp, _vp]),
+        "bbfc_load_histogram": (_st, [_vp, _vp, _vp]),
+        "bbfc_host_key_mask": (_st, [_vp, _u32, ctypes.c_int32, _u64, _vp]),
         "bbfc_destroy": (_st, [_vp]),
         "bbfc_insert": (_st, [_vp, _vp, _u64, _vp]),
         "bbfc_insert_deterministic": (_st, [_vp, _vp, _u64, _vp]),
@@ -215,6 +228,23 @@ def host_bit_hash(a: int, x: int) -> int:
     return int(lib().bbfc_host_bit_hash(a, x))
 
 
+def _bits_id(bit_selection) -> int:
+    if isinstance(bit_selection, str):
+        return _BITS_BY_NAME[bit_selection]
+    return int(bit_selection)
+
+
+def host_key_mask(bit_mult, x: int, bit_selection="random"):
+    """F(x) as 8 uint64 words (numpy), computed by the library's host build
+    of the kernels' bit selection code."""
+    import numpy as np
+
+    am = (ctypes.c_uint64 * len(bit_mult))(*[int(v) for v in bit_mult])
+    out = np.zeros(8, dtype=np.uint64)
+    _check(lib().bbfc_host_key_mask(am, len(bit_mult), _bits_id(bit_selection), x, out.ctypes.data))
+    return out
+
+
 @dataclass(frozen=True)
 class Params:
     n_blocks: int
@@ -224,17 +254,30 @@ class Params:
     cost_param: float
     block_mult: tuple
     bit_mult: tuple
+    bit_selection: int = BITS_RANDOM
 
 
 class Filter:
     """One filter resident in device memory (owned by the library)."""
 
     def __init__(self, n_blocks: int, choices: int, bits_per_key: int, cost="none", cost_param=None, *,
-                 seed: int | None = None, block_mult=None, bit_mult=None):
+                 seed: int | None = None, block_mult=None, bit_mult=None, bit_selection="random"):
         L = lib()
         h = ctypes.c_void_p()
         cs = _cost_struct(cost, cost_param)
-        if block_mult is not None or bit_mult is not None:
+        sel = _bits_id(bit_selection)
+        if sel != BITS_RANDOM:
+            if block_mult is not None and len(block_mult) != choices:
+                raise ValueError("block_mult needs `choices` entries")
+            if bit_mult is not None and len(bit_mult) != bits_per_key:
+                raise ValueError("bit_mult needs `bits_per_key` entries")
+            bm = (ctypes.c_uint64 * choices)(*[int(v) for v in block_mult]) if block_mult is not None else None
+            am = (ctypes.c_uint64 * bits_per_key)(*[int(v) for v in bit_mult]) if bit_mult is not None else None
+            cfg = _Config(n_blocks, choices, bits_per_key, cs, sel, 0 if seed is None else seed,
+                          ctypes.cast(bm, ctypes.c_void_p) if bm is not None else None,
+                          ctypes.cast(am, ctypes.c_void_p) if am is not None else None)
+            _check(L.bbfc_create_config(ctypes.byref(cfg), ctypes.byref(h)))
+        elif block_mult is not None or bit_mult is not None:
             if block_mult is None or bit_mult is None:
                 raise ValueError("give both block_mult and bit_mult")
             bm = (ctypes.c_uint64 * len(block_mult))(*[int(v) for v in block_mult])
@@ -257,7 +300,10 @@ class Filter:
         am = (ctypes.c_uint64 * 32)()
         _check(lib().bbfc_get_params(self._h, ctypes.byref(M), ctypes.byref(c), ctypes.byref(k), ctypes.byref(cs),
                                      bm, am))
-        return Params(M.value, c.value, k.value, cs.kind, cs.param, tuple(bm[: c.value]), tuple(am[: k.value]))
+        sel = ctypes.c_int32()
+        _check(lib().bbfc_get_bit_selection(self._h, ctypes.byref(sel)))
+        return Params(M.value, c.value, k.value, cs.kind, cs.param, tuple(bm[: c.value]), tuple(am[: k.value]),
+                      sel.value)
 
     @property
     def handle(self):
@@ -346,6 +392,18 @@ class Filter:
 
     def clear(self, stream=None) -> None:
         _check(lib().bbfc_clear(self.handle, _stream_handle(stream)))
+
+    def load_histogram(self, out=None, stream=None):
+        """Blocks per popcount j = 0..512 as an int64 GPU tensor of 513."""
+        import torch
+
+        if out is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+            out = torch.empty(513, dtype=torch.int64, device=dev)
+        elif out.numel() < 513:
+            raise ValueError("histogram needs 513 entries")
+        _check(lib().bbfc_load_histogram(self.handle, out.data_ptr(), _stream_handle(stream)))
+        return out[:513]
 
     def download(self, stream=None):
         """All filter words as a numpy uint64 array (synchronises)."""

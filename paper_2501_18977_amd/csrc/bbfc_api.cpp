@@ -164,25 +164,54 @@ bbfc_status check_shape(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_co
     return BBFC_OK;
 }
 
-bbfc_status create_impl(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_cost cost, const uint64_t *block_mult,
-                        const uint64_t *bit_mult, bbfc_handle *out)
+// Modulus of bit hash i (counted from 0): 512, or 512 - i under distinct
+// selection (App. B).
+uint64_t bit_modulus(int32_t bit_selection, uint32_t i)
+{
+    return bit_selection == BBFC_BITS_DISTINCT ? 512u - i : 512u;
+}
+
+// SplitMix64 draws, made odd; draws below 2^32 or sharing a factor with the
+// modulus are skipped. Block multipliers first, then bit multipliers.
+void derive_multipliers(uint64_t seed, uint64_t n_blocks, uint32_t choices, uint32_t k, int32_t bit_selection,
+                        uint64_t *bm, uint64_t *am)
+{
+    uint64_t state = seed;
+    for (uint32_t i = 0; i < choices;) {
+        const uint64_t a = splitmix64(state) | 1;
+        if (a >= (1ull << 32) && gcd_u64(a, n_blocks) == 1)
+            bm[i++] = a;
+    }
+    for (uint32_t i = 0; i < k;) {
+        const uint64_t a = splitmix64(state) | 1;
+        if (a >= (1ull << 32) && gcd_u64(a, bit_modulus(bit_selection, i)) == 1)
+            am[i++] = a;
+    }
+}
+
+bbfc_status create_impl(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_cost cost, int32_t bit_selection,
+                        const uint64_t *block_mult, const uint64_t *bit_mult, bbfc_handle *out)
 {
     if (out == nullptr)
         return fail(BBFC_EINVAL, "out handle pointer is null");
     bbfc_status st = check_shape(n_blocks, choices, k, cost);
     if (st != BBFC_OK)
         return st;
+    if (bit_selection != BBFC_BITS_RANDOM && bit_selection != BBFC_BITS_DISTINCT)
+        return fail(BBFC_EINVAL, "unknown bit selection %d", (int)bit_selection);
     for (uint32_t i = 0; i < choices; ++i)
         if (gcd_u64(block_mult[i], n_blocks) != 1 && n_blocks != 1)
             return fail(BBFC_EINVAL, "block multiplier %u is not coprime to n_blocks", i);
     for (uint32_t i = 0; i < k; ++i)
-        if ((bit_mult[i] & 1) == 0)
-            return fail(BBFC_EINVAL, "bit multiplier %u is even", i);
+        if (gcd_u64(bit_mult[i], bit_modulus(bit_selection, i)) != 1)
+            return fail(BBFC_EINVAL, "bit multiplier %u is not coprime to its modulus %llu", i,
+                        (unsigned long long)bit_modulus(bit_selection, i));
 
     auto *f = new bbfc_filter();
     f->M = n_blocks;
     f->c = choices;
     f->k = k;
+    f->bit_selection = bit_selection;
     f->cost_kind = choices > 1 ? cost.kind : BBFC_COST_NONE;
     f->cost_param = choices > 1 ? (isnan(cost.param) ? default_param(cost.kind, k) : cost.param) : 0.0;
     memcpy(f->block_mult, block_mult, choices * sizeof(uint64_t));
@@ -253,7 +282,26 @@ bbfc_status bbfc_create_with_multipliers(uint64_t n_blocks, uint32_t choices, ui
 {
     if (block_mult == nullptr || bit_mult == nullptr)
         return fail(BBFC_EINVAL, "multiplier arrays must not be null");
-    return create_impl(n_blocks, choices, bits_per_key, cost, block_mult, bit_mult, out);
+    return create_impl(n_blocks, choices, bits_per_key, cost, BBFC_BITS_RANDOM, block_mult, bit_mult, out);
+}
+
+bbfc_status bbfc_create_config(const bbfc_config *cfg, bbfc_handle *out)
+{
+    if (cfg == nullptr)
+        return fail(BBFC_EINVAL, "null config");
+    bbfc_status st = check_shape(cfg->n_blocks, cfg->choices, cfg->bits_per_key, cfg->cost);
+    if (st != BBFC_OK)
+        return st;
+    if (cfg->bit_selection != BBFC_BITS_RANDOM && cfg->bit_selection != BBFC_BITS_DISTINCT)
+        return fail(BBFC_EINVAL, "unknown bit selection %d", (int)cfg->bit_selection);
+    uint64_t bm[BBFC_MAX_CHOICES];
+    uint64_t am[BBFC_MAX_BITS_PER_KEY];
+    derive_multipliers(cfg->seed, cfg->n_blocks, cfg->choices, cfg->bits_per_key, cfg->bit_selection, bm, am);
+    if (cfg->block_mult)
+        memcpy(bm, cfg->block_mult, cfg->choices * sizeof(uint64_t));
+    if (cfg->bit_mult)
+        memcpy(am, cfg->bit_mult, cfg->bits_per_key * sizeof(uint64_t));
+    return create_impl(cfg->n_blocks, cfg->choices, cfg->bits_per_key, cfg->cost, cfg->bit_selection, bm, am, out);
 }
 
 bbfc_status bbfc_create_seeded(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
@@ -264,18 +312,8 @@ bbfc_status bbfc_create_seeded(uint64_t n_blocks, uint32_t choices, uint32_t bit
         return st;
     uint64_t bm[BBFC_MAX_CHOICES];
     uint64_t am[BBFC_MAX_BITS_PER_KEY];
-    uint64_t state = seed;
-    for (uint32_t i = 0; i < choices;) {
-        const uint64_t a = splitmix64(state) | 1;
-        if (a >= (1ull << 32) && gcd_u64(a, n_blocks) == 1)
-            bm[i++] = a;
-    }
-    for (uint32_t i = 0; i < bits_per_key;) {
-        const uint64_t a = splitmix64(state) | 1;
-        if (a >= (1ull << 32))
-            am[i++] = a;
-    }
-    return create_impl(n_blocks, choices, bits_per_key, cost, bm, am, out);
+    derive_multipliers(seed, n_blocks, choices, bits_per_key, BBFC_BITS_RANDOM, bm, am);
+    return create_impl(n_blocks, choices, bits_per_key, cost, BBFC_BITS_RANDOM, bm, am, out);
 }
 
 bbfc_status bbfc_create(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
@@ -460,6 +498,23 @@ bbfc_status bbfc_get_params(bbfc_handle h, uint64_t *n_blocks, uint32_t *choices
     if (bit_mult)
         memcpy(bit_mult, h->bit_mult, h->k * sizeof(uint64_t));
     return BBFC_OK;
+}
+
+bbfc_status bbfc_get_bit_selection(bbfc_handle h, int32_t *bit_selection)
+{
+    if (h == nullptr || bit_selection == nullptr)
+        return fail(BBFC_EINVAL, "null handle or output pointer");
+    *bit_selection = h->bit_selection;
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_load_histogram(bbfc_handle h, uint64_t *d_hist, hipStream_t stream)
+{
+    if (h == nullptr || d_hist == nullptr)
+        return fail(BBFC_EINVAL, "null handle or histogram pointer");
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_load_histogram(*h, d_hist, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching the load histogram");
 }
 
 bbfc_status bbfc_get_words(bbfc_handle h, uint64_t **d_words)
@@ -713,6 +768,25 @@ uint64_t bbfc_host_block_hash(uint64_t n_blocks, uint64_t a, uint64_t x)
 uint32_t bbfc_host_bit_hash(uint64_t a, uint64_t x)
 {
     return bbfc::bit_hash(a, x);
+}
+
+bbfc_status bbfc_host_key_mask(const uint64_t *bit_mult, uint32_t k, int32_t bit_selection, uint64_t x,
+                               uint64_t *out)
+{
+    if (bit_mult == nullptr || out == nullptr)
+        return fail(BBFC_EINVAL, "null multiplier or output pointer");
+    if (k < 1 || k > BBFC_MAX_BITS_PER_KEY)
+        return fail(BBFC_EINVAL, "bits_per_key must be in [1, %u], got %u", BBFC_MAX_BITS_PER_KEY, k);
+    if (bit_selection != BBFC_BITS_RANDOM && bit_selection != BBFC_BITS_DISTINCT)
+        return fail(BBFC_EINVAL, "unknown bit selection %d", (int)bit_selection);
+    for (int w = 0; w < 8; ++w)
+        out[w] = 0;
+    auto set_bit = [out](uint32_t f) { out[f >> 6] |= 1ull << (f & 63); };
+    if (bit_selection == BBFC_BITS_DISTINCT)
+        bbfc::distinct_bits(bit_mult, k, x, set_bit);
+    else
+        bbfc::random_bits(bit_mult, k, x, set_bit);
+    return BBFC_OK;
 }
 
 } // extern "C"

@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kWGSize) void batch_query_kernel(const BatchFilter 
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = wave_index();
     uint32_t f = 0;
-    auto unit = [&](uint64_t u) {
+    auto unit = [&](uint64_t u) __attribute__((always_inline)) {
         while (f + 1 < n_filters && filt[f + 1].unit_off <= u)
             ++f;
         const BatchFilter &bf = filt[f];

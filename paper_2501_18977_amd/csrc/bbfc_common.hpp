@@ -8,6 +8,8 @@
 
 #include <stdint.h>
 
+#include <utility>
+
 #include <hip/hip_runtime.h>
 
 #include "../../include/bbfc.h"
@@ -50,7 +52,7 @@ inline FastMod make_fastmod(uint64_t d)
     return fm;
 }
 
-__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
+__host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     return __umul64hi(a, b);
@@ -59,13 +61,13 @@ __host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
 #endif
 }
 
-__host__ __device__ inline uint64_t fastdiv(uint64_t n, uint64_t magic, uint32_t sh1, uint32_t sh2)
+__host__ __device__ __forceinline__ uint64_t fastdiv(uint64_t n, uint64_t magic, uint32_t sh1, uint32_t sh2)
 {
     const uint64_t t = mulhi64(magic, n);
     return (t + ((n - t) >> sh1)) >> sh2;
 }
 
-__host__ __device__ inline uint64_t fastmod(uint64_t n, uint64_t d, uint64_t magic, uint32_t sh1, uint32_t sh2)
+__host__ __device__ __forceinline__ uint64_t fastmod(uint64_t n, uint64_t d, uint64_t magic, uint32_t sh1, uint32_t sh2)
 {
     uint64_t t = mulhi64(magic, n);
     uint64_t q = (t + ((n - t) >> sh1)) >> sh2;
@@ -84,15 +86,16 @@ struct KParams {
     uint32_t k;
     uint32_t mode;          // HashMode of M
     uint32_t c;             // choices (informational; kernels take C as a template)
+    uint32_t distinct;      // bit selection: 0 random, 1 distinct
     uint64_t block_mult[BBFC_MAX_CHOICES];
     uint64_t bit_mult[BBFC_MAX_BITS_PER_KEY];
 };
 
 template <int MODE>
-__host__ __device__ inline uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x);
+__host__ __device__ __forceinline__ uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x);
 
 // The hash mode read from the parameters (uniform across a wavefront).
-__host__ __device__ inline uint64_t block_hash_rt(const KParams &p, uint64_t a, uint64_t x)
+__host__ __device__ __forceinline__ uint64_t block_hash_rt(const KParams &p, uint64_t a, uint64_t x)
 {
     switch (p.mode) {
     case kModeOne:
@@ -107,7 +110,7 @@ __host__ __device__ inline uint64_t block_hash_rt(const KParams &p, uint64_t a, 
 }
 
 template <int MODE>
-__host__ __device__ inline uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x)
+__host__ __device__ __forceinline__ uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x)
 {
     uint64_t prod = a * x;
     if constexpr (MODE == kModeOne) {
@@ -122,9 +125,94 @@ __host__ __device__ inline uint64_t block_hash(const KParams &p, uint64_t a, uin
 }
 
 // Bit address in [0, 512): the top 9 bits of a*x (b = 512 = 2^9).
-__host__ __device__ inline uint32_t bit_hash(uint64_t a, uint64_t x)
+__host__ __device__ __forceinline__ uint32_t bit_hash(uint64_t a, uint64_t x)
 {
     return (uint32_t)((a * x) >> 55);
+}
+
+// ------------------------------------------------- distinct bit selection
+//
+// Section 3.3 / App. B: the i-th value (i counted from 0) is hashed into
+// [512 - i] and then names the raw-th address not taken by the earlier ones,
+// so a key gets exactly k distinct addresses, a uniform k-subset of [512].
+// The paper reaches that address by insertion sort. Here each earlier
+// address s keeps fb(s), the number of free addresses below it; s lies
+// below the new address v exactly when fb(s) <= raw, so
+//     v = raw + #{ s : fb(s) <= raw },
+// and afterwards every s above v loses one free address below it. That is
+// k(k-1)/2 independent compare/add pairs with no data-dependent indexing.
+
+// Granlund-Montgomery magic for a divisor d in (256, 512] (l = 9):
+// floor(2^64 (512 - d) / d) + 1 by binary long division.
+constexpr uint64_t small_magic(uint64_t d)
+{
+    uint64_t q = 0;
+    uint64_t rem = 512 - d;
+    for (int b = 0; b < 64; ++b) {
+        rem <<= 1;
+        q <<= 1;
+        if (rem >= d) {
+            rem -= d;
+            q |= 1;
+        }
+    }
+    return q + 1;
+}
+
+// f_i(x) into [512 - I] with the hash of Section 3.4 (I = 0: top 9 bits).
+template <uint32_t I>
+__host__ __device__ __forceinline__ uint32_t distinct_raw(uint64_t a, uint64_t x)
+{
+    const uint64_t prod = a * x;
+    if constexpr (I == 0) {
+        return (uint32_t)(prod >> 55);
+    } else {
+        constexpr uint64_t d = 512 - I;
+        constexpr uint64_t magic = small_magic(d);
+        const uint64_t n = (d & 1) ? prod : (prod ^ (prod >> 32));
+        return (uint32_t)fastmod(n, d, magic, 1, 8);
+    }
+}
+
+template <uint32_t I, typename Emit>
+__host__ __device__ __forceinline__ void distinct_step(uint64_t a, uint64_t x, uint32_t (&fb)[BBFC_MAX_BITS_PER_KEY],
+                                              Emit &emit)
+{
+    const uint32_t raw = distinct_raw<I>(a, x);
+    uint32_t v = raw;
+#pragma unroll
+    for (uint32_t j = 0; j < I; ++j) {
+        const bool below = fb[j] <= raw;
+        v += below ? 1u : 0u;
+        fb[j] -= below ? 0u : 1u;
+    }
+    fb[I] = raw;
+    emit(v);
+}
+
+template <typename Emit, uint32_t... I>
+__host__ __device__ __forceinline__ void distinct_bits_seq(const uint64_t *mult, uint32_t k, uint64_t x, Emit &emit,
+                                                  std::integer_sequence<uint32_t, I...>)
+{
+    uint32_t fb[BBFC_MAX_BITS_PER_KEY];
+    (void)((I < k ? (distinct_step<I>(mult[I], x, fb, emit), true) : false) && ...);
+}
+
+// Calls emit(v) once for each of the k distinct addresses of key x.
+template <typename Emit>
+__host__ __device__ __forceinline__ void distinct_bits(const uint64_t *mult, uint32_t k, uint64_t x, Emit &&emit)
+{
+    distinct_bits_seq(mult, k, x, emit, std::make_integer_sequence<uint32_t, BBFC_MAX_BITS_PER_KEY>{});
+}
+
+// Calls emit(f_i(x)) for the k random-strategy addresses (may repeat).
+template <typename Emit>
+__host__ __device__ __forceinline__ void random_bits(const uint64_t *mult, uint32_t k, uint64_t x, Emit &&emit)
+{
+#pragma unroll
+    for (int i = 0; i < (int)BBFC_MAX_BITS_PER_KEY; ++i)
+        if ((uint32_t)i < k)
+            emit(bit_hash(mult[i], x));
 }
 
 } // namespace bbfc

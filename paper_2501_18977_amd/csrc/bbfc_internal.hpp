@@ -15,6 +15,7 @@ struct bbfc_filter {
     double cost_param = 0.0;
     uint64_t block_mult[BBFC_MAX_CHOICES] = {};
     uint64_t bit_mult[BBFC_MAX_BITS_PER_KEY] = {};
+    int32_t bit_selection = BBFC_BITS_RANDOM;
     int hash_mode = bbfc::kModeOne;
     bbfc::FastMod fm{};
     uint32_t pow2_shift = 0;
@@ -63,6 +64,7 @@ hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out,
                         hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s);
+hipError_t launch_load_histogram(const bbfc_filter &f, uint64_t *hist, hipStream_t s);
 
 // Canonical q-grams of a 2-bit packed sequence cut into segments (see
 // bbfc_kmer_keys): fused insert and query, and the keys written out.

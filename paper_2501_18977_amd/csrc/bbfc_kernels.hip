@@ -128,6 +128,33 @@ __global__ void fill_zero_kernel(uint64_t *p, uint64_t n_words)
         p[i] = 0;
 }
 
+// Popcount histogram of the blocks: eight lanes read one block's eight
+// words (coalesced), sum their popcounts with lane swizzles inside the
+// group, and bump a workgroup histogram in LDS; non-empty bins are added to
+// the global histogram at the end. The grid stride is a multiple of 8
+// words, so every group of eight lanes stays on one block.
+__global__ __launch_bounds__(256) void load_histogram_kernel(const uint64_t *__restrict__ words, uint64_t n_words,
+                                                            unsigned long long *__restrict__ hist)
+{
+    __shared__ uint32_t sh[513];
+    for (uint32_t i = threadIdx.x; i < 513; i += blockDim.x)
+        sh[i] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < n_words; w += stride) {
+        uint32_t pc = (uint32_t)__popcll(words[w]);
+        pc += __shfl_xor(pc, 1);
+        pc += __shfl_xor(pc, 2);
+        pc += __shfl_xor(pc, 4);
+        if ((threadIdx.x & 7) == 0)
+            atomicAdd(&sh[pc], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 513; i += blockDim.x)
+        if (sh[i])
+            atomicAdd(&hist[i], (unsigned long long)sh[i]);
+}
+
 // ------------------------------------------------------------ launchers
 
 KParams make_kparams(const bbfc_filter &f)
@@ -143,6 +170,7 @@ KParams make_kparams(const bbfc_filter &f)
     p.k = f.k;
     p.mode = (uint32_t)f.hash_mode;
     p.c = f.c;
+    p.distinct = f.bit_selection == BBFC_BITS_DISTINCT ? 1u : 0u;
     for (uint32_t i = 0; i < f.c; ++i)
         p.block_mult[i] = f.block_mult[i];
     for (uint32_t i = 0; i < f.k; ++i)
@@ -369,6 +397,21 @@ hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
 {
     return query_any(f, ArrayKeys{keys}, n, out, s);
+}
+
+hipError_t launch_load_histogram(const bbfc_filter &f, uint64_t *hist, hipStream_t s)
+{
+    hipError_t e = launch_fill_zero(hist, 513, s);
+    if (e != hipSuccess)
+        return e;
+    const uint64_t n_words = f.M * 8; // a multiple of 8: groups of 8 lanes never straddle the end
+    uint64_t blocks = (n_words + 255) / 256;
+    const uint64_t cap = (uint64_t)(f.num_cus > 0 ? f.num_cus : 256) * 8;
+    if (blocks > cap)
+        blocks = cap;
+    hipLaunchKernelGGL(load_histogram_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, f.d_words, n_words,
+                       reinterpret_cast<unsigned long long *>(hist));
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s)

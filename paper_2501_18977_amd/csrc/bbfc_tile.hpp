@@ -49,7 +49,7 @@ constexpr int kSlotDw = 18;      // LDS dwords per key mask (16 used; stride 18 
                                  // round's groups over disjoint bank pairs)
 constexpr int kRankStride = 513; // j in [0, 512]
 
-__device__ inline void wave_sync()
+__device__ __forceinline__ void wave_sync()
 {
     // LDS operations of one wavefront execute in order; this only keeps the
     // compiler from moving LDS accesses across the phase boundary.
@@ -60,7 +60,7 @@ __device__ inline void wave_sync()
 
 // Sum over each aligned group of LPK (4 or 8) lanes, result in every lane.
 template <int LPK>
-__device__ inline uint32_t group_sum(uint32_t v)
+__device__ __forceinline__ uint32_t group_sum(uint32_t v)
 {
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false); // quad_perm 1,0,3,2
     v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false); // quad_perm 2,3,0,1
@@ -71,7 +71,7 @@ __device__ inline uint32_t group_sum(uint32_t v)
 
 // Bit LPK*g of the result is the AND of the LPK ballot bits of group g.
 template <int LPK>
-__device__ inline uint64_t group_all(uint64_t b)
+__device__ __forceinline__ uint64_t group_all(uint64_t b)
 {
     b &= b >> 1;
     b &= b >> 2;
@@ -89,7 +89,7 @@ struct Lanes {
     static constexpr uint64_t kLsb = LPK == 8 ? 0x0101010101010101ull : 0x1111111111111111ull;
 };
 
-__device__ inline uint32_t popc64(uint64_t v)
+__device__ __forceinline__ uint32_t popc64(uint64_t v)
 {
     return (uint32_t)__popcll(v);
 }
@@ -141,7 +141,7 @@ struct KmerKeys {
 // Phase A: lane t handles key base + t; keys past n are hashed as key 0,
 // whose candidate blocks are in range, so later loads need no guard.
 template <int C, typename Src>
-__device__ inline void phase_a(const KParams &p, const Src &src, uint64_t n, uint64_t base, uint32_t lane,
+__device__ __forceinline__ void phase_a(const KParams &p, const Src &src, uint64_t n, uint64_t base, uint32_t lane,
                                uint32_t *smask, uint64_t *sblk)
 {
     const uint64_t idx = base + lane;
@@ -152,20 +152,18 @@ __device__ inline void phase_a(const KParams &p, const Src &src, uint64_t n, uin
 #pragma unroll
     for (int d = 0; d < 16; ++d)
         slot[d] = 0;
-#pragma unroll
-    for (int i = 0; i < (int)BBFC_MAX_BITS_PER_KEY; ++i) {
-        if ((uint32_t)i < p.k) {
-            const uint32_t f = bit_hash(p.bit_mult[i], x);
-            atomicOr(slot + (f >> 5), 1u << (f & 31));
-        }
-    }
+    auto set_bit = [slot](uint32_t f) { atomicOr(slot + (f >> 5), 1u << (f & 31)); };
+    if (p.distinct)
+        distinct_bits(p.bit_mult, p.k, x, set_bit);
+    else
+        random_bits(p.bit_mult, p.k, x, set_bit);
 #pragma unroll
     for (int i = 0; i < C; ++i)
         sblk[lane * C + i] = block_hash_rt(p, p.block_mult[i], x);
 }
 
 template <int KW>
-__device__ inline void mask_words(const uint32_t *smask, uint32_t t, uint32_t w0, uint64_t (&m)[KW])
+__device__ __forceinline__ void mask_words(const uint32_t *smask, uint32_t t, uint32_t w0, uint64_t (&m)[KW])
 {
 #pragma unroll
     for (int q = 0; q < KW; ++q) {
@@ -176,7 +174,7 @@ __device__ inline void mask_words(const uint32_t *smask, uint32_t t, uint32_t w0
 
 // Words w0 .. w0+KW-1 of a block (16-byte aligned when KW == 2).
 template <int KW>
-__device__ inline void load_block(const uint64_t *src, uint64_t (&B)[KW])
+__device__ __forceinline__ void load_block(const uint64_t *src, uint64_t (&B)[KW])
 {
     if constexpr (KW == 1) {
         B[0] = src[0];
@@ -188,7 +186,7 @@ __device__ inline void load_block(const uint64_t *src, uint64_t (&B)[KW])
 }
 
 template <int KW>
-__device__ inline bool holds(const uint64_t (&B)[KW], const uint64_t (&m)[KW])
+__device__ __forceinline__ bool holds(const uint64_t (&B)[KW], const uint64_t (&m)[KW])
 {
     bool ok = true;
 #pragma unroll
@@ -205,7 +203,7 @@ __device__ inline bool holds(const uint64_t (&B)[KW], const uint64_t (&m)[KW])
 // groups whose key candidates 1..i did not answer (same answers, fewer
 // random lines).
 template <int C, int LPK, int T, bool EARLY, typename Src>
-__device__ inline void query_tiles(const KParams &p, const Src &keys, uint64_t n, uint64_t base,
+__device__ __forceinline__ void query_tiles(const KParams &p, const Src &keys, uint64_t n, uint64_t base,
                                    uint64_t *__restrict__ out_tile, uint32_t lane, uint32_t *smask, uint64_t *sblk)
 {
     using L = Lanes<LPK>;
@@ -303,7 +301,7 @@ struct JA {
 };
 
 template <int C, int LPK, int KW>
-__device__ inline JA<C> reduce_ja(const uint64_t (&B)[C][KW], const uint64_t (&m)[KW])
+__device__ __forceinline__ JA<C> reduce_ja(const uint64_t (&B)[C][KW], const uint64_t (&m)[KW])
 {
     JA<C> r;
 #pragma unroll
@@ -327,7 +325,7 @@ __device__ inline JA<C> reduce_ja(const uint64_t (&B)[C][KW], const uint64_t (&m
 
 // Choice receiving the key, or -1 if some candidate already holds F(x).
 template <int C>
-__device__ inline int decide(const JA<C> &ja, const uint16_t *rank)
+__device__ __forceinline__ int decide(const JA<C> &ja, const uint16_t *rank)
 {
     bool present = false;
 #pragma unroll
@@ -352,7 +350,7 @@ __device__ inline int decide(const JA<C> &ja, const uint16_t *rank)
     }
 }
 
-__device__ inline void atomic_or_word(uint64_t *addr, uint64_t v)
+__device__ __forceinline__ void atomic_or_word(uint64_t *addr, uint64_t v)
 {
     __hip_atomic_fetch_or(addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -360,7 +358,7 @@ __device__ inline void atomic_or_word(uint64_t *addr, uint64_t v)
 // B[i][q] selected with masks rather than an index, so the candidates stay in
 // registers (an indexed select would be lowered to a private-memory array).
 template <int C, int KW>
-__device__ inline uint64_t pick(const uint64_t (&B)[C][KW], int i, int q)
+__device__ __forceinline__ uint64_t pick(const uint64_t (&B)[C][KW], int i, int q)
 {
     uint64_t v = 0;
 #pragma unroll
@@ -371,7 +369,7 @@ __device__ inline uint64_t pick(const uint64_t (&B)[C][KW], int i, int q)
 
 // Racing insert of T consecutive tiles whose first key is keys[base].
 template <int C, int LPK, int T, typename Src>
-__device__ inline void insert_tiles(const KParams &p, const uint16_t *rank, const Src &keys, uint64_t n,
+__device__ __forceinline__ void insert_tiles(const KParams &p, const uint16_t *rank, const Src &keys, uint64_t n,
                                     uint64_t base, uint32_t lane, uint32_t *smask, uint64_t *sblk)
 {
     using L = Lanes<LPK>;

@@ -136,8 +136,39 @@ def test_create_rejects_bad_shapes_before_touching_the_device(args, needle):
 def test_create_rejects_bad_multipliers():
     with pytest.raises(bbfc.BBFCError, match="coprime"):
         bbfc.Filter(6, 2, 4, "exp", block_mult=[3 | (1 << 40), 5 | (1 << 40)], bit_mult=[(1 << 40) + 1] * 4)
-    with pytest.raises(bbfc.BBFCError, match="even"):
+    with pytest.raises(bbfc.BBFCError, match="bit multiplier 1 is not coprime to its modulus 512"):
         bbfc.Filter(8, 2, 2, "exp", block_mult=[(1 << 40) + 1] * 2, bit_mult=[(1 << 40) + 1, 1 << 40])
+    # distinct selection: bit hash 1 reduces modulo 511 = 7 * 73
+    with pytest.raises(bbfc.BBFCError, match="bit multiplier 1 is not coprime to its modulus 511"):
+        bbfc.Filter(8, 2, 2, "exp", block_mult=[(1 << 40) + 1] * 2, bit_mult=[(1 << 40) + 1, 7 * ((1 << 40) + 1)],
+                    bit_selection="distinct")
+    with pytest.raises(bbfc.BBFCError, match="unknown bit selection"):
+        bbfc.Filter(8, 2, 2, "exp", bit_selection=5)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 14, 17, 20, 31, 32])
+@pytest.mark.parametrize("sel", ["random", "distinct"])
+def test_key_mask_source_matches_oracle(k, sel):
+    """The kernels' bit selection code (compiled for the host) gives the
+    oracle's F(x), for both strategies (Section 3.3, App. B). The device
+    computes distinct addresses by counting free addresses, the oracle by
+    the paper's insertion sort: they share nothing but the definition."""
+    distinct = sel == "distinct"
+    am = workload.draw_multipliers(k + 7, k, coprime_to=workload.distinct_moduli(k) if distinct else 512)
+    keys = list(workload.positive_keys(k, 3000)) + [0, 1, (1 << 64) - 1]
+    for x in keys:
+        got = bbfc.host_key_mask(am, int(x), sel)
+        want = oracle.mask(am, int(x), distinct=distinct)
+        assert np.array_equal(got, want), (k, sel, int(x))
+
+
+def test_key_mask_argument_errors():
+    with pytest.raises(bbfc.BBFCError):
+        bbfc.host_key_mask([], 1)
+    with pytest.raises(bbfc.BBFCError):
+        bbfc.host_key_mask([(1 << 40) + 1] * 33, 1)
+    with pytest.raises(bbfc.BBFCError):
+        bbfc.host_key_mask([(1 << 40) + 1], 1, 2)
 
 
 def test_null_handle_calls_are_rejected():

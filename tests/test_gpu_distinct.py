@@ -1,0 +1,202 @@
+"""Distinct bit selection on the GPU against the oracle (GPU only).
+
+The kernels compute each key's k distinct addresses (Section 3.3, App. B) by
+counting free addresses; the oracle follows the paper's insertion sort. The
+checks are those of the random strategy:
+
+* query: bit-exact on filters the oracle built;
+* deterministic insert: filter words bit-exact;
+* racing insert: bit-exact with one choice; with choices zero false
+  negatives and every bit inside the oracle's envelope;
+* the same through the batch kernels (distinct and random filters in one
+  plan) and the fused q-gram path;
+* default multipliers drawn like the oracle's (coprime to 512 - i).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2501_18977_amd as bbfc
+import workload
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to(dev)
+
+
+def from_dev(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def make_pair(M, c, k, cost, seed):
+    bm = workload.draw_multipliers(seed, c, coprime_to=M)
+    am = workload.draw_multipliers(seed + 7919, k, coprime_to=workload.distinct_moduli(k))
+    ref = oracle.OracleFilter(M, c, k, oracle.COST_NAMES[cost], None, bm, am, distinct=True)
+    gpu = bbfc.Filter(M, c, k, cost, block_mult=bm, bit_mult=am, bit_selection="distinct")
+    assert gpu.params.bit_selection == bbfc.BITS_DISTINCT
+    return ref, gpu
+
+
+# every hash mode of M, c = 1..4, k from 1 to 32, light to overloaded
+CONFIGS = [
+    (1, 2, 5, "exp", 40),
+    (8, 3, 6, "mix", 300),
+    (1 << 10, 2, 14, "la", 1 << 15),
+    (3000, 3, 8, "mix", 3000 * 512 // 12),
+    (1001, 2, 17, "exp", 1001 * 512 // 20),
+    (1 << 14, 1, 10, "none", (1 << 14) * 512 // 16),
+    (777, 4, 20, "la", 777 * 512 // 24),
+    (1 << 12, 2, 32, "exp", (1 << 12) * 512 // 48),
+    (1 << 12, 2, 1, "exp", 20000),
+    (6, 2, 7, "la", 500),
+]
+
+
+@pytest.mark.parametrize("M,c,k,cost,n", CONFIGS)
+def test_query_matches_oracle(dev, M, c, k, cost, n):
+    ref, gpu = make_pair(M, c, k, cost, seed=M + 31 * c + k)
+    try:
+        keys = workload.positive_keys(M + k, n)
+        ref.insert(keys)
+        gpu.upload(ref.words)
+        probe = np.concatenate([keys, workload.negative_keys(M + k, n, n + 4321)])
+        got = from_dev(gpu.query(to_dev(probe, dev)))
+        assert np.array_equal(got, ref.query_bits(probe))
+        assert bbfc.unpack_bits(got, len(probe))[:n].all()
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("M,c,k,cost,n", CONFIGS)
+def test_deterministic_insert_is_bit_exact(dev, M, c, k, cost, n):
+    ref, gpu = make_pair(M, c, k, cost, seed=3 * M + c + k)
+    try:
+        keys = workload.positive_keys(2 * M + k, n)
+        keys = np.concatenate([keys, keys[: n // 10]])
+        ref.insert(keys)
+        gpu.insert_deterministic(to_dev(keys, dev))
+        assert np.array_equal(gpu.download(), ref.words)
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("M,c,k,cost,n", CONFIGS)
+def test_racing_insert(dev, M, c, k, cost, n):
+    ref, gpu = make_pair(M, c, k, cost, seed=5 * M + c + k)
+    try:
+        keys = workload.positive_keys(3 * M + k, n)
+        gpu.insert(to_dev(keys, dev))
+        words = gpu.download()
+        if c == 1:
+            ref.insert(keys)
+            assert np.array_equal(words, ref.words)
+        else:
+            assert not np.any(words & ~ref.envelope(keys))
+        hits = bbfc.unpack_bits(from_dev(gpu.query(to_dev(keys, dev))), n)
+        assert hits.all(), "false negative"
+    finally:
+        gpu.close()
+
+
+def test_racing_insert_fpr_matches_sequential_build(dev):
+    """A full-size-per-block build (k = 14, three choices, EXP): the racing
+    build's conditional FPR within 2% of the oracle's sequential build."""
+    n, k, c = 1 << 20, 14, 3
+    M = math.ceil(n * k / math.log(2) / 512)
+    ref, gpu = make_pair(M, c, k, "exp", seed=41)
+    try:
+        keys = workload.positive_keys(41, n)
+        ref.insert(keys)
+        gpu.insert(to_dev(keys, dev))
+        neg = workload.negative_keys(41, n, 1 << 20)
+        want = ref.conditional_fpr(neg)
+        got = ref.conditional_fpr(neg, words=gpu.download())
+        print(f"distinct k=14 c=3: sequential FPR {want:.4e}, racing {got:.4e}", flush=True)
+        assert got == pytest.approx(want, rel=0.02)
+    finally:
+        gpu.close()
+
+
+def test_default_multipliers_match_oracle(dev):
+    for seed, M, c, k in ((0, 1 << 12, 2, 14), (9, 3001, 3, 32), (4, 6000, 1, 5)):
+        cost = "none" if c == 1 else "exp"
+        f = bbfc.Filter(M, c, k, cost, seed=seed, bit_selection="distinct")
+        try:
+            bm, am = oracle.derive_multipliers(seed, M, c, k, distinct=True)
+            assert list(f.params.block_mult) == bm and list(f.params.bit_mult) == am
+        finally:
+            f.close()
+
+
+def test_batch_with_distinct_and_random_filters(dev):
+    """One batch plan over filters of both strategies: answers bit-exact,
+    racing batch inserts keep every key and stay inside the envelope."""
+    specs = [(3000, 12, 8, True), (20000, 16, 14, False), (65, 16, 11, True), (70000, 14, 20, True),
+             (1, 16, 5, False)]
+    refs, gpus, ns = [], [], []
+    for i, (n, bits, k, distinct) in enumerate(specs):
+        M = max(1, math.ceil(n * bits / 512))
+        bm = workload.draw_multipliers(50 + i, 2, coprime_to=M)
+        am = workload.draw_multipliers(60 + i, k, coprime_to=workload.distinct_moduli(k) if distinct else 512)
+        refs.append(oracle.OracleFilter(M, 2, k, oracle.COST_EXP, None, bm, am, distinct=distinct))
+        gpus.append(bbfc.Filter(M, 2, k, "exp", block_mult=bm, bit_mult=am,
+                                bit_selection="distinct" if distinct else "random"))
+        ns.append(n)
+    try:
+        keys = [workload.positive_keys(70 + i, n) for i, n in enumerate(ns)]
+        for r, g, kk in zip(refs, gpus, keys):
+            r.insert(kk)
+            g.upload(r.words)
+        probes = [np.concatenate([kk, workload.negative_keys(70 + i, len(kk), len(kk))]) for i, kk in enumerate(keys)]
+        qn = [len(p) for p in probes]
+        plan = bbfc.Batch(gpus, qn)
+        got = from_dev(plan.query(to_dev(np.concatenate(probes), dev)))
+        wo = 0
+        for r, p in zip(refs, probes):
+            nw = (len(p) + 63) // 64
+            assert np.array_equal(got[wo:wo + nw], r.query_bits(p))
+            wo += nw
+        for g in gpus:
+            g.clear()
+        ins = bbfc.Batch(gpus, ns)
+        ins.insert(to_dev(np.concatenate(keys), dev))
+        for r, g, kk in zip(refs, gpus, keys):
+            words = g.download()
+            assert not np.any(words & ~r.envelope(kk))
+            assert bbfc.unpack_bits(from_dev(g.query(to_dev(kk, dev))), len(kk)).all()
+    finally:
+        for g in gpus:
+            g.close()
+
+
+def test_fused_kmer_query_with_distinct_bits(dev):
+    q = 31
+    genome = workload.random_bases(17, 150_000)
+    gkeys = oracle.qgrams(genome, 1, len(genome), q)
+    M = bbfc.blocks_for(len(gkeys), 14)
+    ref, gpu = make_pair(M, 3, 10, "mix", seed=17)
+    try:
+        ref.insert(gkeys)
+        gpu.upload(ref.words)
+        reads = np.concatenate([genome[:30_000], workload.random_bases(18, 30_000)])
+        rk = oracle.qgrams(reads, 400, 150, q)
+        got = from_dev(gpu.query_kmers(to_dev(workload.pack_2bit(reads), dev), 400, 150, q))
+        assert np.array_equal(got, ref.query_bits(rk))
+    finally:
+        gpu.close()

@@ -97,16 +97,24 @@ class SplitMix64:
         return z ^ (z >> 31)
 
 
-def draw_multipliers(seed: int, count: int, coprime_to: int = 2) -> list[int]:
+def draw_multipliers(seed: int, count: int, coprime_to=2) -> list[int]:
     """``count`` random odd 64-bit multipliers, each >= 2^32 and coprime to
-    ``coprime_to``; used as hash parameters handed to both sides."""
+    ``coprime_to`` (one modulus for all, or a sequence with one modulus per
+    multiplier); used as hash parameters handed to both sides."""
+    mods = [coprime_to] * count if isinstance(coprime_to, int) else [int(m) for m in coprime_to]
+    assert len(mods) == count
     rng = SplitMix64(seed ^ 0x5DEECE66D)
     out: list[int] = []
     while len(out) < count:
         a = rng.next() | 1
-        if a >= (1 << 32) and math.gcd(a, coprime_to) == 1:
+        if a >= (1 << 32) and math.gcd(a, mods[len(out)]) == 1:
             out.append(a)
     return out
+
+
+def distinct_moduli(k: int) -> list[int]:
+    """Moduli of the k bit hashes under distinct bit selection: 512, 511, ..."""
+    return [512 - i for i in range(k)]
 
 
 def batch_specs(seed: int, count: int, log2_lo: float = 10.0, log2_hi: float = 24.0,
