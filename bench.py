@@ -98,20 +98,23 @@ def run_probes(stream=None):
 
 
 def copy_calibration():
-    """Three launches of a streaming copy of 2^27 words (1 GiB read, 1 GiB
-    written), so FETCH_SIZE and WRITE_SIZE can be scaled to bytes."""
+    """Copies of 2^27 words (1 GiB read, 1 GiB written), three launches with
+    128-byte requests, then three with 64-byte requests, so FETCH_SIZE and
+    WRITE_SIZE can be scaled to bytes for either request size."""
     import torch
 
     import paper_2501_18977_amd as bbfc
 
     dev = torch.device("cuda:0")
-    src = torch.ones(1 << 27, dtype=torch.int64, device=dev)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        bbfc.probe_copy(src, dst)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8,
-                      "launches": 3, "ok": bool(torch.equal(src, dst))}), flush=True)
+    src = torch.arange(1 << 27, dtype=torch.int64, device=dev)
+    rec = {"copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8, "launches_each": 3}
+    for req in (128, 64):
+        dst = torch.zeros_like(src)
+        for _ in range(3):
+            bbfc.probe_copy(src, dst, request_bytes=req)
+        torch.cuda.synchronize()
+        rec[f"ok_{req}B"] = bool(torch.equal(src, dst))
+    print(json.dumps(rec), flush=True)
 
 
 def kernel_source_sha() -> str:
@@ -123,18 +126,28 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(op: str, kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if it is absent or was taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.json")
+    None if it is absent, or was taken on a different kernel source or
+    launch shape."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{op}.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha") != kernel_source_sha():
+    if rec.get("source_sha") != kernel_source_sha() or rec.get("kernel") != kernel:
         return None
     return rec.get("bytes_per_launch")
+
+
+def kernel_name(op: str, c: int, shape: dict, early: bool = True) -> str:
+    """The kernel's name as rocprofv3 prints it (without namespaces)."""
+    lpk, tpw = shape["lanes_per_key"], shape["tiles_per_wave"]
+    if op == "insert":
+        return f"insert_kernel<{c}, {lpk}, {tpw}, ArrayKeys>"
+    ee = "true" if (early and c > 1) else "false"
+    return f"query_kernel<{c}, {lpk}, {tpw}, {ee}, ArrayKeys>"
 
 
 def cpu_baseline(n_blocks, c, k, target_s, distinct=False):
@@ -667,17 +680,19 @@ def main():
     avg_qry = sum(qry_ms) / len(qry_ms)
     if avg_ins >= avg_qry:
         dom, dom_ms, dom_bytes = "insert", avg_ins, INSERT_BYTES_PER_KEY * n
+        dom_kernel = kernel_name("insert", c, filt.get_shape(bbfc.OP_INSERT))
     else:
         dom, dom_ms, dom_bytes = "query", avg_qry, QUERY_BYTES_PER_KEY * n_q
+        dom_kernel = kernel_name("query", c, filt.get_shape(bbfc.OP_QUERY))
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
     roofline = {
         "bound": "hbm",
-        "kernel": f"{dom}_kernel<2,pow2>",
+        "kernel": dom_kernel,
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(dom),
+        "traffic": measured_traffic(dom, dom_kernel),
         "bytes_per_launch_algorithmic": int(dom_bytes),
         "launch_ms": round(dom_ms, 3),
     }

@@ -470,8 +470,16 @@ bbfc_status bbfc_probe_gather(const uint64_t *d_buf, uint64_t n_lines64, uint32_
 bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
                                 hipStream_t stream);
 
-/* Plain streaming copy of n_words words (calibrates traffic counters). */
-bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, hipStream_t stream);
+/* Plain copy of n_words words, to calibrate the traffic counters. With
+ * request_bytes == 128 every lane moves 16 contiguous bytes (128-byte
+ * requests, a streaming copy; an odd last word is not copied). With
+ * request_bytes == 64 every group of eight lanes moves one 64-byte half of a
+ * 128-byte line per instruction, the low halves first, then the high halves
+ * (64-byte requests, the size of a filter block read); n_words must then be
+ * a multiple of 128. Errors: EINVAL for null buffers, another request size
+ * or a bad n_words; EHIP. */
+bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, uint32_t request_bytes,
+                            hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Host-side checks of the device hashing code (no device needed).      */

@@ -124,7 +124,7 @@ def lib() -> ctypes.CDLL:
         "bbfc_last_error": (ctypes.c_char_p, []),
         "bbfc_probe_gather": (_st, [_vp, _u64, _u32, _u64, _u64, _vp, _vp]),
         "bbfc_probe_atomic64": (_st, [_vp, _u64, _u64, _u64, _vp]),
-        "bbfc_probe_copy": (_st, [_vp, _vp, _u64, _vp]),
+        "bbfc_probe_copy": (_st, [_vp, _vp, _u64, _u32, _vp]),
         "bbfc_batch_create": (_st, [_vp, _vp, _u32, _vp]),
         "bbfc_batch_destroy": (_st, [_vp]),
         "bbfc_batch_layout": (_st, [_vp, _vp, _vp]),
@@ -644,9 +644,9 @@ def probe_atomic64(buf, n_access: int, seed: int, stream=None) -> None:
     _check(lib().bbfc_probe_atomic64(buf.data_ptr(), n_lines, n_access, seed, _stream_handle(stream)))
 
 
-def probe_copy(src, dst, stream=None) -> None:
+def probe_copy(src, dst, request_bytes: int = 128, stream=None) -> None:
     n = min(src.numel(), dst.numel())
-    _check(lib().bbfc_probe_copy(src.data_ptr(), dst.data_ptr(), n, _stream_handle(stream)))
+    _check(lib().bbfc_probe_copy(src.data_ptr(), dst.data_ptr(), n, request_bytes, _stream_handle(stream)))
 
 
 def unpack_bits(words, n: int):

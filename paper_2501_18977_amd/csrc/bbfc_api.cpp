@@ -736,11 +736,16 @@ bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_ac
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching atomic probe");
 }
 
-bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, hipStream_t stream)
+bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, uint32_t request_bytes,
+                            hipStream_t stream)
 {
     if (d_src == nullptr || d_dst == nullptr)
         return fail(BBFC_EINVAL, "null buffer");
-    hipError_t e = bbfc::launch_probe_copy(d_src, d_dst, n_words, stream);
+    if (request_bytes != 64 && request_bytes != 128)
+        return fail(BBFC_EINVAL, "request_bytes must be 64 or 128, got %u", request_bytes);
+    if (request_bytes == 64 && n_words % 128 != 0)
+        return fail(BBFC_EINVAL, "a 64-byte-request copy needs a multiple of 128 words");
+    hipError_t e = bbfc::launch_probe_copy(d_src, d_dst, n_words, request_bytes, stream);
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching copy probe");
 }
 

@@ -86,6 +86,24 @@ __global__ __launch_bounds__(kProbeWG) void probe_copy_kernel(const uint4 *__res
         dst[i] = src[i];
 }
 
+// 64-byte requests: a wavefront takes 8 consecutive 128-byte lines per
+// unit; group g (lanes 8g..8g+7) moves the low 64-byte half of line g, then,
+// in a second instruction, its high half.
+__global__ __launch_bounds__(kProbeWG) void probe_copy64_kernel(const uint64_t *__restrict__ src,
+                                                                uint64_t *__restrict__ dst, uint64_t n_units)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t g = lane >> 3;
+    const uint64_t w = lane & 7;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t u = wave; u < n_units; u += n_waves) {
+        const uint64_t line = (u * 8 + g) * 16;
+        dst[line + w] = src[line + w];
+        dst[line + 8 + w] = src[line + 8 + w];
+    }
+}
+
 uint32_t probe_grid(const void *kernel)
 {
     int dev = 0, cus = 0, per_cu = 0;
@@ -128,8 +146,15 @@ hipError_t launch_probe_atomic64(uint64_t *buf, uint64_t n_lines, uint64_t n_acc
     return hipGetLastError();
 }
 
-hipError_t launch_probe_copy(const uint64_t *src, uint64_t *dst, uint64_t n_words, hipStream_t s)
+hipError_t launch_probe_copy(const uint64_t *src, uint64_t *dst, uint64_t n_words, uint32_t request_bytes,
+                             hipStream_t s)
 {
+    if (request_bytes == 64) {
+        const uint64_t n_units = n_words / 128; // 8 lines of 16 words; the caller checked divisibility
+        const uint32_t grid = probe_grid((const void *)probe_copy64_kernel) * 2;
+        hipLaunchKernelGGL(probe_copy64_kernel, dim3(grid), dim3(kProbeWG), 0, s, src, dst, n_units);
+        return hipGetLastError();
+    }
     const uint64_t n_vec = n_words / 2; // whole 16-byte vectors; an odd last word is not copied
     uint32_t grid = probe_grid((const void *)probe_copy_kernel) * 2;
     hipLaunchKernelGGL(probe_copy_kernel, dim3(grid), dim3(kProbeWG), 0, s, reinterpret_cast<const uint4 *>(src),

@@ -322,3 +322,12 @@ def test_probes_run(dev):
     torch.cuda.synchronize()
     assert torch.equal(buf, dst)
     assert int(buf.ne(0).sum()) > 0
+    src = torch.arange(1 << 19, dtype=torch.int64, device=dev)
+    d64 = torch.zeros_like(src)
+    bbfc.probe_copy(src, d64, request_bytes=64)
+    torch.cuda.synchronize()
+    assert torch.equal(src, d64)
+    with pytest.raises(bbfc.BBFCError):
+        bbfc.probe_copy(src[:1000], d64[:1000], request_bytes=64)
+    with pytest.raises(bbfc.BBFCError):
+        bbfc.probe_copy(src, d64, request_bytes=32)

@@ -140,4 +140,5 @@ def test_overload_sweep(dev, c, cost):
             assert got == pytest.approx(want, rel=0.02)
         got_fpr.append(got)
     assert all(a < b for a, b in zip(got_fpr, got_fpr[1:]))
-    assert 1.5 < got_fpr[1] / got_fpr[0] < 2.2  # 10% overload: below twice the FPR
+    # 10% overload: about the factor 1.912 of a standard Bloom filter (Section 2.1)
+    assert 1.5 < got_fpr[1] / got_fpr[0] < 2.2
