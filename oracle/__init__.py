@@ -41,6 +41,14 @@ _lib = None
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
+class _Layout(ctypes.Structure):
+    """M blocks in T sub-arrays; h_0 has multiplier sub_mult (Section 3.4)."""
+    _fields_ = [("M", ctypes.c_uint64), ("T", ctypes.c_uint64), ("sub_mult", ctypes.c_uint64)]
+
+
+_Lp = ctypes.POINTER(_Layout)
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -57,21 +65,23 @@ def _load():
     lib.bbo_default_param.restype = dbl
     lib.bbo_cost.argtypes = [i32, dbl, u32, u32, u32]
     lib.bbo_cost.restype = dbl
-    lib.bbo_insert_one.argtypes = [_u64p, u64, u32, u32, i32, i32, dbl, _u64p, _u64p, u64]
+    lib.bbo_block.argtypes = [_Lp, u64, u64]
+    lib.bbo_block.restype = u64
+    lib.bbo_insert_one.argtypes = [_u64p, _Lp, u32, u32, i32, i32, dbl, _u64p, _u64p, u64]
     lib.bbo_insert_one.restype = i32
-    lib.bbo_insert.argtypes = [_u64p, u64, u32, u32, i32, i32, dbl, _u64p, _u64p, _u64p, u64]
+    lib.bbo_insert.argtypes = [_u64p, _Lp, u32, u32, i32, i32, dbl, _u64p, _u64p, _u64p, u64]
     lib.bbo_insert.restype = u64
-    lib.bbo_query_one.argtypes = [_u64p, u64, u32, u32, i32, _u64p, _u64p, u64]
+    lib.bbo_query_one.argtypes = [_u64p, _Lp, u32, u32, i32, _u64p, _u64p, u64]
     lib.bbo_query_one.restype = i32
-    lib.bbo_query.argtypes = [_u64p, u64, u32, u32, i32, _u64p, _u64p, _u64p, u64, _u64p]
+    lib.bbo_query.argtypes = [_u64p, _Lp, u32, u32, i32, _u64p, _u64p, _u64p, u64, _u64p]
     lib.bbo_query.restype = u64
-    lib.bbo_derive_multipliers.argtypes = [u64, u64, u32, u32, i32, _u64p, _u64p]
+    lib.bbo_derive_multipliers.argtypes = [u64, u64, u64, u32, u32, i32, _u64p, _u64p, _u64p]
     lib.bbo_derive_multipliers.restype = None
-    lib.bbo_envelope.argtypes = [_u64p, u64, u32, u32, i32, _u64p, _u64p, _u64p, u64]
+    lib.bbo_envelope.argtypes = [_u64p, _Lp, u32, u32, i32, _u64p, _u64p, _u64p, u64]
     lib.bbo_envelope.restype = None
     lib.bbo_block_loads.argtypes = [_u64p, u64, _u64p]
     lib.bbo_block_loads.restype = None
-    lib.bbo_conditional_fpr.argtypes = [_u64p, u64, u32, u32, i32, _u64p, _u64p, u64]
+    lib.bbo_conditional_fpr.argtypes = [_u64p, _Lp, u32, u32, i32, _u64p, _u64p, u64]
     lib.bbo_conditional_fpr.restype = dbl
     lib.bbo_distinct_positions.argtypes = [ctypes.c_void_p, u32, ctypes.c_void_p]
     lib.bbo_distinct_positions.restype = None
@@ -131,11 +141,22 @@ def qgrams(bases, n_segments: int, seg_len: int, q: int) -> np.ndarray:
     return out[:n]
 
 
-def derive_multipliers(seed: int, M: int, c: int, k: int, distinct: bool = False):
+def derive_multipliers(seed: int, M: int, c: int, k: int, distinct: bool = False, subarrays: int = 1,
+                       with_sub: bool = False):
+    """Default (block, bit) multipliers; with_sub=True adds the h_0 multiplier."""
     bm = np.zeros(c, dtype=np.uint64)
     am = np.zeros(k, dtype=np.uint64)
-    _load().bbo_derive_multipliers(seed, M, c, k, int(distinct), _ptr(bm), _ptr(am))
-    return [int(v) for v in bm], [int(v) for v in am]
+    sm = ctypes.c_uint64(0)
+    _load().bbo_derive_multipliers(seed, M, subarrays, c, k, int(distinct), _ptr(bm), _ptr(am),
+                                   ctypes.cast(ctypes.byref(sm), _u64p))
+    out = ([int(v) for v in bm], [int(v) for v in am])
+    return out + (int(sm.value),) if with_sub else out
+
+
+def block_index(n_blocks: int, subarrays: int, sub_mult: int, a: int, x: int) -> int:
+    """Candidate block of multiplier a for key x under a sub-array layout."""
+    L = _Layout(n_blocks, subarrays, sub_mult)
+    return int(_load().bbo_block(ctypes.byref(L), a, x))
 
 
 class OracleFilter:
@@ -143,19 +164,22 @@ class OracleFilter:
 
     def __init__(self, n_blocks: int, choices: int, k: int, cost_kind: int = COST_NONE,
                  cost_param: float | None = None, block_mult=None, bit_mult=None, seed: int = 0,
-                 distinct: bool = False):
-        if choices < 1 or k < 1 or n_blocks < 1:
+                 distinct: bool = False, subarrays: int = 1, sub_mult=None):
+        if choices < 1 or k < 1 or n_blocks < 1 or subarrays < 1 or n_blocks % subarrays:
             raise ValueError("bad filter shape")
         self.M, self.c, self.k = int(n_blocks), int(choices), int(k)
+        self.T = int(subarrays)
         self.distinct = int(bool(distinct))
         self.kind = int(cost_kind)
         if cost_param is None or (isinstance(cost_param, float) and np.isnan(cost_param)):
             cost_param = default_param(self.kind, self.k)
         self.param = float(cost_param)
-        if block_mult is None or bit_mult is None:
-            dbm, dam = derive_multipliers(seed, self.M, self.c, self.k, bool(self.distinct))
-            block_mult = dbm if block_mult is None else block_mult
-            bit_mult = dam if bit_mult is None else bit_mult
+        dbm, dam, dsm = derive_multipliers(seed, self.M, self.c, self.k, bool(self.distinct), self.T,
+                                           with_sub=True)
+        block_mult = dbm if block_mult is None else block_mult
+        bit_mult = dam if bit_mult is None else bit_mult
+        self.sub_mult = int(dsm if sub_mult is None else sub_mult)
+        self.layout = _Layout(self.M, self.T, self.sub_mult)
         self.block_mult = _u64(block_mult)
         self.bit_mult = _u64(bit_mult)
         assert len(self.block_mult) == self.c and len(self.bit_mult) == self.k
@@ -163,18 +187,18 @@ class OracleFilter:
 
     def insert(self, keys) -> int:
         keys = _u64(keys)
-        return int(_load().bbo_insert(_ptr(self.words), self.M, self.c, self.k, self.distinct, self.kind, self.param,
+        return int(_load().bbo_insert(_ptr(self.words), ctypes.byref(self.layout), self.c, self.k, self.distinct, self.kind, self.param,
                                       _ptr(self.block_mult), _ptr(self.bit_mult), _ptr(keys), len(keys)))
 
     def insert_one(self, key: int) -> int:
-        return int(_load().bbo_insert_one(_ptr(self.words), self.M, self.c, self.k, self.distinct, self.kind,
+        return int(_load().bbo_insert_one(_ptr(self.words), ctypes.byref(self.layout), self.c, self.k, self.distinct, self.kind,
                                           self.param, _ptr(self.block_mult), _ptr(self.bit_mult), key))
 
     def query_bits(self, keys) -> np.ndarray:
         """Packed answers: bit t of word t//64 (LSB first) for keys[t]."""
         keys = _u64(keys)
         out = np.zeros((len(keys) + 63) // 64, dtype=np.uint64)
-        _load().bbo_query(_ptr(self.words), self.M, self.c, self.k, self.distinct, _ptr(self.block_mult),
+        _load().bbo_query(_ptr(self.words), ctypes.byref(self.layout), self.c, self.k, self.distinct, _ptr(self.block_mult),
                           _ptr(self.bit_mult), _ptr(keys), len(keys), _ptr(out))
         return out
 
@@ -186,17 +210,17 @@ class OracleFilter:
 
     def count_hits(self, keys) -> int:
         keys = _u64(keys)
-        return int(_load().bbo_query(_ptr(self.words), self.M, self.c, self.k, self.distinct, _ptr(self.block_mult),
+        return int(_load().bbo_query(_ptr(self.words), ctypes.byref(self.layout), self.c, self.k, self.distinct, _ptr(self.block_mult),
                                      _ptr(self.bit_mult), _ptr(keys), len(keys), None))
 
     def query_one(self, key: int) -> bool:
-        return bool(_load().bbo_query_one(_ptr(self.words), self.M, self.c, self.k, self.distinct,
+        return bool(_load().bbo_query_one(_ptr(self.words), ctypes.byref(self.layout), self.c, self.k, self.distinct,
                                           _ptr(self.block_mult), _ptr(self.bit_mult), key))
 
     def envelope(self, keys) -> np.ndarray:
         keys = _u64(keys)
         env = np.zeros_like(self.words)
-        _load().bbo_envelope(_ptr(env), self.M, self.c, self.k, self.distinct, _ptr(self.block_mult),
+        _load().bbo_envelope(_ptr(env), ctypes.byref(self.layout), self.c, self.k, self.distinct, _ptr(self.block_mult),
                              _ptr(self.bit_mult), _ptr(keys), len(keys))
         return env
 
@@ -209,5 +233,5 @@ class OracleFilter:
     def conditional_fpr(self, keys, words: np.ndarray | None = None) -> float:
         w = self.words if words is None else _u64(words)
         keys = _u64(keys)
-        return float(_load().bbo_conditional_fpr(_ptr(w), self.M, self.c, self.k, self.distinct,
+        return float(_load().bbo_conditional_fpr(_ptr(w), ctypes.byref(self.layout), self.c, self.k, self.distinct,
                                                  _ptr(self.block_mult), _ptr(keys), len(keys)))

@@ -14,6 +14,10 @@
  *   filter    M blocks of 512 bits; block b is the eight 64-bit words
  *             W[8b .. 8b+7]; bit f of a block is bit (f mod 64) of word
  *             (f div 64)                         (Section 2.2; reading R2)
+ *   layout    T sub-arrays of S = M/T blocks; h_0(x) in [T] picks the
+ *             sub-array and h_i(x) in [S] the block inside it, so candidate
+ *             i is block h_0(x) S + h_i(x); T = 1 is a single array
+ *                                      (Section 3.4, "Parallelization")
  *   F(x)      { f_i(x) : i = 1..k }, f_i random-strategy bit hashes into
  *             [512]                  (Section 3.1 eq. bitset; Section 3.3)
  *   j, a      for a candidate block with bit set F':
@@ -29,7 +33,8 @@
  *   R1  keys are u = 64-bit words for every hash.
  *   R3  hash multipliers are odd, >= 2^32, coprime to the modulus; the
  *       default set comes from a SplitMix64 stream (Steele, Lea, Flood 2014)
- *       seeded by the filter seed: c block multipliers, then k bit ones.
+ *       seeded by the filter seed: c block multipliers, then k bit ones,
+ *       then the sub-array multiplier when there are sub-arrays.
  *   R4  a modulus of 1 hashes every key to 0.
  *   R5  on equal cost the lower choice index wins.
  *   R6  costs are IEEE-754 double, evaluated left to right as written in
@@ -74,6 +79,23 @@ uint64_t bbo_hash(uint64_t a, uint64_t x, uint64_t b)
     if ((b & 1) == 0)
         return (p ^ (p >> 32)) % b;
     return p % b;
+}
+
+/* Where a key's candidates lie (Section 3.4, "Parallelization"): the M
+ * blocks form T sub-arrays of S = M/T blocks each (T divides M); h_0, with
+ * its own multiplier, picks the sub-array, and the block hashes h_i map into
+ * [S]. T = 1 is the single array of Section 3.1 (h_0 = 0 by R4, S = M). */
+typedef struct {
+    uint64_t M;        /* blocks in the filter */
+    uint64_t T;        /* sub-arrays */
+    uint64_t sub_mult; /* multiplier of h_0; unused when T = 1 */
+} bbo_layout;
+
+/* Index of the block that block hash a selects for key x. */
+uint64_t bbo_block(const bbo_layout *L, uint64_t a, uint64_t x)
+{
+    uint64_t S = L->M / L->T;
+    return bbo_hash(L->sub_mult, x, L->T) * S + bbo_hash(a, x, S);
 }
 
 /* F(x) as a 512-bit mask (eq. bitset; random bit selection, Section 3.3). */
@@ -174,7 +196,7 @@ static void bbo_mask_sel(int distinct, const uint64_t *bit_mult, uint32_t k, uin
 
 /* Insert one key (Sections 3.1, 3.2). Returns the chosen choice index, or
  * -1 when some candidate already contains F(x). */
-int bbo_insert_one(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct, int kind, double param,
+int bbo_insert_one(uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct, int kind, double param,
                    const uint64_t *block_mult, const uint64_t *bit_mult, uint64_t x)
 {
     uint64_t m[8];
@@ -182,7 +204,7 @@ int bbo_insert_one(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct
     uint32_t j[8], a[8];
     bbo_mask_sel(distinct, bit_mult, k, x, m);
     for (uint32_t i = 0; i < c; i++) {
-        blk[i] = bbo_hash(block_mult[i], x, M);
+        blk[i] = bbo_block(L, block_mult[i], x);
         const uint64_t *B = W + 8 * blk[i];
         unsigned before = 0, after = 0;
         for (int w = 0; w < 8; w++) {
@@ -214,25 +236,25 @@ int bbo_insert_one(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct
 
 /* Sequential insertion of keys[0..n) in order. Returns how many keys set
  * at least one bit. */
-uint64_t bbo_insert(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct, int kind, double param,
+uint64_t bbo_insert(uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct, int kind, double param,
                     const uint64_t *block_mult, const uint64_t *bit_mult, const uint64_t *keys,
                     uint64_t n)
 {
     uint64_t written = 0;
     for (uint64_t t = 0; t < n; t++)
-        if (bbo_insert_one(W, M, c, k, distinct, kind, param, block_mult, bit_mult, keys[t]) >= 0)
+        if (bbo_insert_one(W, L, c, k, distinct, kind, param, block_mult, bit_mult, keys[t]) >= 0)
             written++;
     return written;
 }
 
 /* Query one key: F(x) subset of some candidate block (Section 3.1). */
-int bbo_query_one(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct,
+int bbo_query_one(const uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct,
                   const uint64_t *block_mult, const uint64_t *bit_mult, uint64_t x)
 {
     uint64_t m[8];
     bbo_mask_sel(distinct, bit_mult, k, x, m);
     for (uint32_t i = 0; i < c; i++) {
-        const uint64_t *B = W + 8 * bbo_hash(block_mult[i], x, M);
+        const uint64_t *B = W + 8 * bbo_block(L, block_mult[i], x);
         int all = 1;
         for (int w = 0; w < 8; w++)
             if ((B[w] & m[w]) != m[w])
@@ -246,14 +268,15 @@ int bbo_query_one(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int dis
 /* Queries keys[0..n); bit t of out_bits[t/64] (least significant first) is
  * the answer for keys[t]; bits past n in the last word are zero. Returns the
  * number of positive answers. */
-uint64_t bbo_query(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct, const uint64_t *block_mult,
-                   const uint64_t *bit_mult, const uint64_t *keys, uint64_t n, uint64_t *out_bits)
+uint64_t bbo_query(const uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct,
+                   const uint64_t *block_mult, const uint64_t *bit_mult, const uint64_t *keys, uint64_t n,
+                   uint64_t *out_bits)
 {
     uint64_t hits = 0;
     if (out_bits)
         memset(out_bits, 0, ((n + 63) / 64) * sizeof(uint64_t));
     for (uint64_t t = 0; t < n; t++) {
-        int h = bbo_query_one(W, M, c, k, distinct, block_mult, bit_mult, keys[t]);
+        int h = bbo_query_one(W, L, c, k, distinct, block_mult, bit_mult, keys[t]);
         hits += (uint64_t)h;
         if (h && out_bits)
             out_bits[t / 64] |= (uint64_t)1 << (t % 64);
@@ -285,16 +308,18 @@ static uint64_t gcd64(uint64_t a, uint64_t b)
 /* Default hash multipliers of a filter with seed `seed` (Section 3.4's
  * "random large integer a, coprime with b"; reading R3): one SplitMix64
  * stream; each draw is made odd; draws below 2^32 or sharing a factor with
- * the modulus are skipped. Block multipliers come first (modulus M), then
- * bit multipliers (modulus 512, or 512 - i for the i-th with distinct bit
- * selection, counting from 0). */
-void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint32_t c, uint32_t k, int distinct, uint64_t *block_mult,
-                            uint64_t *bit_mult)
+ * the modulus are skipped. Block multipliers come first (modulus S = M/T),
+ * then bit multipliers (modulus 512, or 512 - i for the i-th with distinct
+ * bit selection, counting from 0), then, with T > 1 sub-arrays, the
+ * multiplier of h_0 (modulus T). */
+void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint64_t T, uint32_t c, uint32_t k, int distinct,
+                            uint64_t *block_mult, uint64_t *bit_mult, uint64_t *sub_mult)
 {
     uint64_t st = seed;
+    uint64_t S = M / T;
     for (uint32_t i = 0; i < c;) {
         uint64_t a = splitmix_next(&st) | 1;
-        if (a >= ((uint64_t)1 << 32) && gcd64(a, M) == 1)
+        if (a >= ((uint64_t)1 << 32) && gcd64(a, S) == 1)
             block_mult[i++] = a;
     }
     for (uint32_t i = 0; i < k;) {
@@ -302,6 +327,14 @@ void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint32_t c, uint32_t k, i
         uint64_t b = distinct ? 512 - i : 512; /* modulus of bit hash i */
         if (a >= ((uint64_t)1 << 32) && gcd64(a, b) == 1)
             bit_mult[i++] = a;
+    }
+    *sub_mult = 0;
+    while (T > 1) {
+        uint64_t a = splitmix_next(&st) | 1;
+        if (a >= ((uint64_t)1 << 32) && gcd64(a, T) == 1) {
+            *sub_mult = a;
+            break;
+        }
     }
 }
 
@@ -311,14 +344,14 @@ void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint32_t c, uint32_t k, i
  * these keys (sequential or with racing inserts) is bitwise contained in
  * this envelope, since bits only ever come from some key's mask placed in
  * one of its candidates. */
-void bbo_envelope(uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct, const uint64_t *block_mult,
-                  const uint64_t *bit_mult, const uint64_t *keys, uint64_t n)
+void bbo_envelope(uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct,
+                  const uint64_t *block_mult, const uint64_t *bit_mult, const uint64_t *keys, uint64_t n)
 {
     uint64_t m[8];
     for (uint64_t t = 0; t < n; t++) {
         bbo_mask_sel(distinct, bit_mult, k, keys[t], m);
         for (uint32_t i = 0; i < c; i++) {
-            uint64_t *B = W + 8 * bbo_hash(block_mult[i], keys[t], M);
+            uint64_t *B = W + 8 * bbo_block(L, block_mult[i], keys[t]);
             for (int w = 0; w < 8; w++)
                 B[w] |= m[w];
         }
@@ -346,14 +379,14 @@ void bbo_block_loads(const uint64_t *W, uint64_t M, uint64_t *hist)
  * inclusion-exclusion over the non-empty subsets I of choices:
  *   sum_I (-1)^(|I|+1) (|intersection of S_i, i in I| / 512)^k.
  * Returns the mean over the keys. */
-double bbo_conditional_fpr(const uint64_t *W, uint64_t M, uint32_t c, uint32_t k, int distinct,
+double bbo_conditional_fpr(const uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct,
                            const uint64_t *block_mult, const uint64_t *keys, uint64_t n)
 {
     double total = 0.0;
     for (uint64_t t = 0; t < n; t++) {
         uint64_t blk[8];
         for (uint32_t i = 0; i < c; i++)
-            blk[i] = bbo_hash(block_mult[i], keys[t], M);
+            blk[i] = bbo_block(L, block_mult[i], keys[t]);
         double p = 0.0;
         for (uint32_t sub = 1; sub < (1u << c); sub++) {
             unsigned size = 0, inter = 0;

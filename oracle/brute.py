@@ -58,15 +58,18 @@ def cost(kind: str, param: float, k: int, j: int, a: int) -> float:
 
 class BruteFilter:
     def __init__(self, M: int, c: int, k: int, kind: str, param: float, block_mult, bit_mult,
-                 distinct: bool = False):
+                 distinct: bool = False, subarrays: int = 1, sub_mult: int = 0):
         self.M, self.c, self.k, self.kind, self.param = M, c, k, kind, param
         self.distinct = distinct
+        self.T, self.sub_mult = subarrays, sub_mult  # Section 3.4, Parallelization
         self.block_mult = [int(v) for v in block_mult]
         self.bit_mult = [int(v) for v in bit_mult]
         self.blocks: list[set[int]] = [set() for _ in range(M)]
 
     def candidates(self, x: int) -> list[int]:
-        return [lin_hash(b, x, self.M) for b in self.block_mult]
+        S = self.M // self.T
+        base = S * lin_hash(self.sub_mult, x, self.T)  # sub-array h_0(x), then h_i(x) inside it
+        return [base + lin_hash(b, x, S) for b in self.block_mult]
 
     def F(self, x: int) -> set[int]:
         return bit_set_distinct(self.bit_mult, x) if self.distinct else bit_set(self.bit_mult, x)
