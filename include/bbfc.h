@@ -96,7 +96,15 @@ typedef enum {
     BBFC_BITS_DISTINCT = 1
 } bbfc_bit_selection;
 
-/* Everything that defines a filter, for bbfc_create_config. */
+/* Everything that defines a filter, for bbfc_create_config.
+ *
+ * Sub-arrays (Section 3.4, Parallelization): with subarrays = T > 1 the
+ * n_blocks blocks form T sub-arrays of S = n_blocks / T blocks (T must
+ * divide n_blocks). A key's sub-array is h_0(x), the linear hash into [T]
+ * with multiplier sub_mult; its candidates are blocks h_0(x) S + h_i(x) with
+ * the block hashes h_i into [S]. subarrays 0 or 1 is a single array. The
+ * layout changes which blocks a key uses, not the method; it is what lets
+ * bbfc_bulk_insert stage a whole sub-array in on-chip memory. */
 typedef struct {
     uint64_t n_blocks;
     uint32_t choices;
@@ -106,6 +114,8 @@ typedef struct {
     uint64_t seed;              /* multiplier stream (see bbfc_create_seeded) */
     const uint64_t *block_mult; /* host [choices], or null: drawn from seed */
     const uint64_t *bit_mult;   /* host [bits_per_key], or null: drawn from seed */
+    uint64_t subarrays;         /* T; 0 or 1: one array */
+    uint64_t sub_mult;          /* multiplier of h_0 (coprime to T), or 0: drawn from seed */
 } bbfc_config;
 
 /* Create an empty filter of n_blocks 512-bit blocks (64 bytes each, the
@@ -138,12 +148,15 @@ bbfc_status bbfc_create_with_multipliers(uint64_t n_blocks, uint32_t choices, ui
                                          const uint64_t *bit_mult, bbfc_handle *out);
 
 /* The general constructor: shape and cost as bbfc_create, the bit
- * selection strategy, and multipliers given or drawn. Multipliers are drawn
- * as in bbfc_create_seeded, except that with DISTINCT the i-th bit
- * multiplier (i from 1) is drawn coprime to 512 - i + 1. Given arrays are
- * checked (block multipliers coprime to n_blocks, bit multipliers coprime
- * to their moduli) and copied. Errors: as bbfc_create, plus EINVAL for a
- * null cfg or an unknown bit_selection. */
+ * selection strategy, the sub-array layout, and multipliers given or drawn.
+ * Multipliers are drawn as in bbfc_create_seeded, except that block
+ * multipliers are coprime to S = n_blocks / subarrays, that with DISTINCT
+ * the i-th bit multiplier (i from 1) is drawn coprime to 512 - i + 1, and
+ * that with subarrays > 1 one more draw, coprime to T, is the multiplier of
+ * h_0. Given multipliers are checked (block ones coprime to S, bit ones to
+ * their moduli, sub_mult to T) and copied. Errors: as bbfc_create, plus
+ * EINVAL for a null cfg, an unknown bit_selection or a subarrays that does
+ * not divide n_blocks. */
 bbfc_status bbfc_create_config(const bbfc_config *cfg, bbfc_handle *out);
 
 /* Synchronise the device, then free the filter. A null handle is EINVAL. */
@@ -177,6 +190,26 @@ bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uin
 bbfc_status bbfc_query(bbfc_handle h, const uint64_t *d_keys, uint64_t n, uint64_t *d_out_bits,
                        hipStream_t stream);
 
+/* Bulk insert for filters with sub-arrays (Section 3.4, Parallelization):
+ * the same result as bbfc_insert_deterministic, i.e. as inserting
+ * d_keys[0..n) one at a time in index order (Section 3.2), built the way
+ * the paper parallelises insertion: the keys are routed to their
+ * sub-arrays by a stable partition on h_0, and each sub-array is filled by a
+ * single writer (one wavefront holding the sub-array in LDS). Needs at most
+ * 1024 blocks per sub-array (n_blocks / subarrays <= 1024; a filter without
+ * sub-arrays qualifies when n_blocks <= 1024). d_workspace is device memory
+ * of at least bbfc_bulk_insert_workspace(h, n) bytes (about 16 bytes per
+ * key, for at most 2^31 keys; larger n is inserted in consecutive pieces),
+ * owned by the caller and free again when the stream reaches the end of the
+ * call. Errors: EINVAL (null handle or pointers, workspace too small),
+ * EUNSUPPORTED (sub-arrays too large for LDS), EHIP. */
+bbfc_status bbfc_bulk_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, void *d_workspace,
+                             uint64_t workspace_bytes, hipStream_t stream);
+
+/* Workspace bytes bbfc_bulk_insert needs for n keys (*bytes; 0 for n = 0).
+ * Errors: EINVAL (null handle or output), EUNSUPPORTED as bbfc_bulk_insert. */
+bbfc_status bbfc_bulk_insert_workspace(bbfc_handle h, uint64_t n, uint64_t *bytes);
+
 /* Set every filter bit to zero (stream-ordered, uses a fill kernel). */
 bbfc_status bbfc_clear(bbfc_handle h, hipStream_t stream);
 
@@ -193,6 +226,11 @@ bbfc_status bbfc_get_params(bbfc_handle h, uint64_t *n_blocks, uint32_t *choices
 
 /* The filter's bbfc_bit_selection. */
 bbfc_status bbfc_get_bit_selection(bbfc_handle h, int32_t *bit_selection);
+
+/* The sub-array layout: *subarrays = T (1 for a single array) and
+ * *sub_mult = the multiplier of h_0 (0 when T = 1). Either pointer may be
+ * null. */
+bbfc_status bbfc_get_subarrays(bbfc_handle h, uint64_t *subarrays, uint64_t *sub_mult);
 
 /* Load histogram (App. C, the per-block load figure): d_hist[j], j = 0..512
  * (device memory, 513 uint64, caller-owned) receives the number of blocks
@@ -488,6 +526,12 @@ bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_w
 /* Block index h(x) in [0, n_blocks) for multiplier a, through the same
  * source the kernels compile (Section 3.4). */
 uint64_t bbfc_host_block_hash(uint64_t n_blocks, uint64_t a, uint64_t x);
+
+/* Candidate block of key x for block multiplier a in a filter of n_blocks
+ * blocks in `subarrays` sub-arrays with h_0 multiplier sub_mult: h_0(x) S +
+ * h(x), through the same source the kernels compile. Returns 0 when
+ * n_blocks is 0 or subarrays does not divide it. */
+uint64_t bbfc_host_block_index(uint64_t n_blocks, uint64_t subarrays, uint64_t sub_mult, uint64_t a, uint64_t x);
 
 /* Bit address f(x) in [0, 512) for multiplier a (Section 3.4, b = 2^9). */
 uint32_t bbfc_host_bit_hash(uint64_t a, uint64_t x);

@@ -32,6 +32,7 @@ __all__ = [
     "kmer_keys",
     "host_bit_hash",
     "host_key_mask",
+    "host_block_index",
     "lib",
     "library_path",
     "probe_gather",
@@ -64,7 +65,8 @@ class _Cost(ctypes.Structure):
 class _Config(ctypes.Structure):
     _fields_ = [("n_blocks", ctypes.c_uint64), ("choices", ctypes.c_uint32), ("bits_per_key", ctypes.c_uint32),
                 ("cost", _Cost), ("bit_selection", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("block_mult", ctypes.c_void_p), ("bit_mult", ctypes.c_void_p)]
+                ("block_mult", ctypes.c_void_p), ("bit_mult", ctypes.c_void_p),
+                ("subarrays", ctypes.c_uint64), ("sub_mult", ctypes.c_uint64)]
 
 
 class _ServerConfig(ctypes.Structure):
@@ -105,6 +107,10 @@ def lib() -> ctypes.CDLL:
         "bbfc_create_with_multipliers": (_st, [_u64, _u32, _u32, _Cost, _vp, _vp, _vp]),
         "bbfc_create_config": (_st, [_vp, _vp]),
         "bbfc_get_bit_selection": (_st, [_vp, _vp]),
+        "bbfc_get_subarrays": (_st, [_vp, _vp, _vp]),
+        "bbfc_bulk_insert": (_st, [_vp, _vp, _u64, _vp, _u64, _vp]),
+        "bbfc_bulk_insert_workspace": (_st, [_vp, _u64, _vp]),
+        "bbfc_host_block_index": (_u64, [_u64, _u64, _u64, _u64, _u64]),
         "bbfc_load_histogram": (_st, [_vp, _vp, _vp]),
         "bbfc_host_key_mask": (_st, [_vp, _u32, ctypes.c_int32, _u64, _vp]),
         "bbfc_destroy": (_st, [_vp]),
@@ -234,6 +240,10 @@ def _bits_id(bit_selection) -> int:
     return int(bit_selection)
 
 
+def host_block_index(n_blocks: int, subarrays: int, sub_mult: int, a: int, x: int) -> int:
+    return int(lib().bbfc_host_block_index(n_blocks, subarrays, sub_mult, a, x))
+
+
 def host_key_mask(bit_mult, x: int, bit_selection="random"):
     """F(x) as 8 uint64 words (numpy), computed by the library's host build
     of the kernels' bit selection code."""
@@ -255,18 +265,21 @@ class Params:
     block_mult: tuple
     bit_mult: tuple
     bit_selection: int = BITS_RANDOM
+    subarrays: int = 1
+    sub_mult: int = 0
 
 
 class Filter:
     """One filter resident in device memory (owned by the library)."""
 
     def __init__(self, n_blocks: int, choices: int, bits_per_key: int, cost="none", cost_param=None, *,
-                 seed: int | None = None, block_mult=None, bit_mult=None, bit_selection="random"):
+                 seed: int | None = None, block_mult=None, bit_mult=None, bit_selection="random",
+                 subarrays: int = 1, sub_mult: int | None = None):
         L = lib()
         h = ctypes.c_void_p()
         cs = _cost_struct(cost, cost_param)
         sel = _bits_id(bit_selection)
-        if sel != BITS_RANDOM:
+        if sel != BITS_RANDOM or subarrays > 1:
             if block_mult is not None and len(block_mult) != choices:
                 raise ValueError("block_mult needs `choices` entries")
             if bit_mult is not None and len(bit_mult) != bits_per_key:
@@ -275,7 +288,8 @@ class Filter:
             am = (ctypes.c_uint64 * bits_per_key)(*[int(v) for v in bit_mult]) if bit_mult is not None else None
             cfg = _Config(n_blocks, choices, bits_per_key, cs, sel, 0 if seed is None else seed,
                           ctypes.cast(bm, ctypes.c_void_p) if bm is not None else None,
-                          ctypes.cast(am, ctypes.c_void_p) if am is not None else None)
+                          ctypes.cast(am, ctypes.c_void_p) if am is not None else None,
+                          subarrays, 0 if sub_mult is None else int(sub_mult))
             _check(L.bbfc_create_config(ctypes.byref(cfg), ctypes.byref(h)))
         elif block_mult is not None or bit_mult is not None:
             if block_mult is None or bit_mult is None:
@@ -302,8 +316,10 @@ class Filter:
                                      bm, am))
         sel = ctypes.c_int32()
         _check(lib().bbfc_get_bit_selection(self._h, ctypes.byref(sel)))
+        T, sm = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().bbfc_get_subarrays(self._h, ctypes.byref(T), ctypes.byref(sm)))
         return Params(M.value, c.value, k.value, cs.kind, cs.param, tuple(bm[: c.value]), tuple(am[: k.value]),
-                      sel.value)
+                      sel.value, T.value, sm.value)
 
     @property
     def handle(self):
@@ -392,6 +408,23 @@ class Filter:
 
     def clear(self, stream=None) -> None:
         _check(lib().bbfc_clear(self.handle, _stream_handle(stream)))
+
+    def bulk_workspace_bytes(self, n: int) -> int:
+        b = ctypes.c_uint64()
+        _check(lib().bbfc_bulk_insert_workspace(self.handle, n, ctypes.byref(b)))
+        return int(b.value)
+
+    def bulk_insert(self, keys, workspace=None, stream=None) -> None:
+        """Sequential-semantics insert through the sub-array partition; the
+        workspace (a uint8 GPU tensor) is allocated if not given."""
+        import torch
+
+        keys = _device_u64(keys, "keys")
+        need = self.bulk_workspace_bytes(keys.numel())
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+        _check(lib().bbfc_bulk_insert(self.handle, keys.data_ptr(), keys.numel(), workspace.data_ptr(),
+                                      workspace.numel() * workspace.element_size(), _stream_handle(stream)))
 
     def load_histogram(self, out=None, stream=None):
         """Blocks per popcount j = 0..512 as an int64 GPU tensor of 513."""

@@ -87,6 +87,9 @@ uint64_t gcd_u64(uint64_t a, uint64_t b)
 
 bool is_pow2(uint64_t v) { return v != 0 && (v & (v - 1)) == 0; }
 
+// Keys per bulk-insert launch (offsets inside a launch are 32-bit).
+constexpr uint64_t kBulkPiece = 1ull << 31;
+
 // The paper's parameter values: sigma (MIX) is printed for k = 7 (2.5) and
 // k = 14 (50) in App. C; other k take the value of the nearer printed k.
 // mu = 3.5 (App. C); beta = golden ratio (Section 4, App. C).
@@ -172,14 +175,15 @@ uint64_t bit_modulus(int32_t bit_selection, uint32_t i)
 }
 
 // SplitMix64 draws, made odd; draws below 2^32 or sharing a factor with the
-// modulus are skipped. Block multipliers first, then bit multipliers.
-void derive_multipliers(uint64_t seed, uint64_t n_blocks, uint32_t choices, uint32_t k, int32_t bit_selection,
-                        uint64_t *bm, uint64_t *am)
+// modulus are skipped. Block multipliers (modulus S) first, then bit
+// multipliers, then, with T > 1 sub-arrays, the multiplier of h_0.
+void derive_multipliers(uint64_t seed, uint64_t S, uint64_t T, uint32_t choices, uint32_t k, int32_t bit_selection,
+                        uint64_t *bm, uint64_t *am, uint64_t *sub_mult)
 {
     uint64_t state = seed;
     for (uint32_t i = 0; i < choices;) {
         const uint64_t a = splitmix64(state) | 1;
-        if (a >= (1ull << 32) && gcd_u64(a, n_blocks) == 1)
+        if (a >= (1ull << 32) && gcd_u64(a, S) == 1)
             bm[i++] = a;
     }
     for (uint32_t i = 0; i < k;) {
@@ -187,10 +191,19 @@ void derive_multipliers(uint64_t seed, uint64_t n_blocks, uint32_t choices, uint
         if (a >= (1ull << 32) && gcd_u64(a, bit_modulus(bit_selection, i)) == 1)
             am[i++] = a;
     }
+    *sub_mult = 0;
+    while (T > 1) {
+        const uint64_t a = splitmix64(state) | 1;
+        if (a >= (1ull << 32) && gcd_u64(a, T) == 1) {
+            *sub_mult = a;
+            break;
+        }
+    }
 }
 
 bbfc_status create_impl(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_cost cost, int32_t bit_selection,
-                        const uint64_t *block_mult, const uint64_t *bit_mult, bbfc_handle *out)
+                        uint64_t T, uint64_t sub_mult, const uint64_t *block_mult, const uint64_t *bit_mult,
+                        bbfc_handle *out)
 {
     if (out == nullptr)
         return fail(BBFC_EINVAL, "out handle pointer is null");
@@ -199,9 +212,15 @@ bbfc_status create_impl(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_co
         return st;
     if (bit_selection != BBFC_BITS_RANDOM && bit_selection != BBFC_BITS_DISTINCT)
         return fail(BBFC_EINVAL, "unknown bit selection %d", (int)bit_selection);
+    if (T < 1 || n_blocks % T != 0)
+        return fail(BBFC_EINVAL, "subarrays (%llu) must divide n_blocks (%llu)", (unsigned long long)T,
+                    (unsigned long long)n_blocks);
+    const uint64_t S = n_blocks / T;
+    if (T > 1 && gcd_u64(sub_mult, T) != 1)
+        return fail(BBFC_EINVAL, "the sub-array multiplier is not coprime to subarrays");
     for (uint32_t i = 0; i < choices; ++i)
-        if (gcd_u64(block_mult[i], n_blocks) != 1 && n_blocks != 1)
-            return fail(BBFC_EINVAL, "block multiplier %u is not coprime to n_blocks", i);
+        if (gcd_u64(block_mult[i], S) != 1 && S != 1)
+            return fail(BBFC_EINVAL, "block multiplier %u is not coprime to the blocks per sub-array", i);
     for (uint32_t i = 0; i < k; ++i)
         if (gcd_u64(bit_mult[i], bit_modulus(bit_selection, i)) != 1)
             return fail(BBFC_EINVAL, "bit multiplier %u is not coprime to its modulus %llu", i,
@@ -212,19 +231,15 @@ bbfc_status create_impl(uint64_t n_blocks, uint32_t choices, uint32_t k, bbfc_co
     f->c = choices;
     f->k = k;
     f->bit_selection = bit_selection;
+    f->T = T;
+    f->S = S;
+    f->sub_mult = T > 1 ? sub_mult : 0;
+    f->blk = bbfc::make_hashmod(S);
+    f->sub = bbfc::make_hashmod(T);
     f->cost_kind = choices > 1 ? cost.kind : BBFC_COST_NONE;
     f->cost_param = choices > 1 ? (isnan(cost.param) ? default_param(cost.kind, k) : cost.param) : 0.0;
     memcpy(f->block_mult, block_mult, choices * sizeof(uint64_t));
     memcpy(f->bit_mult, bit_mult, k * sizeof(uint64_t));
-    if (n_blocks == 1) {
-        f->hash_mode = bbfc::kModeOne;
-    } else if (is_pow2(n_blocks)) {
-        f->hash_mode = bbfc::kModePow2;
-        f->pow2_shift = 64u - (uint32_t)__builtin_ctzll(n_blocks);
-    } else {
-        f->hash_mode = (n_blocks & 1) ? bbfc::kModeOdd : bbfc::kModeEven;
-    }
-    f->fm = bbfc::make_fastmod(n_blocks);
 
     hipError_t e = hipGetDevice(&f->device);
     if (e == hipSuccess)
@@ -282,7 +297,7 @@ bbfc_status bbfc_create_with_multipliers(uint64_t n_blocks, uint32_t choices, ui
 {
     if (block_mult == nullptr || bit_mult == nullptr)
         return fail(BBFC_EINVAL, "multiplier arrays must not be null");
-    return create_impl(n_blocks, choices, bits_per_key, cost, BBFC_BITS_RANDOM, block_mult, bit_mult, out);
+    return create_impl(n_blocks, choices, bits_per_key, cost, BBFC_BITS_RANDOM, 1, 0, block_mult, bit_mult, out);
 }
 
 bbfc_status bbfc_create_config(const bbfc_config *cfg, bbfc_handle *out)
@@ -294,14 +309,23 @@ bbfc_status bbfc_create_config(const bbfc_config *cfg, bbfc_handle *out)
         return st;
     if (cfg->bit_selection != BBFC_BITS_RANDOM && cfg->bit_selection != BBFC_BITS_DISTINCT)
         return fail(BBFC_EINVAL, "unknown bit selection %d", (int)cfg->bit_selection);
+    const uint64_t T = cfg->subarrays > 1 ? cfg->subarrays : 1;
+    if (cfg->n_blocks % T != 0)
+        return fail(BBFC_EINVAL, "subarrays (%llu) must divide n_blocks (%llu)", (unsigned long long)T,
+                    (unsigned long long)cfg->n_blocks);
     uint64_t bm[BBFC_MAX_CHOICES];
     uint64_t am[BBFC_MAX_BITS_PER_KEY];
-    derive_multipliers(cfg->seed, cfg->n_blocks, cfg->choices, cfg->bits_per_key, cfg->bit_selection, bm, am);
+    uint64_t sm = 0;
+    derive_multipliers(cfg->seed, cfg->n_blocks / T, T, cfg->choices, cfg->bits_per_key, cfg->bit_selection, bm, am,
+                       &sm);
     if (cfg->block_mult)
         memcpy(bm, cfg->block_mult, cfg->choices * sizeof(uint64_t));
     if (cfg->bit_mult)
         memcpy(am, cfg->bit_mult, cfg->bits_per_key * sizeof(uint64_t));
-    return create_impl(cfg->n_blocks, cfg->choices, cfg->bits_per_key, cfg->cost, cfg->bit_selection, bm, am, out);
+    if (cfg->sub_mult)
+        sm = cfg->sub_mult;
+    return create_impl(cfg->n_blocks, cfg->choices, cfg->bits_per_key, cfg->cost, cfg->bit_selection, T, sm, bm, am,
+                       out);
 }
 
 bbfc_status bbfc_create_seeded(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
@@ -312,8 +336,9 @@ bbfc_status bbfc_create_seeded(uint64_t n_blocks, uint32_t choices, uint32_t bit
         return st;
     uint64_t bm[BBFC_MAX_CHOICES];
     uint64_t am[BBFC_MAX_BITS_PER_KEY];
-    derive_multipliers(seed, n_blocks, choices, bits_per_key, BBFC_BITS_RANDOM, bm, am);
-    return create_impl(n_blocks, choices, bits_per_key, cost, BBFC_BITS_RANDOM, bm, am, out);
+    uint64_t sm = 0;
+    derive_multipliers(seed, n_blocks, 1, choices, bits_per_key, BBFC_BITS_RANDOM, bm, am, &sm);
+    return create_impl(n_blocks, choices, bits_per_key, cost, BBFC_BITS_RANDOM, 1, 0, bm, am, out);
 }
 
 bbfc_status bbfc_create(uint64_t n_blocks, uint32_t choices, uint32_t bits_per_key, bbfc_cost cost,
@@ -505,6 +530,55 @@ bbfc_status bbfc_get_bit_selection(bbfc_handle h, int32_t *bit_selection)
     if (h == nullptr || bit_selection == nullptr)
         return fail(BBFC_EINVAL, "null handle or output pointer");
     *bit_selection = h->bit_selection;
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_bulk_insert_workspace(bbfc_handle h, uint64_t n, uint64_t *bytes)
+{
+    if (h == nullptr || bytes == nullptr)
+        return fail(BBFC_EINVAL, "null handle or output pointer");
+    if (!bbfc::bulk_supported(*h))
+        return fail(BBFC_EUNSUPPORTED, "bulk insert needs at most 1024 blocks per sub-array, this filter has %llu",
+                    (unsigned long long)h->S);
+    const uint64_t piece = n < kBulkPiece ? n : kBulkPiece;
+    *bytes = piece ? bbfc::bulk_workspace_bytes(*h, piece) : 0;
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_bulk_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, void *d_workspace,
+                             uint64_t workspace_bytes, hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (n == 0)
+        return BBFC_OK;
+    if (d_keys == nullptr)
+        return fail(BBFC_EINVAL, "null keys");
+    uint64_t need = 0;
+    bbfc_status st = bbfc_bulk_insert_workspace(h, n, &need);
+    if (st != BBFC_OK)
+        return st;
+    if (need > 0 && (d_workspace == nullptr || workspace_bytes < need))
+        return fail(BBFC_EINVAL, "the workspace needs %llu bytes, got %llu", (unsigned long long)need,
+                    (unsigned long long)workspace_bytes);
+    DeviceGuard guard(h->device);
+    for (uint64_t off = 0; off < n; off += kBulkPiece) {
+        const uint64_t m = n - off < kBulkPiece ? n - off : kBulkPiece;
+        hipError_t e = bbfc::launch_bulk_insert(*h, d_keys + off, m, d_workspace, stream);
+        if (e != hipSuccess)
+            return hip_fail(e, "launching the bulk insert");
+    }
+    return BBFC_OK;
+}
+
+bbfc_status bbfc_get_subarrays(bbfc_handle h, uint64_t *subarrays, uint64_t *sub_mult)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (subarrays)
+        *subarrays = h->T;
+    if (sub_mult)
+        *sub_mult = h->sub_mult;
     return BBFC_OK;
 }
 
@@ -753,21 +827,19 @@ uint64_t bbfc_host_block_hash(uint64_t n_blocks, uint64_t a, uint64_t x)
 {
     if (n_blocks == 0)
         return 0;
+    return bbfc::hash_mod_rt(bbfc::make_hashmod(n_blocks), a, x);
+}
+
+uint64_t bbfc_host_block_index(uint64_t n_blocks, uint64_t subarrays, uint64_t sub_mult, uint64_t a, uint64_t x)
+{
+    const uint64_t T = subarrays > 1 ? subarrays : 1;
+    if (n_blocks == 0 || n_blocks % T != 0)
+        return 0;
     bbfc::KParams p{};
-    p.M = n_blocks;
-    const bbfc::FastMod fm = bbfc::make_fastmod(n_blocks);
-    p.fm_magic = fm.magic;
-    p.fm_sh1 = fm.sh1;
-    p.fm_sh2 = fm.sh2;
-    if (n_blocks == 1)
-        return bbfc::block_hash<bbfc::kModeOne>(p, a, x);
-    if (is_pow2(n_blocks)) {
-        p.pow2_shift = 64u - (uint32_t)__builtin_ctzll(n_blocks);
-        return bbfc::block_hash<bbfc::kModePow2>(p, a, x);
-    }
-    if (n_blocks & 1)
-        return bbfc::block_hash<bbfc::kModeOdd>(p, a, x);
-    return bbfc::block_hash<bbfc::kModeEven>(p, a, x);
+    p.blk = bbfc::make_hashmod(n_blocks / T);
+    p.sub = bbfc::make_hashmod(T);
+    p.sub_mult = sub_mult;
+    return bbfc::sub_base(p, x) + bbfc::block_hash_rt(p, a, x);
 }
 
 uint32_t bbfc_host_bit_hash(uint64_t a, uint64_t x)

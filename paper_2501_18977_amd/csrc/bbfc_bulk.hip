@@ -1,0 +1,735 @@
+// Bulk insert for filters with sub-arrays (Section 3.4, Parallelization).
+//
+// The paper parallelises insertion by giving each thread a sub-array: a
+// distributor routes every key to the sub-array h_0(x) and a single writer
+// inserts it there. On the GPU the routing is a stable radix partition of the
+// keys by h_0, and the single writer of a sub-array is one wavefront that
+// stages the whole sub-array in LDS, inserts the sub-array's keys in their
+// original order, and writes the sub-array back. Nothing touches HBM at
+// random: the partition passes stream the keys, the insert streams the
+// sorted keys and each sub-array once.
+//
+// The result equals inserting the keys one at a time in index order
+// (Section 3.2 applied key by key): the partition is stable, so every
+// sub-array sees its keys in index order, and inside a sub-array the
+// wavefront takes the keys in windows of consecutive keys whose candidate
+// blocks are pairwise disjoint, so the keys of a window can be decided
+// together against the state left by all earlier windows.
+//
+// Kernels, per radix pass p (digits of h_0, least significant first):
+//   bulk_hist_kernel     per tile of 4096 keys, the count of each digit
+//   scan kernels         exclusive prefix over (digit, tile), digit-major
+//   bulk_scatter_kernel  stable scatter of each tile, staged in LDS so the
+//                        writes go out as runs
+// then bulk_insert_kernel over the sorted keys.
+#include <stdint.h>
+
+#include <utility>
+
+#include <hip/hip_runtime.h>
+
+#include "bbfc_internal.hpp"
+#include "bbfc_tile.hpp"
+
+namespace bbfc {
+
+namespace {
+
+constexpr int kPartThreads = 256;
+constexpr int kPartPerLane = 16;
+constexpr int kPartTile = kPartThreads * kPartPerLane; // 4096 keys per tile
+constexpr int kPartWaveKeys = kWave * kPartPerLane;    // 1024 keys per wavefront of a tile
+constexpr int kMaxDigitBits = 9;
+constexpr int kMaxDigits = 1 << kMaxDigitBits;
+constexpr int kScanThreads = 256;
+constexpr int kScanPerThread = 16;
+constexpr int kScanBlock = kScanThreads * kScanPerThread; // 4096 counts per scan block
+constexpr int kScanTopThreads = 1024;
+constexpr int kClaimSlots = 256;                          // hashed claim table entries per wavefront
+
+// One radix digit of h_0: (h_0(x) >> shift) & mask; MODE is the hash mode
+// of the number of sub-arrays, fixed per launch.
+struct Digit {
+    HashMod sub;
+    uint64_t sub_mult;
+    uint32_t shift;
+    uint32_t mask;
+    template <int MODE>
+    __device__ __forceinline__ uint32_t of(uint64_t x) const
+    {
+        return (uint32_t)(hash_mod<MODE>(sub, sub_mult, x) >> shift) & mask;
+    }
+};
+
+// f(integral_constant<int, R>) for R = 0..N-1, so array indices stay
+// compile-time constants however large the body.
+template <typename F, int... R>
+__device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, R...>)
+{
+    (f(std::integral_constant<int, R>{}), ...);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt(uint32_t lane)
+{
+    return lane == 0 ? 0 : (~0ull >> (64 - lane));
+}
+
+// ----------------------------------------------------------- partition
+
+template <int MODE>
+__global__ __launch_bounds__(kPartThreads) void bulk_hist_kernel(const uint64_t *__restrict__ keys, uint64_t n,
+                                                                 Digit dg, uint32_t n_digits,
+                                                                 uint32_t *__restrict__ counts, uint32_t n_tiles)
+{
+    __shared__ uint32_t h[kMaxDigits];
+    for (uint32_t i = threadIdx.x; i < n_digits; i += kPartThreads)
+        h[i] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kPartTile;
+#pragma unroll 8
+    for (int r = 0; r < kPartPerLane; ++r) {
+        const uint64_t idx = base + (uint64_t)r * kPartThreads + threadIdx.x;
+        if (idx < n)
+            atomicAdd(&h[dg.of<MODE>(keys[idx])], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n_digits; i += kPartThreads)
+        counts[(uint64_t)i * n_tiles + blockIdx.x] = h[i];
+}
+
+// Exclusive scan of uint32 counts in three launches: block sums, a scan of
+// the block sums in one workgroup, then each block rescanned with its offset.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &total)
+{
+    // Hillis-Steele over the workgroup in LDS (blockDim.x entries).
+    const uint32_t t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (uint32_t off = 1; off < blockDim.x; off <<= 1) {
+        const uint32_t add = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = sh[t];
+    total = sh[blockDim.x - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t *__restrict__ in, uint64_t len,
+                                                                   uint32_t *__restrict__ partial)
+{
+    __shared__ uint32_t sh[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock;
+    uint32_t s = 0;
+    for (int r = 0; r < kScanPerThread; ++r) {
+        const uint64_t i = base + (uint64_t)r * kScanThreads + threadIdx.x;
+        if (i < len)
+            s += in[i];
+    }
+    uint32_t total;
+    (void)block_exclusive_scan(s, sh, total);
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive scan of n_part block sums in place.
+__global__ __launch_bounds__(kScanTopThreads) void scan_partials_kernel(uint32_t *__restrict__ partial,
+                                                                        uint32_t n_part)
+{
+    __shared__ uint32_t sh[kScanTopThreads];
+    const uint32_t per = (n_part + kScanTopThreads - 1) / kScanTopThreads;
+    const uint32_t lo = threadIdx.x * per;
+    uint32_t s = 0;
+    for (uint32_t i = lo; i < lo + per && i < n_part; ++i)
+        s += partial[i];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, sh, total);
+    for (uint32_t i = lo; i < lo + per && i < n_part; ++i) {
+        const uint32_t v = partial[i];
+        partial[i] = run;
+        run += v;
+    }
+}
+
+// Each thread owns kScanPerThread consecutive counts of the block.
+__global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__restrict__ data, uint64_t len,
+                                                                  const uint32_t *__restrict__ partial)
+{
+    __shared__ uint32_t sh[kScanThreads];
+    const uint64_t base = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)threadIdx.x * kScanPerThread;
+    uint32_t v[kScanPerThread];
+    uint32_t s = 0;
+#pragma unroll
+    for (int r = 0; r < kScanPerThread; ++r) {
+        v[r] = base + r < len ? data[base + r] : 0;
+        s += v[r];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, sh, total) + partial[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < kScanPerThread; ++r) {
+        if (base + r < len)
+            data[base + r] = run;
+        run += v[r];
+    }
+}
+
+// Stable scatter of one tile. Wavefront w owns the tile's keys
+// [w*1024, (w+1)*1024), lane l round r takes key w*1024 + 64r + l, so key
+// order is (w, r, l). 1) per-wavefront digit counts; 2) where each
+// (wavefront, digit) run starts inside the tile's staging area; 3) every
+// round ranks its keys among equal digits of the round (ballot matching)
+// and stages them; 4) the staged tile, now ordered by digit, is written to
+// the digit runs the scan assigned to this tile.
+template <int MODE>
+__global__ __launch_bounds__(kPartThreads) void bulk_scatter_kernel(const uint64_t *__restrict__ in,
+                                                                    uint64_t *__restrict__ out, uint64_t n, Digit dg,
+                                                                    uint32_t n_digits,
+                                                                    const uint32_t *__restrict__ offsets,
+                                                                    uint32_t n_tiles)
+{
+    extern __shared__ uint64_t staged[]; // kPartTile keys
+    __shared__ uint32_t wcnt[kPartThreads / kWave][kMaxDigits];
+    __shared__ uint32_t tpre[kMaxDigits]; // digit run start inside the tile
+    __shared__ uint32_t gofs[kMaxDigits]; // digit run start in the output
+    __shared__ uint32_t scan_sh[kPartThreads];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t w = threadIdx.x / kWave;
+    const uint64_t tile_base = (uint64_t)blockIdx.x * kPartTile;
+    const uint64_t wave_base = tile_base + (uint64_t)w * kPartWaveKeys;
+
+    uint64_t key[kPartPerLane];
+#pragma unroll
+    for (int r = 0; r < kPartPerLane; ++r) {
+        const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
+        key[r] = idx < n ? in[idx] : 0;
+    }
+    for (uint32_t d = lane; d < n_digits; d += kWave)
+        wcnt[w][d] = 0;
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < kPartPerLane; ++r) {
+        const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
+        if (idx < n)
+            atomicAdd(&wcnt[w][dg.of<MODE>(key[r])], 1u);
+    }
+    __syncthreads();
+
+    // digit totals of the tile, their exclusive prefix, and the per-wavefront
+    // run starts (digits d = t and t + 256 for thread t)
+    uint32_t tot[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t d = threadIdx.x + h * kPartThreads;
+        if (d < n_digits)
+            for (int ww = 0; ww < kPartThreads / kWave; ++ww)
+                tot[h] += wcnt[ww][d];
+    }
+    uint32_t total0;
+    const uint32_t pre0 = block_exclusive_scan(tot[0], scan_sh, total0);
+    uint32_t total1;
+    const uint32_t pre1 = block_exclusive_scan(tot[1], scan_sh, total1) + total0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t d = threadIdx.x + h * kPartThreads;
+        if (d < n_digits) {
+            uint32_t run = h == 0 ? pre0 : pre1;
+            tpre[d] = run;
+            gofs[d] = offsets[(uint64_t)d * n_tiles + blockIdx.x];
+            for (int ww = 0; ww < kPartThreads / kWave; ++ww) {
+                const uint32_t c = wcnt[ww][d];
+                wcnt[ww][d] = run;
+                run += c;
+            }
+        }
+    }
+    __syncthreads();
+
+    static_for(
+        [&](auto rc) __attribute__((always_inline)) {
+            constexpr int r = decltype(rc)::value;
+            const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
+            const bool valid = idx < n;
+            const uint32_t d = valid ? dg.of<MODE>(key[r]) : 0;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < kMaxDigitBits; ++b) { // bits above the digit are zero in every lane
+                const uint64_t m = __ballot((d >> b) & 1);
+                peers &= ((d >> b) & 1) ? m : ~m;
+            }
+            if (valid) {
+                const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt(lane));
+                const uint32_t pos = wcnt[w][d] + rank;
+                staged[pos] = key[r];
+            }
+            wave_sync(); // every lane has read its run start before the leader moves it
+            if (valid && (peers & lanemask_lt(lane)) == 0)
+                wcnt[w][d] += (uint32_t)__popcll(peers);
+            wave_sync();
+        },
+        std::make_integer_sequence<int, kPartPerLane>{});
+    __syncthreads();
+
+    const uint64_t left = n - tile_base;
+    const uint32_t in_tile = left < (uint64_t)kPartTile ? (uint32_t)left : (uint32_t)kPartTile;
+    for (uint32_t i = threadIdx.x; i < in_tile; i += kPartThreads) {
+        const uint64_t x = staged[i];
+        const uint32_t d = dg.of<MODE>(x);
+        out[(uint64_t)gofs[d] + (i - tpre[d])] = x;
+    }
+}
+
+// --------------------------------------------------------------- insert
+
+// LDS of one wavefront of the insert kernel.
+template <int SUB, int C>
+struct WaveLds {
+    static constexpr size_t kSub = (size_t)SUB * 64;                    // the staged sub-array
+    static constexpr size_t kSlots = (size_t)kTile * kSlotDw * 4;       // key masks
+    static constexpr size_t kClaim = (size_t)kClaimSlots * 8;          // claim bits
+    static constexpr size_t kBytes = kSub + kSlots + kClaim;
+};
+
+// Lane src's 64-bit value.
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Each wavefront takes the sub-arrays whose run of sorted keys starts in its
+// share [c0, c1) of the positions, and for each: stages the sub-array in
+// LDS, inserts the run's keys in order in windows of disjoint candidates,
+// and writes the sub-array back. S <= SUB blocks per sub-array.
+template <int C, int SUB>
+__global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint64_t *__restrict__ sorted, uint64_t n,
+                                                           uint32_t waves_per_wg, uint64_t n_waves)
+{
+    using WL = WaveLds<SUB, C>;
+    constexpr int LPK = 8;
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint16_t *s_rank = reinterpret_cast<uint16_t *>(lds);
+    const size_t rank_bytes = C > 1 ? (((size_t)(p.k + 1) * kRankStride * 2 + 15) & ~(size_t)15) : 0;
+    if constexpr (C > 1) {
+        const uint32_t nr = (p.k + 1) * kRankStride;
+        for (uint32_t i = threadIdx.x; i < nr; i += blockDim.x)
+            s_rank[i] = p.rank[i];
+    }
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave;
+    uint8_t *mine = lds + rank_bytes + (size_t)wv * WL::kBytes;
+    uint64_t *sub = reinterpret_cast<uint64_t *>(mine);
+    uint32_t *smask = reinterpret_cast<uint32_t *>(mine + WL::kSub);
+    uint64_t *claim = reinterpret_cast<uint64_t *>(mine + WL::kSub + WL::kSlots);
+    for (int i = lane; i < kClaimSlots; i += kWave)
+        claim[i] = 0;
+
+    const uint64_t S = p.blk.b;
+    const uint64_t gw = (uint64_t)blockIdx.x * waves_per_wg + wv;
+    const uint64_t c0 = n * gw / n_waves;
+    const uint64_t c1 = n * (gw + 1) / n_waves;
+    auto h0 = [&](uint64_t x) { return hash_mod_rt(p.sub, p.sub_mult, x); };
+
+    uint64_t pos = c0;
+    if (pos > 0 && pos < c1) {
+        // the run of the sub-array that started before c0 belongs to the previous share
+        const uint64_t prev = h0(sorted[pos - 1]);
+        for (;;) {
+            const uint64_t idx = pos + lane;
+            const bool same = idx < n && h0(sorted[idx]) == prev;
+            const uint64_t b = __ballot(same);
+            const uint32_t cnt = (uint32_t)__popcll(b); // the equal keys form a prefix of the lanes
+            pos += cnt;
+            if (cnt < kWave)
+                break;
+        }
+    }
+
+    const uint32_t g = lane / LPK;
+    const uint32_t w0 = lane % LPK;
+    constexpr int kSubIters = SUB * 8 / (2 * kWave); // 16-byte pieces per lane of a staged sub-array
+    constexpr int kBatch = kSubIters < 8 ? kSubIters : 8;
+    const uint64_t n_words = S * 8;
+    uint64_t v = pos < c1 ? uniform_u64(h0(sorted[pos])) : 0;
+    while (pos < c1) {
+        // stage sub-array v; its first chunk of keys is loaded alongside
+        uint64_t *gsub = p.words + v * S * 8;
+        uint64_t x = pos + lane < n ? sorted[pos + lane] : 0;
+#pragma unroll
+        for (int b0 = 0; b0 < kSubIters; b0 += kBatch) {
+            ulonglong2 t[kBatch];
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const uint64_t i = (uint64_t)(b0 + b) * 2 * kWave + lane * 2;
+                t[b] = i < n_words ? *reinterpret_cast<const ulonglong2 *>(gsub + i) : make_ulonglong2(0, 0);
+            }
+#pragma unroll
+            for (int b = 0; b < kBatch; ++b) {
+                const uint64_t i = (uint64_t)(b0 + b) * 2 * kWave + lane * 2;
+                if (i < n_words) {
+                    sub[i] = t[b].x;
+                    sub[i + 1] = t[b].y;
+                }
+            }
+        }
+        wave_sync();
+
+        uint64_t v_next = 0;
+        bool v_next_known = false;
+        for (;;) {
+            const bool valid = pos + lane < n && h0(x) == v;
+            const uint64_t vb = __ballot(valid);
+            const uint32_t n_valid = (uint32_t)__popcll(vb); // a prefix of the lanes
+            if (n_valid == 0)
+                break;
+            if (n_valid < (uint32_t)kWave && pos + n_valid < n) {
+                // lane n_valid holds the first key of the next sub-array's run
+                v_next = uniform_u64(shfl_u64(h0(x), (int)n_valid));
+                v_next_known = true;
+            }
+
+            // key masks into LDS slots, candidate blocks (inside the sub-array) in registers
+            uint32_t *slot = smask + lane * kSlotDw;
+#pragma unroll
+            for (int d = 0; d < 16; d += 2)
+                *reinterpret_cast<uint2 *>(slot + d) = make_uint2(0, 0);
+            wave_sync();
+            auto set_bit = [slot](uint32_t f) { atomicOr(slot + (f >> 5), 1u << (f & 31)); };
+            if (valid) {
+                if (p.distinct)
+                    distinct_bits(p.bit_mult, p.k, x, set_bit);
+                else
+                    random_bits(p.bit_mult, p.k, x, set_bit);
+            }
+            uint32_t cand[C];
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                cand[i] = (uint32_t)hash_mod_rt(p.blk, p.block_mult[i], x);
+
+            // the next chunk's keys are in flight while this chunk is inserted
+            // (issued after the last use of x, so waiting for x does not wait for them)
+            const uint64_t nidx = pos + kWave + lane;
+            const bool more = n_valid == (uint32_t)kWave;
+            const uint64_t x_next = more && nidx < n ? sorted[nidx] : 0;
+
+            // P: earlier keys of the same 8-key round that share a candidate
+            // (claim bits hashed into kClaimSlots entries; a collision only
+            // splits a window)
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    atomicOr((unsigned long long *)&claim[cand[i] % kClaimSlots], 1ull << lane);
+            }
+            wave_sync();
+            uint64_t P = 0;
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                P |= claim[cand[i] % kClaimSlots];
+            P &= lanemask_lt(lane) & ~lanemask_lt(lane & ~7u);
+            wave_sync();
+            if (valid) {
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    claim[cand[i] % kClaimSlots] = 0;
+            }
+
+            // Round r takes keys 8r..8r+7, group g key 8r+g: its candidates
+            // and its mask word w0, fetched for all rounds before any round runs.
+            uint32_t rc[8][C];
+            uint64_t mw[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int src = 8 * r + (int)g;
+#pragma unroll
+                for (int i = 0; i < C; ++i)
+                    rc[r][i] = (uint32_t)__shfl((int)cand[i], src);
+                const uint32_t *ks = smask + src * kSlotDw + 2 * w0;
+                mw[r] = *reinterpret_cast<const uint64_t *>(ks);
+            }
+
+            static_for(
+                [&](auto rconst) __attribute__((always_inline)) {
+                    constexpr int r = decltype(rconst)::value;
+                    const uint32_t lo = 8 * r;
+                    const uint32_t hi = lo + 8 < n_valid ? lo + 8 : n_valid;
+                    uint32_t s = lo;
+                    while (s < hi) {
+                        const uint64_t conflict = __ballot(lane > s && lane < hi && (P >> s) != 0);
+                        const uint32_t e = conflict ? (uint32_t)__builtin_ctzll(conflict) : hi;
+                        const uint32_t t = lo + g;
+                        const bool active = t >= s && t < e;
+                        uint64_t B[C][1];
+#pragma unroll
+                        for (int i = 0; i < C; ++i)
+                            B[i][0] = sub[(uint64_t)rc[r][i] * 8 + w0];
+                        const uint64_t m[1] = {mw[r]};
+                        const JA<C> ja = reduce_ja<C, LPK, 1>(B, m);
+                        const int best = decide<C>(ja, s_rank);
+                        if (active && best >= 0) {
+                            uint32_t blk = rc[r][0];
+#pragma unroll
+                            for (int i = 1; i < C; ++i)
+                                blk = best == i ? rc[r][i] : blk;
+                            const uint64_t old = pick<C, 1>(B, best, 0);
+                            if (m[0] & ~old)
+                                sub[(uint64_t)blk * 8 + w0] = old | m[0];
+                        }
+                        wave_sync();
+                        s = e;
+                    }
+                },
+                std::make_integer_sequence<int, 8>{});
+            pos += n_valid;
+            if (!more)
+                break;
+            x = x_next;
+        }
+
+        wave_sync();
+#pragma unroll
+        for (int b = 0; b < kSubIters; ++b) {
+            const uint64_t i = (uint64_t)b * 2 * kWave + lane * 2;
+            if (i < n_words) {
+                ulonglong2 t;
+                t.x = sub[i];
+                t.y = sub[i + 1];
+                *reinterpret_cast<ulonglong2 *>(gsub + i) = t;
+            }
+        }
+        wave_sync();
+        if (pos >= c1 || pos >= n)
+            break;
+        v = v_next_known ? v_next : uniform_u64(h0(sorted[pos]));
+    }
+}
+
+// ------------------------------------------------------------- planning
+
+struct Plan {
+    uint32_t passes = 0;
+    uint32_t bits[3] = {0, 0, 0};
+    uint64_t n_tiles = 0;
+    uint64_t counts_len = 0; // max over passes of n_digits * n_tiles
+    uint64_t n_scan_blocks = 0;
+    int sub_max = 0;         // LDS sub-array capacity in blocks
+    // workspace layout (bytes, 256-aligned)
+    uint64_t off_keys_a = 0, off_keys_b = 0, off_counts = 0, off_partial = 0, bytes = 0;
+};
+
+uint64_t align256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }
+
+int sub_capacity(uint64_t S)
+{
+    if (S <= 256)
+        return 256;
+    if (S <= 512)
+        return 512;
+    if (S <= 1024)
+        return 1024;
+    return 0;
+}
+
+Plan make_plan(const bbfc_filter &f, uint64_t n)
+{
+    Plan pl;
+    uint32_t tbits = 0;
+    while (tbits < 64 && ((uint64_t)1 << tbits) < f.T)
+        ++tbits;
+    pl.passes = (tbits + kMaxDigitBits - 1) / kMaxDigitBits;
+    for (uint32_t q = 0; q < pl.passes; ++q) { // spread the bits evenly over the passes
+        pl.bits[q] = tbits / pl.passes + (q < tbits % pl.passes ? 1 : 0);
+    }
+    pl.n_tiles = (n + kPartTile - 1) / kPartTile;
+    uint32_t max_bits = 0;
+    for (uint32_t q = 0; q < pl.passes; ++q)
+        max_bits = pl.bits[q] > max_bits ? pl.bits[q] : max_bits;
+    pl.counts_len = ((uint64_t)1 << max_bits) * pl.n_tiles;
+    pl.n_scan_blocks = (pl.counts_len + kScanBlock - 1) / kScanBlock;
+    pl.sub_max = sub_capacity(f.S);
+    uint64_t at = 0;
+    if (pl.passes >= 1) {
+        pl.off_keys_a = at;
+        at = align256(at + n * 8);
+    }
+    if (pl.passes >= 2) {
+        pl.off_keys_b = at;
+        at = align256(at + n * 8);
+    }
+    if (pl.passes >= 1) {
+        pl.off_counts = at;
+        at = align256(at + pl.counts_len * 4);
+        pl.off_partial = at;
+        at = align256(at + pl.n_scan_blocks * 4);
+    }
+    pl.bytes = at;
+    return pl;
+}
+
+template <int C, int SUB>
+size_t insert_lds_bytes(uint32_t k, uint32_t waves)
+{
+    const size_t rank = C > 1 ? (((size_t)(k + 1) * kRankStride * 2 + 15) & ~(size_t)15) : 0;
+    return rank + (size_t)waves * WaveLds<SUB, C>::kBytes;
+}
+
+template <int C, int SUB>
+hipError_t launch_insert_sub(const bbfc_filter &f, const uint64_t *sorted, uint64_t n, hipStream_t s)
+{
+    const size_t per = WaveLds<SUB, C>::kBytes;
+    const size_t rank = insert_lds_bytes<C, SUB>(f.k, 0);
+    if (f.max_lds < rank + per)
+        return hipErrorInvalidValue;
+    uint32_t waves = (uint32_t)((f.max_lds - rank) / per);
+    if (waves > 8) // the kernel's launch bound: 512 threads
+        waves = 8;
+    const size_t lds = rank + waves * per;
+    // one workgroup per CU: the LDS holds `waves` sub-arrays at a time
+    uint64_t wgs = (uint64_t)(f.num_cus > 0 ? f.num_cus : 256);
+    const uint64_t n_waves = wgs * waves;
+    hipError_t e = hipFuncSetAttribute((const void *)bulk_insert_kernel<C, SUB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((bulk_insert_kernel<C, SUB>), dim3((uint32_t)wgs), dim3(waves * kWave), lds, s,
+                       make_kparams(f), sorted, n, waves, n_waves);
+    return hipGetLastError();
+}
+
+template <int C>
+hipError_t launch_insert_c(const bbfc_filter &f, int sub_max, const uint64_t *sorted, uint64_t n, hipStream_t s)
+{
+    switch (sub_max) {
+    case 256:
+        return launch_insert_sub<C, 256>(f, sorted, n, s);
+    case 512:
+        return launch_insert_sub<C, 512>(f, sorted, n, s);
+    default:
+        return launch_insert_sub<C, 1024>(f, sorted, n, s);
+    }
+}
+
+template <int MODE>
+hipError_t launch_hist_m(uint32_t n_tiles, hipStream_t s, const uint64_t *src, uint64_t n, const Digit &dg,
+                         uint32_t n_digits, uint32_t *counts)
+{
+    hipLaunchKernelGGL(bulk_hist_kernel<MODE>, dim3(n_tiles), dim3(kPartThreads), 0, s, src, n, dg, n_digits, counts,
+                       n_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist(uint32_t mode, uint32_t n_tiles, hipStream_t s, const uint64_t *src, uint64_t n,
+                       const Digit &dg, uint32_t n_digits, uint32_t *counts)
+{
+    switch (mode) {
+    case kModePow2:
+        return launch_hist_m<kModePow2>(n_tiles, s, src, n, dg, n_digits, counts);
+    case kModeEven:
+        return launch_hist_m<kModeEven>(n_tiles, s, src, n, dg, n_digits, counts);
+    default:
+        return launch_hist_m<kModeOdd>(n_tiles, s, src, n, dg, n_digits, counts);
+    }
+}
+
+template <int MODE>
+hipError_t launch_scatter_m(uint32_t n_tiles, hipStream_t s, const uint64_t *src, uint64_t *dst, uint64_t n,
+                            const Digit &dg, uint32_t n_digits, const uint32_t *offsets)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)bulk_scatter_kernel<MODE>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kPartTile * 8);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(bulk_scatter_kernel<MODE>, dim3(n_tiles), dim3(kPartThreads), kPartTile * 8, s, src, dst, n,
+                       dg, n_digits, offsets, n_tiles);
+    return hipGetLastError();
+}
+
+// Radix passes run only with T > 1 sub-arrays, so the mode of T is never One.
+hipError_t launch_scatter(uint32_t mode, uint32_t n_tiles, hipStream_t s, const uint64_t *src, uint64_t *dst,
+                          uint64_t n, const Digit &dg, uint32_t n_digits, const uint32_t *offsets)
+{
+    switch (mode) {
+    case kModePow2:
+        return launch_scatter_m<kModePow2>(n_tiles, s, src, dst, n, dg, n_digits, offsets);
+    case kModeEven:
+        return launch_scatter_m<kModeEven>(n_tiles, s, src, dst, n, dg, n_digits, offsets);
+    default:
+        return launch_scatter_m<kModeOdd>(n_tiles, s, src, dst, n, dg, n_digits, offsets);
+    }
+}
+
+} // namespace
+
+uint64_t bulk_workspace_bytes(const bbfc_filter &f, uint64_t n)
+{
+    return make_plan(f, n).bytes;
+}
+
+bool bulk_supported(const bbfc_filter &f)
+{
+    return sub_capacity(f.S) != 0 && make_plan(f, 1).passes <= 3;
+}
+
+hipError_t launch_bulk_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, void *workspace,
+                              hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    const Plan pl = make_plan(f, n);
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    uint64_t *bufs[2] = {reinterpret_cast<uint64_t *>(ws + pl.off_keys_a),
+                         reinterpret_cast<uint64_t *>(ws + pl.off_keys_b)};
+    uint32_t *counts = reinterpret_cast<uint32_t *>(ws + pl.off_counts);
+    uint32_t *partial = reinterpret_cast<uint32_t *>(ws + pl.off_partial);
+    const uint64_t *src = keys;
+    uint32_t shift = 0;
+    for (uint32_t q = 0; q < pl.passes; ++q) {
+        Digit dg;
+        dg.sub = f.sub;
+        dg.sub_mult = f.sub_mult;
+        dg.shift = shift;
+        dg.mask = (1u << pl.bits[q]) - 1;
+        const uint32_t n_digits = 1u << pl.bits[q];
+        const uint64_t len = (uint64_t)n_digits * pl.n_tiles;
+        const uint64_t n_blocks = (len + kScanBlock - 1) / kScanBlock;
+        uint64_t *dst = bufs[q & 1];
+        hipError_t e = launch_hist(f.sub.mode, (uint32_t)pl.n_tiles, s, src, n, dg, n_digits, counts);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(scan_reduce_kernel, dim3((uint32_t)n_blocks), dim3(kScanThreads), 0, s, counts, len,
+                           partial);
+        hipLaunchKernelGGL(scan_partials_kernel, dim3(1), dim3(kScanTopThreads), 0, s, partial,
+                           (uint32_t)n_blocks);
+        hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)n_blocks), dim3(kScanThreads), 0, s, counts, len,
+                           partial);
+        e = launch_scatter(f.sub.mode, (uint32_t)pl.n_tiles, s, src, dst, n, dg, n_digits, counts);
+        if (e != hipSuccess)
+            return e;
+        src = dst;
+        shift += pl.bits[q];
+    }
+    switch (f.c) {
+    case 1:
+        return launch_insert_c<1>(f, pl.sub_max, src, n, s);
+    case 2:
+        return launch_insert_c<2>(f, pl.sub_max, src, n, s);
+    case 3:
+        return launch_insert_c<3>(f, pl.sub_max, src, n, s);
+    default:
+        return launch_insert_c<4>(f, pl.sub_max, src, n, s);
+    }
+}
+
+} // namespace bbfc

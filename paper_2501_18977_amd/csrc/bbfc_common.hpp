@@ -16,12 +16,12 @@
 
 namespace bbfc {
 
-// How block addresses reduce a*x into [0, M).
+// How the linear hash reduces a*x into [0, b).
 enum HashMode : int {
-    kModeOne = 0,  // M == 1: every key maps to block 0
-    kModePow2 = 1, // M == 2^s: top s bits
-    kModeEven = 2, // M even, not 2^s: fold, then remainder
-    kModeOdd = 3,  // M odd: remainder
+    kModeOne = 0,  // b == 1: every key maps to 0
+    kModePow2 = 1, // b == 2^s: top s bits
+    kModeEven = 2, // b even, not 2^s: fold, then remainder
+    kModeOdd = 3,  // b odd: remainder
 };
 
 // Remainder by an invariant 64-bit divisor d >= 1 without a division
@@ -74,54 +74,92 @@ __host__ __device__ __forceinline__ uint64_t fastmod(uint64_t n, uint64_t d, uin
     return n - q * d;
 }
 
-// Everything a kernel needs to address the filter, passed by value.
+// A modulus b of the linear hash with what its reduction needs.
+struct HashMod {
+    uint64_t b;
+    uint64_t magic;         // FastMod of b (modes Even, Odd)
+    uint32_t sh1;
+    uint32_t sh2;
+    uint32_t pow2_shift;    // 64 - log2(b) (mode Pow2)
+    uint32_t mode;          // HashMode of b
+};
+
+inline HashMod make_hashmod(uint64_t b)
+{
+    HashMod h{};
+    h.b = b;
+    const FastMod fm = make_fastmod(b);
+    h.magic = fm.magic;
+    h.sh1 = fm.sh1;
+    h.sh2 = fm.sh2;
+    if (b == 1) {
+        h.mode = kModeOne;
+    } else if ((b & (b - 1)) == 0) {
+        h.mode = kModePow2;
+        h.pow2_shift = 64u - (uint32_t)__builtin_ctzll(b);
+    } else {
+        h.mode = (b & 1) ? kModeOdd : kModeEven;
+    }
+    return h;
+}
+
+template <int MODE>
+__host__ __device__ __forceinline__ uint64_t hash_mod(const HashMod &h, uint64_t a, uint64_t x)
+{
+    const uint64_t prod = a * x;
+    if constexpr (MODE == kModeOne) {
+        return 0;
+    } else if constexpr (MODE == kModePow2) {
+        return prod >> h.pow2_shift;
+    } else if constexpr (MODE == kModeEven) {
+        return fastmod(prod ^ (prod >> 32), h.b, h.magic, h.sh1, h.sh2);
+    } else {
+        return fastmod(prod, h.b, h.magic, h.sh1, h.sh2);
+    }
+}
+
+// The mode read at run time (uniform across a wavefront).
+__host__ __device__ __forceinline__ uint64_t hash_mod_rt(const HashMod &h, uint64_t a, uint64_t x)
+{
+    switch (h.mode) {
+    case kModeOne:
+        return hash_mod<kModeOne>(h, a, x);
+    case kModePow2:
+        return hash_mod<kModePow2>(h, a, x);
+    case kModeEven:
+        return hash_mod<kModeEven>(h, a, x);
+    default:
+        return hash_mod<kModeOdd>(h, a, x);
+    }
+}
+
+// Everything a kernel needs to address the filter, passed by value. The M
+// blocks form T sub-arrays of S = M/T blocks (Section 3.4, Parallelization):
+// h_0(x) (modulus T, multiplier sub_mult) picks the sub-array and the block
+// hashes (modulus S) the block inside it. T = 1 is a single array, S = M.
 struct KParams {
     uint64_t *words;        // 8*M words, block b = words[8b .. 8b+8)
     const uint16_t *rank;   // (k+1)*513 cost ranks, index a*513 + j
-    uint64_t M;
-    uint64_t fm_magic;      // FastMod of M (modes Even, Odd)
-    uint32_t fm_sh1;
-    uint32_t fm_sh2;
-    uint32_t pow2_shift;    // 64 - log2(M) (mode Pow2)
+    HashMod blk;            // modulus S of the block hashes h_1..h_c
+    HashMod sub;            // modulus T of the sub-array hash h_0
+    uint64_t sub_mult;
     uint32_t k;
-    uint32_t mode;          // HashMode of M
     uint32_t c;             // choices (informational; kernels take C as a template)
     uint32_t distinct;      // bit selection: 0 random, 1 distinct
     uint64_t block_mult[BBFC_MAX_CHOICES];
     uint64_t bit_mult[BBFC_MAX_BITS_PER_KEY];
 };
 
-template <int MODE>
-__host__ __device__ __forceinline__ uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x);
-
-// The hash mode read from the parameters (uniform across a wavefront).
+// Block index inside the key's sub-array, for block multiplier a.
 __host__ __device__ __forceinline__ uint64_t block_hash_rt(const KParams &p, uint64_t a, uint64_t x)
 {
-    switch (p.mode) {
-    case kModeOne:
-        return block_hash<kModeOne>(p, a, x);
-    case kModePow2:
-        return block_hash<kModePow2>(p, a, x);
-    case kModeEven:
-        return block_hash<kModeEven>(p, a, x);
-    default:
-        return block_hash<kModeOdd>(p, a, x);
-    }
+    return hash_mod_rt(p.blk, a, x);
 }
 
-template <int MODE>
-__host__ __device__ __forceinline__ uint64_t block_hash(const KParams &p, uint64_t a, uint64_t x)
+// First block of the key's sub-array: h_0(x) * S (0 for a single array).
+__host__ __device__ __forceinline__ uint64_t sub_base(const KParams &p, uint64_t x)
 {
-    uint64_t prod = a * x;
-    if constexpr (MODE == kModeOne) {
-        return 0;
-    } else if constexpr (MODE == kModePow2) {
-        return prod >> p.pow2_shift;
-    } else if constexpr (MODE == kModeEven) {
-        return fastmod(prod ^ (prod >> 32), p.M, p.fm_magic, p.fm_sh1, p.fm_sh2);
-    } else {
-        return fastmod(prod, p.M, p.fm_magic, p.fm_sh1, p.fm_sh2);
-    }
+    return p.sub.b == 1 ? 0 : hash_mod_rt(p.sub, p.sub_mult, x) * p.blk.b;
 }
 
 // Bit address in [0, 512): the top 9 bits of a*x (b = 512 = 2^9).

@@ -16,9 +16,11 @@ struct bbfc_filter {
     uint64_t block_mult[BBFC_MAX_CHOICES] = {};
     uint64_t bit_mult[BBFC_MAX_BITS_PER_KEY] = {};
     int32_t bit_selection = BBFC_BITS_RANDOM;
-    int hash_mode = bbfc::kModeOne;
-    bbfc::FastMod fm{};
-    uint32_t pow2_shift = 0;
+    uint64_t T = 1;               // sub-arrays (Section 3.4, Parallelization)
+    uint64_t S = 0;               // blocks per sub-array, M / T
+    uint64_t sub_mult = 0;        // multiplier of h_0 (T > 1)
+    bbfc::HashMod blk{};          // modulus S
+    bbfc::HashMod sub{};          // modulus T
     uint64_t *d_words = nullptr;  // 8*M words
     uint16_t *d_rank = nullptr;   // (k+1)*513 ranks, null for one choice
     std::vector<uint16_t> h_rank;
@@ -65,6 +67,13 @@ hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, 
                         hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s);
 hipError_t launch_load_histogram(const bbfc_filter &f, uint64_t *hist, hipStream_t s);
+
+// Bulk insert through a stable partition by sub-array (bbfc_bulk.hip).
+// n < 2^32 keys per launch; the workspace holds bulk_workspace_bytes(f, n).
+bool bulk_supported(const bbfc_filter &f);
+uint64_t bulk_workspace_bytes(const bbfc_filter &f, uint64_t n);
+hipError_t launch_bulk_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, void *workspace,
+                              hipStream_t s);
 
 // Canonical q-grams of a 2-bit packed sequence cut into segments (see
 // bbfc_kmer_keys): fused insert and query, and the keys written out.

@@ -162,13 +162,10 @@ KParams make_kparams(const bbfc_filter &f)
     KParams p{};
     p.words = f.d_words;
     p.rank = f.d_rank;
-    p.M = f.M;
-    p.fm_magic = f.fm.magic;
-    p.fm_sh1 = f.fm.sh1;
-    p.fm_sh2 = f.fm.sh2;
-    p.pow2_shift = f.pow2_shift;
+    p.blk = f.blk;
+    p.sub = f.sub;
+    p.sub_mult = f.sub_mult;
     p.k = f.k;
-    p.mode = (uint32_t)f.hash_mode;
     p.c = f.c;
     p.distinct = f.bit_selection == BBFC_BITS_DISTINCT ? 1u : 0u;
     for (uint32_t i = 0; i < f.c; ++i)

@@ -157,9 +157,10 @@ __device__ __forceinline__ void phase_a(const KParams &p, const Src &src, uint64
         distinct_bits(p.bit_mult, p.k, x, set_bit);
     else
         random_bits(p.bit_mult, p.k, x, set_bit);
+    const uint64_t first = sub_base(p, x);
 #pragma unroll
     for (int i = 0; i < C; ++i)
-        sblk[lane * C + i] = block_hash_rt(p, p.block_mult[i], x);
+        sblk[lane * C + i] = first + block_hash_rt(p, p.block_mult[i], x);
 }
 
 template <int KW>
@@ -212,8 +213,7 @@ __device__ __forceinline__ void query_tiles(const KParams &p, const Src &keys, u
     const uint32_t g = lane / LPK;
     const uint32_t w0 = (lane % LPK) * KW;
 
-#pragma unroll
-    for (int tt = 0; tt < T; ++tt)
+    for (int tt = 0; tt < T; ++tt) // T = 1 or 2; phase A writes only LDS, no registers carry over
         phase_a<C>(p, keys, n, base + (uint64_t)tt * kTile, lane, smask + tt * kTile * kSlotDw, sblk + tt * kTile * C);
     wave_sync();
 
@@ -378,8 +378,7 @@ __device__ __forceinline__ void insert_tiles(const KParams &p, const uint16_t *r
     const uint32_t g = lane / LPK;
     const uint32_t w0 = (lane % LPK) * KW;
 
-#pragma unroll
-    for (int tt = 0; tt < T; ++tt)
+    for (int tt = 0; tt < T; ++tt) // T = 1 or 2; phase A writes only LDS, no registers carry over
         phase_a<C>(p, keys, n, base + (uint64_t)tt * kTile, lane, smask + tt * kTile * kSlotDw, sblk + tt * kTile * C);
     wave_sync();
 

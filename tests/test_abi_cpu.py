@@ -64,6 +64,18 @@ def test_block_hash_source_matches_oracle(M):
         assert bbfc.host_block_hash(M, a, x) == oracle.hash_(a, x, M)
 
 
+@pytest.mark.parametrize("M,T", [(1 << 15, 1 << 6), (1 << 15, 1), (3 * 1024, 3), (6000, 12), (7, 7),
+                                 ((1 << 25), 1 << 15), (1001 * 64, 1001)])
+def test_block_index_source_matches_oracle(M, T):
+    """Sub-array addressing (Section 3.4, Parallelization) compiled for the
+    host: h_0(x) S + h_i(x) equals the oracle's for pow2, even and odd T, S."""
+    S = M // T
+    sm = workload.draw_multipliers(T, 1, coprime_to=T)[0] if T > 1 else 0
+    for a in workload.draw_multipliers(M % 91, 3, coprime_to=S):
+        for x in list(workload.positive_keys(M % 53, 300)) + [0, (1 << 64) - 1]:
+            assert bbfc.host_block_index(M, T, sm, a, int(x)) == oracle.block_index(M, T, sm, a, int(x))
+
+
 def test_bit_hash_source_matches_oracle():
     for a in workload.draw_multipliers(3, 16):
         for x in workload.positive_keys(3, 300):
@@ -144,6 +156,13 @@ def test_create_rejects_bad_multipliers():
                     bit_selection="distinct")
     with pytest.raises(bbfc.BBFCError, match="unknown bit selection"):
         bbfc.Filter(8, 2, 2, "exp", bit_selection=5)
+    with pytest.raises(bbfc.BBFCError, match="must divide n_blocks"):
+        bbfc.Filter(1000, 2, 8, "exp", subarrays=3)
+    with pytest.raises(bbfc.BBFCError, match="not coprime to subarrays"):
+        bbfc.Filter(1024, 2, 8, "exp", subarrays=4, sub_mult=(1 << 40) + 2)
+    with pytest.raises(bbfc.BBFCError, match="blocks per sub-array"):
+        bbfc.Filter(3 * 512, 2, 8, "exp", subarrays=512, block_mult=[3 * ((1 << 40) + 1)] * 2,
+                    bit_mult=[(1 << 40) + 1] * 8)
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 5, 8, 14, 17, 20, 31, 32])
