@@ -54,6 +54,10 @@ def parse_args():
     ap.add_argument("--log2-keys", type=int, default=30, help="keys to insert (2^n); blocks = keys/32")
     ap.add_argument("--bits", choices=["random", "distinct"], default="random",
                     help="plain workload: bit selection strategy (Section 3.3)")
+    ap.add_argument("--subarray-blocks", type=int, default=0,
+                    help="plain workload: blocks per sub-array (Section 3.4; 0 = one array)")
+    ap.add_argument("--insert", choices=["racing", "bulk"], default="racing",
+                    help="plain workload: racing atomic insert, or the sequential bulk insert (needs sub-arrays)")
     ap.add_argument("--filters", type=int, default=256, help="batch workload: number of filters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
@@ -150,14 +154,14 @@ def kernel_name(op: str, c: int, shape: dict, early: bool = True) -> str:
     return f"query_kernel<{c}, {lpk}, {tpw}, {ee}, ArrayKeys>"
 
 
-def cpu_baseline(n_blocks, c, k, target_s, distinct=False):
+def cpu_baseline(n_blocks, c, k, target_s, distinct=False, subarrays=1):
     """The sequential oracle on a bounded sample of the same workload."""
     import numpy as np
 
     import oracle
     import workload
 
-    f = oracle.OracleFilter(n_blocks, c, k, oracle.COST_LA, None, seed=0, distinct=distinct)
+    f = oracle.OracleFilter(n_blocks, c, k, oracle.COST_LA, None, seed=0, distinct=distinct, subarrays=subarrays)
 
     def timed(fn, keys):
         t = time.perf_counter()
@@ -631,12 +635,29 @@ def main():
     workload.device_keys(0, 0, n, out=keys[:n])          # positives: counters [0, n)
     workload.device_keys(0, n, n, out=keys[n:])          # negatives: counters [n, 2n)
     out = torch.empty(n_q // 64, dtype=torch.int64, device=dev)
-    filt = bbfc.Filter(n_blocks, c, k, "la", seed=0, bit_selection=args.bits)
+    T = n_blocks // args.subarray_blocks if args.subarray_blocks else 1
+    if T * max(args.subarray_blocks, 1) != n_blocks and args.subarray_blocks:
+        sys.exit("--subarray-blocks must divide the number of blocks")
+    if args.insert == "bulk" and T == 1:
+        sys.exit("--insert bulk needs --subarray-blocks (at most 1024)")
+    filt = bbfc.Filter(n_blocks, c, k, "la", seed=0, bit_selection=args.bits, subarrays=T)
+    ws = None
+    if args.insert == "bulk":
+        ws = torch.empty(filt.bulk_workspace_bytes(n), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
+
+    def do_insert(stream):
+        if args.insert == "bulk":
+            filt.bulk_insert(keys[:n], workspace=ws, stream=stream)
+        else:
+            filt.insert(keys[:n], stream)
 
     stream = torch.cuda.current_stream()
     tuned = None
-    if not args.no_tune:
+    if not args.no_tune and args.insert == "bulk":
+        do_insert(stream)
+        tuned = {"query": filt.tune(bbfc.OP_QUERY, keys, out=out, reps=2, stream=stream)}
+    elif not args.no_tune:
         # the autotuner times each launch shape on this workload (the insert on
         # an empty filter, restored afterwards), untimed, before the steps
         filt.clear(stream)
@@ -650,7 +671,7 @@ def main():
         evs[0].record(stream)
         filt.clear(stream)
         evs[1].record(stream)
-        filt.insert(keys[:n], stream)
+        do_insert(stream)
         evs[2].record(stream)
         filt.query(keys, out=out, stream=stream)
         evs[3].record(stream)
@@ -678,7 +699,7 @@ def main():
 
     avg_ins = sum(ins_ms) / len(ins_ms)
     avg_qry = sum(qry_ms) / len(qry_ms)
-    if avg_ins >= avg_qry:
+    if avg_ins >= avg_qry and args.insert == "racing":
         dom, dom_ms, dom_bytes = "insert", avg_ins, INSERT_BYTES_PER_KEY * n
         dom_kernel = kernel_name("insert", c, filt.get_shape(bbfc.OP_INSERT))
     else:
@@ -721,7 +742,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(n_blocks, c, k, args.cpu_seconds, distinct=args.bits == "distinct")
+        cpu = cpu_baseline(n_blocks, c, k, args.cpu_seconds, distinct=args.bits == "distinct", subarrays=T)
 
     rec = {
         "metric": "Mkeys/s insert & query, 2-choice 512b blocks; % of random-access HBM peak",
@@ -739,7 +760,9 @@ def main():
         "config": {
             "workload": (f"plain filter: 2^{args.log2_keys} random 64-bit keys inserted into 2^"
                          f"{int(math.log2(n_blocks))} blocks of 512 bits, 2 choices, k=11, lookahead cost "
-                         f"mu=3.5, {args.bits} bit selection; queries: the 2^{args.log2_keys} inserted + "
+                         f"mu=3.5, {args.bits} bit selection"
+                         + (f", {T} sub-arrays of {n_blocks // T} blocks" if T > 1 else "")
+                         + f", {args.insert} insert; queries: the 2^{args.log2_keys} inserted + "
                          f"2^{args.log2_keys} never inserted"),
             "n_keys": n,
             "n_queries": n_q,
@@ -749,6 +772,8 @@ def main():
             "bits_per_key": k,
             "cost": "la",
             "bit_selection": args.bits,
+            "subarrays": T,
+            "insert": args.insert,
         },
         "insert_mkeys_s": round(n / (avg_ins / 1e3) / 1e6, 1),
         "query_mkeys_s": round(n_q / (avg_qry / 1e3) / 1e6, 1),
