@@ -49,6 +49,13 @@ def parse_args():
                          "serve: query requests of mixed sizes against the resident 2^30-key filter; "
                          "kmer: canonical 31-mers of a synthetic genome and of sequenced reads")
     ap.add_argument("--genome-bases", type=float, default=128e6, help="kmer workload: genome length")
+    ap.add_argument("--kmer-bits", type=float, default=12, help="kmer workload: filter bits per distinct 31-mer")
+    ap.add_argument("--kmer-k", type=int, default=8, help="kmer workload: bit hashes per key")
+    ap.add_argument("--repeat-fraction", type=float, default=0.0,
+                    help="kmer workload: genome share covered by planted repeats (log-uniform 300-6000 bp)")
+    ap.add_argument("--repeat-divergence", type=float, default=0.02, help="kmer workload: substitutions in repeats")
+    ap.add_argument("--random-reads", type=int, default=1, help="kmer workload: also query as many random reads")
+    ap.add_argument("--no-unfused", action="store_true", help="kmer workload: skip the unfused comparison")
     ap.add_argument("--reads", type=float, default=1e7, help="kmer workload: reads of 150 bp (and as many random)")
     ap.add_argument("--requests", type=int, default=20000, help="serve workload: requests per offered load")
     ap.add_argument("--log2-keys", type=int, default=30, help="keys to insert (2^n); blocks = keys/32")
@@ -182,6 +189,16 @@ def cpu_baseline(n_blocks, c, k, target_s, distinct=False, subarrays=1):
     t_q = timed(f.count_hits, q_keys)
     r_ins = n_ins / t_ins
     r_q = n_q / t_q
+    # queries are read-only: the same sample split over threads (the oracle's
+    # C calls release the interpreter lock), at most 16 as the host share allows
+    from concurrent.futures import ThreadPoolExecutor
+
+    n_thr = max(1, min(16, os.cpu_count() or 1))
+    parts = np.array_split(q_keys, n_thr)
+    t = time.perf_counter()
+    with ThreadPoolExecutor(n_thr) as ex:
+        hits_mt = sum(ex.map(f.count_hits, parts))
+    t_qmt = time.perf_counter() - t
     # the step's mix: one insert per two queries
     value = 3.0 / (1.0 / r_ins + 2.0 / r_q) / 1e6
     return {
@@ -194,7 +211,32 @@ def cpu_baseline(n_blocks, c, k, target_s, distinct=False, subarrays=1):
                    f"{t_ins + t_q:.1f} s; rates combined with the step's 1 insert : 2 queries mix"),
         "insert_mkeys_s": round(r_ins / 1e6, 3),
         "query_mkeys_s": round(r_q / 1e6, 3),
+        "query_threads": n_thr,
+        "query_all_threads_mkeys_s": round(n_q / t_qmt / 1e6, 3),
     }
+
+
+def host_info() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+# The paper's CPU build rate, for context (not the same workload): distinct
+# 31-grams of the human genome per second of wall time, Section 4.3, Table 1.
+PAPER_CPU_REFERENCE = {
+    "blow2choc_build_human_mkeys_s": 34.7,
+    "derivation": "2.5e9 distinct 31-grams / 72 s build (Table 1), k=14, 2 choices, EXP cost",
+    "hardware": "AMD Ryzen 9 7950X3D, 16 cores, 9 inserter threads, numba",
+    "note": "context only: includes FASTA reading and q-gram extraction; not this metric or workload",
+}
 
 
 def bench_batch(args):
@@ -485,12 +527,21 @@ def bench_kmer(args):
     G = int(args.genome_bases)
     R = int(args.reads)
     genome = workload.device_keys(21, 0, (G + 31) // 32, device=dev)
+    n_segments = 0
+    if args.repeat_fraction > 0:
+        segs = workload.repeat_segments(24, G, args.repeat_fraction)
+        n_segments = len(segs[0])
+        genome = workload.device_plant(genome, G, segs, args.repeat_divergence, seed=25)
     pos = workload.device_reads(genome, G, R, L, 0.01, seed=22)
-    neg = workload.device_keys(23, 0, (R * L + 31) // 32, device=dev)
+    with_neg = bool(args.random_reads)
+    neg = workload.device_keys(23, 0, (R * L + 31) // 32, device=dev) if with_neg else None
     n_g = bbfc.kmer_count(1, G, q)
     n_r = bbfc.kmer_count(R, L, q)
-    M = bbfc.blocks_for(n_g, 12)
-    filt = bbfc.Filter(M, 3, 8, "mix", seed=0)
+    # filter sized for the expected distinct 31-mers: a planted copy repeats
+    # a 31-mer of its source only where none of its 31 bases was substituted
+    n_distinct = int(n_g * (1.0 - args.repeat_fraction * (1.0 - args.repeat_divergence) ** q))
+    M = bbfc.blocks_for(n_distinct, args.kmer_bits)
+    filt = bbfc.Filter(M, 3, args.kmer_k, "mix", seed=0)
     out_p = torch.empty((n_r + 63) // 64, dtype=torch.int64, device=dev)
     out_n = torch.empty_like(out_p)
     stream = torch.cuda.current_stream()
@@ -500,10 +551,13 @@ def bench_kmer(args):
         filt.clear(stream)
         filt.insert_kmers(genome, 1, G, q, stream=stream)
         filt.query_kmers(pos, R, L, q, out=out_p, stream=stream)
-        filt.query_kmers(neg, R, L, q, out=out_n, stream=stream)
+        if with_neg:
+            filt.query_kmers(neg, R, L, q, out=out_n, stream=stream)
 
-    keys_g = torch.empty(n_g, dtype=torch.int64, device=dev)
-    keys_r = torch.empty(n_r, dtype=torch.int64, device=dev)
+    keys_g = keys_r = None
+    if not args.no_unfused:
+        keys_g = torch.empty(n_g, dtype=torch.int64, device=dev)
+        keys_r = torch.empty(n_r, dtype=torch.int64, device=dev)
 
     def unfused():
         filt.clear(stream)
@@ -511,8 +565,9 @@ def bench_kmer(args):
         filt.insert(keys_g, stream)
         bbfc.kmer_keys(pos, R, L, q, out=keys_r, stream=stream)
         filt.query(keys_r, out=out_p, stream=stream)
-        bbfc.kmer_keys(neg, R, L, q, out=keys_r, stream=stream)
-        filt.query(keys_r, out=out_n, stream=stream)
+        if with_neg:
+            bbfc.kmer_keys(neg, R, L, q, out=keys_r, stream=stream)
+            filt.query(keys_r, out=out_n, stream=stream)
 
     def phases():
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
@@ -523,7 +578,8 @@ def bench_kmer(args):
         ev[2].record(stream)
         filt.query_kmers(pos, R, L, q, out=out_p, stream=stream)
         ev[3].record(stream)
-        filt.query_kmers(neg, R, L, q, out=out_n, stream=stream)
+        if with_neg:
+            filt.query_kmers(neg, R, L, q, out=out_n, stream=stream)
         ev[4].record(stream)
         torch.cuda.synchronize()
         return [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
@@ -543,15 +599,16 @@ def bench_kmer(args):
         return best
 
     t_fused = timed(fused)
-    t_unfused = timed(unfused)
+    t_unfused = timed(unfused) if not args.no_unfused else None
     ph = phases()
     hit_pos = float(np.bitwise_count(out_p.cpu().numpy().view(np.uint64)).sum()) / n_r
-    hit_neg = float(np.bitwise_count(out_n.cpu().numpy().view(np.uint64)).sum()) / n_r
+    hit_neg = float(np.bitwise_count(out_n.cpu().numpy().view(np.uint64)).sum()) / n_r if with_neg else None
     # error-free 31-mers of the positive reads always answer true
     ok = hit_pos >= 0.99 ** q - 0.01
-    total = n_g + 2 * n_r
+    n_q = (2 if with_neg else 1) * n_r
+    total = n_g + n_q
     q_ms = ph[2] + ph[3]
-    dom, dom_ms, dom_bytes = ("query", q_ms, (0.25 + 64 * 3 + 1 / 8) * 2 * n_r) if q_ms >= ph[1] else \
+    dom, dom_ms, dom_bytes = ("query", q_ms, (0.25 + 64 * 3 + 1 / 8) * n_q) if q_ms >= ph[1] else \
         ("insert", ph[1], (0.25 + 64 * 3 + 64) * n_g)
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
     rec = {
@@ -567,22 +624,26 @@ def bench_kmer(args):
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": (f"kmer: synthetic uniform genome of {G} bases, its {n_g} canonical 31-mers inserted "
-                                f"into {M} blocks (12 bits/key, 3 choices, k=8, MIX sigma=2.5); queries: the 31-mers "
-                                f"of {R} reads of 150 bp at 1% substitutions and of {R} random reads"),
-                   "genome_bases": G, "reads": R, "genome_kmers": n_g, "read_kmers": 2 * n_r,
-                   "filter_bytes": M * 64},
+        "config": {"workload": (f"kmer: synthetic genome of {G} uniform bases"
+                                + (f" with {args.repeat_fraction:.0%} planted repeats ({n_segments} segments of "
+                                   f"300-6000 bp, {args.repeat_divergence:.0%} divergence)" if n_segments else "")
+                                + f", its {n_g} canonical 31-mers inserted into {M} blocks ({args.kmer_bits:g} bits "
+                                f"per expected distinct 31-mer, 3 choices, k={args.kmer_k}, MIX sigma=2.5); queries: "
+                                f"the 31-mers of {R} reads of 150 bp at 1% substitutions"
+                                + (f" and of {R} random reads" if with_neg else "")),
+                   "genome_bases": G, "reads": R, "genome_kmers": n_g, "read_kmers": n_q,
+                   "expected_distinct_kmers": n_distinct, "filter_bytes": M * 64},
         "fused_ms": round(t_fused, 3),
-        "unfused_ms": round(t_unfused, 3),
-        "fused_speedup": round(t_unfused / t_fused, 3),
+        "unfused_ms": round(t_unfused, 3) if t_unfused else None,
+        "fused_speedup": round(t_unfused / t_fused, 3) if t_unfused else None,
         "phases_ms": {"clear": round(ph[0], 3), "insert_genome": round(ph[1], 3),
                       "query_reads": round(ph[2], 3), "query_random": round(ph[3], 3)},
         "insert_mkeys_s": round(n_g / ph[1] / 1e3, 1),
-        "query_mkeys_s": round(2 * n_r / q_ms / 1e3, 1),
+        "query_mkeys_s": round(n_q / q_ms / 1e3, 1),
         "hit_rate_reads": round(hit_pos, 5),
         "hit_rate_random": hit_neg,
         "error_free_share": round(0.99 ** q, 5),
-        "roofline": {"bound": "hbm", "kernel": f"{dom}_kernel<3,kmer>", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": f"{dom}_kernel<3, ..., KmerKeys>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launch_ms": round(dom_ms, 3)},
         "cpu_baseline": None,
@@ -688,6 +749,7 @@ def main():
     ins_ms = [e[1].elapsed_time(e[2]) for e in per_step]
     qry_ms = [e[2].elapsed_time(e[3]) for e in per_step]
     clr_ms = [e[0].elapsed_time(e[1]) for e in per_step]
+    step_ms = sorted(e[0].elapsed_time(e[3]) for e in per_step)
     ms_per_step = wall * 1e3 / args.steps
     value = (n + n_q) / (ms_per_step / 1e3) / 1e6
 
@@ -780,6 +842,8 @@ def main():
         "insert_ms": round(avg_ins, 3),
         "query_ms": round(avg_qry, 3),
         "clear_ms": round(sum(clr_ms) / len(clr_ms), 3),
+        "step_ms_median": round(step_ms[len(step_ms) // 2], 3),
+        "step_ms_min": round(step_ms[0], 3),
         "zero_false_negatives": fn_free,
         "fpr_negatives": fpr,
         "tuned_shapes": tuned,
@@ -788,6 +852,8 @@ def main():
         "cpu_baseline": cpu,
         "device": props.name,
         "cus": props.multi_processor_count,
+        "host": host_info(),
+        "paper_cpu_reference": PAPER_CPU_REFERENCE,
         "kernel_source_sha": kernel_source_sha(),
     }
     filt.close()

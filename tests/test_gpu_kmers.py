@@ -127,6 +127,15 @@ def test_end_to_end_reads_from_device_genome(dev):
         f.close()
 
 
+@pytest.mark.parametrize("n,frac", [(200_003, 0.1), (65_536, 0.3), (1_000, 0.0)])
+def test_device_planting_matches_numpy(dev, n, frac):
+    bases = workload.random_bases(31, n)
+    segs = workload.repeat_segments(32, n, frac)
+    want = workload.pack_2bit(workload.plant_numpy(bases, segs, 0.02, 33))
+    got = from_dev(workload.device_plant(to_dev(workload.pack_2bit(bases), dev), n, segs, 0.02, 33))
+    assert np.array_equal(got, want)
+
+
 def test_kmer_argument_errors(dev):
     seq = torch.zeros(4, dtype=torch.int64, device=dev)
     with pytest.raises(bbfc.BBFCError):

@@ -182,6 +182,53 @@ def random_bases(seed: int, n: int) -> np.ndarray:
     return unpack_2bit(genome_packed(seed, n), n)
 
 
+_PLANT_ERR_SALT = 0x6B6B6B6B6B6B6B6B
+_PLANT_SUB_SALT = 0x1E1E1E1E1E1E1E1E
+
+
+def repeat_segments(seed: int, n_bases: int, fraction: float, lo: int = 300, hi: int = 6000):
+    """Planted repeat segments: lengths log-uniform in [lo, hi], drawn until
+    they cover `fraction` of the genome, laid out in draw order with random
+    gaps (so they never overlap), each copying from a uniform random source
+    position. Returns (dst, length, src) uint64 arrays sorted by dst."""
+    rng = SplitMix64(seed ^ 0x7E9E47D3)
+    target = int(fraction * n_bases)
+    lens = []
+    total = 0
+    while total < target:
+        u = (rng.next() >> 11) / float(1 << 53)
+        L = int(round(lo * (hi / lo) ** u))
+        L = min(L, n_bases - total)
+        if L <= 0:
+            break
+        lens.append(L)
+        total += L
+    n = len(lens)
+    free = n_bases - total
+    cuts = np.sort(np.array([rng.next() % (free + 1) for _ in range(n)], dtype=np.uint64))
+    lens_a = np.array(lens, dtype=np.uint64)
+    before = np.concatenate([[0], np.cumsum(lens_a)[:-1]]).astype(np.uint64) if n else np.zeros(0, np.uint64)
+    dst = cuts + before
+    src = np.array([rng.next() % (n_bases - L + 1) for L in lens], dtype=np.uint64)
+    return dst, lens_a, src
+
+
+def plant_numpy(bases, segments, div: float, seed: int) -> np.ndarray:
+    """Host restatement of the device planting (one base per byte)."""
+    b = np.ascontiguousarray(bases, dtype=np.uint8)
+    out = b.copy()
+    thr = min(int(div * 2.0 ** 64), MASK64)
+    for d, L, s in zip(*segments):
+        d, L, s = int(d), int(L), int(s)
+        seg = b[s:s + L].astype(np.uint64)
+        err = splitmix64_keys(seed ^ _PLANT_ERR_SALT, d, L)
+        sub = splitmix64_keys(seed ^ _PLANT_SUB_SALT, d, L)
+        flip = err < np.uint64(thr)
+        seg = np.where(flip, (seg + np.uint64(1) + sub % np.uint64(3)) & np.uint64(3), seg)
+        out[d:d + L] = seg.astype(np.uint8)
+    return out
+
+
 # ----------------------------------------------------- device-side generator
 
 import ctypes as _ctypes
@@ -214,6 +261,9 @@ def _device_lib():
         L.wl_splitmix64_keys.restype = _ctypes.c_int
         L.wl_reads.argtypes = [_ctypes.c_void_p] + [_ctypes.c_uint64] * 5 + [_ctypes.c_void_p] * 2
         L.wl_reads.restype = _ctypes.c_int
+        L.wl_plant.argtypes = [_ctypes.c_void_p] * 2 + [_ctypes.c_uint64] + [_ctypes.c_void_p] * 3 + \
+            [_ctypes.c_uint64] * 3 + [_ctypes.c_void_p]
+        L.wl_plant.restype = _ctypes.c_int
         _dev = L
     return _dev
 
@@ -249,4 +299,24 @@ def device_reads(genome, n_genome: int, n_reads: int, read_len: int, err: float,
                                 out.data_ptr(), _ctypes.c_void_p(stream.cuda_stream))
     if rc != 0:
         raise RuntimeError(f"device read generation failed ({rc})")
+    return out
+
+
+def device_plant(genome, n_bases: int, segments, div: float, seed: int, stream=None):
+    """A copy of a packed genome on the GPU with the planted repeat segments
+    (see repeat_segments / plant_numpy)."""
+    import torch
+
+    dst, lens, src = (torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to(genome.device)
+                      for a in segments)
+    out = torch.empty_like(genome)
+    if stream is None:
+        stream = torch.cuda.current_stream(genome.device)
+    thr = min(int(div * 2.0 ** 64), MASK64)
+    rc = _device_lib().wl_plant(genome.data_ptr(), out.data_ptr(), n_bases, dst.data_ptr(), lens.data_ptr(),
+                                src.data_ptr(), len(segments[0]), thr, seed & MASK64,
+                                _ctypes.c_void_p(stream.cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"device repeat planting failed ({rc})")
+    stream.synchronize()  # the segment tables are freed on return
     return out
