@@ -94,6 +94,11 @@ def run_probes(stream=None):
     for name, fn, acc in (
         ("rand64_read", lambda a: bbfc.probe_gather(buf, a, 7, sink, 64, stream), 1 << 28),
         ("rand64_atomic_or", lambda a: bbfc.probe_atomic64(buf, a, 9, stream), 1 << 27),
+        # the insert's pattern over 2 GiB (the bench filter's size)
+        ("insert_pattern_2reads", lambda a: bbfc.probe_insert_pattern(buf[: 1 << 28], a, False, 11, sink, stream),
+         1 << 29),
+        ("insert_pattern_2reads_atomic",
+         lambda a: bbfc.probe_insert_pattern(buf[: 1 << 28], a, True, 13, sink, stream), 1 << 29),
     ):
         fn(acc >> 4)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -102,8 +107,11 @@ def run_probes(stream=None):
         e1.record(stream)
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        out[name + "_GBs"] = round(acc * 64 / (ms / 1e3) / 1e9, 1)
-        out[name + "_Glines_s"] = round(acc / (ms / 1e3) / 1e9, 2)
+        if name.startswith("insert_pattern"):
+            out[name + "_Gkeys_s"] = round(acc / (ms / 1e3) / 1e9, 2)
+        else:
+            out[name + "_GBs"] = round(acc * 64 / (ms / 1e3) / 1e9, 1)
+            out[name + "_Glines_s"] = round(acc / (ms / 1e3) / 1e9, 2)
     del buf
     return out
 
@@ -794,7 +802,11 @@ def main():
         i_overlap = min(r_read / c, r_atom)
         q_rate = n_q / (avg_qry / 1e3) / 1e6
         i_rate = n / (avg_ins / 1e3) / 1e6
+        i_pattern = probe["insert_pattern_2reads_atomic_Gkeys_s"] * 1e3
         probe.update({
+            "query_2read_pattern_mkeys_s": round(probe["insert_pattern_2reads_Gkeys_s"] * 1e3, 1),
+            "insert_pattern_ceiling_mkeys_s": round(i_pattern, 1),
+            "insert_frac_of_pattern_ceiling": round(i_rate / i_pattern, 4),
             "query_ceiling_mkeys_s": round(q_ceil, 1),
             "query_frac_of_ceiling": round(q_rate / q_ceil, 4),
             "insert_ceiling_serial_mkeys_s": round(i_serial, 1),

@@ -508,6 +508,16 @@ bbfc_status bbfc_probe_gather(const uint64_t *d_buf, uint64_t n_lines64, uint32_
 bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
                                 hipStream_t stream);
 
+/* The insert's access pattern without its arithmetic: n_keys keys, each
+ * reading two random 64-byte lines of d_buf (n_lines lines, a power of two;
+ * eight lanes per line); with atomic != 0 each then ORs one 64-bit word per
+ * lane into one of its two lines, chosen from the data read (so the write
+ * depends on both reads, as in the insert). Writes at most one word per
+ * workgroup into d_sink (>= 65536 words). Measures what the device sustains
+ * for the insert's pattern (compare with bbfc_insert). */
+bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t atomic,
+                                      uint64_t seed, uint64_t *d_sink, hipStream_t stream);
+
 /* Plain copy of n_words words, to calibrate the traffic counters. With
  * request_bytes == 128 every lane moves 16 contiguous bytes (128-byte
  * requests, a streaming copy; an odd last word is not copied). With

@@ -131,6 +131,7 @@ def lib() -> ctypes.CDLL:
         "bbfc_probe_gather": (_st, [_vp, _u64, _u32, _u64, _u64, _vp, _vp]),
         "bbfc_probe_atomic64": (_st, [_vp, _u64, _u64, _u64, _vp]),
         "bbfc_probe_copy": (_st, [_vp, _vp, _u64, _u32, _vp]),
+        "bbfc_probe_insert_pattern": (_st, [_vp, _u64, _u64, ctypes.c_int32, _u64, _vp, _vp]),
         "bbfc_batch_create": (_st, [_vp, _vp, _u32, _vp]),
         "bbfc_batch_destroy": (_st, [_vp]),
         "bbfc_batch_layout": (_st, [_vp, _vp, _vp]),
@@ -675,6 +676,14 @@ def probe_atomic64(buf, n_access: int, seed: int, stream=None) -> None:
     if n_lines & (n_lines - 1):
         raise ValueError("probe buffer must hold a power-of-two number of 64-byte lines")
     _check(lib().bbfc_probe_atomic64(buf.data_ptr(), n_lines, n_access, seed, _stream_handle(stream)))
+
+
+def probe_insert_pattern(buf, n_keys: int, atomic: bool, seed: int, sink, stream=None) -> None:
+    """Two random line reads per key, and with `atomic` a dependent atomic
+    OR into one of the lines (see bbfc.h)."""
+    n_lines = buf.numel() // 8
+    _check(lib().bbfc_probe_insert_pattern(buf.data_ptr(), n_lines, n_keys, int(atomic), seed, sink.data_ptr(),
+                                           _stream_handle(stream)))
 
 
 def probe_copy(src, dst, request_bytes: int = 128, stream=None) -> None:

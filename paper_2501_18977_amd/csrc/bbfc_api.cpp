@@ -810,6 +810,15 @@ bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_ac
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching atomic probe");
 }
 
+bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t atomic,
+                                      uint64_t seed, uint64_t *d_sink, hipStream_t stream)
+{
+    if (d_buf == nullptr || d_sink == nullptr || !is_pow2(n_lines))
+        return fail(BBFC_EINVAL, "probe needs buffers and a power-of-two line count");
+    hipError_t e = bbfc::launch_probe_insert_pattern(d_buf, n_lines, n_keys, atomic, seed, d_sink, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching insert-pattern probe");
+}
+
 bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, uint32_t request_bytes,
                             hipStream_t stream)
 {

@@ -86,6 +86,54 @@ __global__ __launch_bounds__(kProbeWG) void probe_copy_kernel(const uint4 *__res
         dst[i] = src[i];
 }
 
+// The insert's access pattern without its arithmetic: per key two random
+// 64-byte lines are read (eight lanes per line, eight keys per lane group in
+// flight) and, with ATOMIC, one 64-bit atomic OR per lane then goes to the
+// first or the second line depending on the data read, so the write waits
+// for both reads as the insert's does.
+template <bool ATOMIC>
+__global__ __launch_bounds__(kProbeWG) void probe_insert_pattern_kernel(uint64_t *__restrict__ buf, uint64_t line_mask,
+                                                                        uint64_t n_keys, uint64_t seed,
+                                                                        uint64_t *__restrict__ sink)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = lane >> 3;
+    const uint32_t w = lane & 7;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    uint64_t acc = 0;
+    for (uint64_t base = wave * 64; base < n_keys; base += n_waves * 64) {
+        uint64_t v0[8], v1[8], l0[8], l1[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint64_t key = base + g * 8 + r;
+            const uint64_t h = probe_line(seed, key);
+            l0[r] = h & line_mask;
+            l1[r] = ((h >> 32) ^ (h << 7)) & line_mask;
+            v0[r] = v1[r] = 0;
+            if (key < n_keys) {
+                v0[r] = buf[l0[r] * 8 + w];
+                v1[r] = buf[l1[r] * 8 + w];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint64_t key = base + g * 8 + r;
+            if (key >= n_keys)
+                continue;
+            if constexpr (ATOMIC) {
+                const uint64_t t = v0[r] | v1[r];
+                __hip_atomic_fetch_or(&buf[((t & 1) ? l1[r] : l0[r]) * 8 + w], (1ull << (key & 63)) | (t & 2),
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                acc += v0[r] + v1[r];
+            }
+        }
+    }
+    if (acc == 0x9E3779B97F4A7C15ull)
+        sink[blockIdx.x & 0xFFFF] = acc;
+}
+
 // 64-byte requests: a wavefront takes 8 consecutive 128-byte lines per
 // unit; group g (lanes 8g..8g+7) moves the low 64-byte half of line g, then,
 // in a second instruction, its high half.
@@ -143,6 +191,24 @@ hipError_t launch_probe_atomic64(uint64_t *buf, uint64_t n_lines, uint64_t n_acc
     if (need < grid)
         grid = (uint32_t)(need ? need : 1);
     hipLaunchKernelGGL(probe_atomic64_kernel, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_access, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_insert_pattern(uint64_t *buf, uint64_t n_lines, uint64_t n_keys, int atomic, uint64_t seed,
+                                       uint64_t *sink, hipStream_t s)
+{
+    const void *k = atomic ? (const void *)probe_insert_pattern_kernel<true>
+                           : (const void *)probe_insert_pattern_kernel<false>;
+    uint32_t grid = probe_grid(k);
+    const uint64_t need = (n_keys + 255) / 256;
+    if (need < grid)
+        grid = (uint32_t)(need ? need : 1);
+    if (atomic)
+        hipLaunchKernelGGL(probe_insert_pattern_kernel<true>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1,
+                           n_keys, seed, sink);
+    else
+        hipLaunchKernelGGL(probe_insert_pattern_kernel<false>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1,
+                           n_keys, seed, sink);
     return hipGetLastError();
 }
 

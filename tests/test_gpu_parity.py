@@ -317,6 +317,8 @@ def test_probes_run(dev):
     bbfc.probe_gather(buf, 1 << 18, 1, sink)
     bbfc.probe_gather(buf, 1 << 18, 1, sink, access_bytes=128)
     bbfc.probe_atomic64(buf, 1 << 18, 2)
+    bbfc.probe_insert_pattern(buf, 1 << 18, False, 3, sink)
+    bbfc.probe_insert_pattern(buf, 1 << 18, True, 4, sink)
     dst = torch.empty_like(buf)
     bbfc.probe_copy(buf, dst)
     torch.cuda.synchronize()
