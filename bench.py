@@ -146,18 +146,19 @@ def kernel_source_sha() -> str:
 
 
 def measured_traffic(op: str, kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if it is absent, or was taken on a different kernel source or
-    launch shape."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{op}.json")
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
+    calibration), or None if the summary is absent, was taken on a different
+    kernel source, or has no such launch shape."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha") != kernel_source_sha() or rec.get("kernel") != kernel:
+    if rec.get("source_sha") != kernel_source_sha():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", {}).get(kernel)
 
 
 def kernel_name(op: str, c: int, shape: dict, early: bool = True) -> str:
@@ -776,17 +777,39 @@ def main():
         dom, dom_ms, dom_bytes = "query", avg_qry, QUERY_BYTES_PER_KEY * n_q
         dom_kernel = kernel_name("query", c, filt.get_shape(bbfc.OP_QUERY))
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
-    roofline = {
+
+    def with_traffic(rec, traffic, ms):
+        # HBM bytes the counters saw per launch (each random 64-byte block
+        # read is served by one 128-byte DRAM request), as a rate and a
+        # fraction of the peak
+        rec["traffic"] = traffic
+        if traffic:
+            rec["traffic_GBs"] = round(traffic / (ms / 1e3) / 1e9, 1)
+            rec["traffic_frac"] = round(traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        return rec
+
+    roofline = with_traffic({
         "bound": "hbm",
         "kernel": dom_kernel,
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(dom, dom_kernel),
         "bytes_per_launch_algorithmic": int(dom_bytes),
         "launch_ms": round(dom_ms, 3),
-    }
+    }, measured_traffic(dom, dom_kernel), dom_ms)
+    q_kernel = kernel_name("query", c, filt.get_shape(bbfc.OP_QUERY))
+    q_bytes = QUERY_BYTES_PER_KEY * n_q
+    roofline_query = with_traffic({
+        "bound": "hbm",
+        "kernel": q_kernel,
+        "achieved": round(q_bytes / (avg_qry / 1e3) / 1e9, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(q_bytes / (avg_qry / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "bytes_per_launch_algorithmic": int(q_bytes),
+        "launch_ms": round(avg_qry, 3),
+    }, measured_traffic("query", q_kernel), avg_qry)
 
     probe = None
     if not args.no_probe:
@@ -860,6 +883,7 @@ def main():
         "fpr_negatives": fpr,
         "tuned_shapes": tuned,
         "roofline": roofline,
+        "roofline_query": roofline_query,
         "probe": probe,
         "cpu_baseline": cpu,
         "device": props.name,

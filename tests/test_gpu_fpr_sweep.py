@@ -1,0 +1,84 @@
+"""False-positive rates of the racing GPU insert across the parameter space
+(GPU only).
+
+For k in {7, 10, 14, 17}, two and three choices and every cost, a filter of
+the standard Bloom size (relative size 1.0, M = n k / (512 ln 2), the
+setting of Section 4.1 and App. C) built by the racing insert has the
+false-positive rate of the oracle's one-key-at-a-time build: the
+conditional estimator (the exact hit probability of each negative given
+the blocks' contents) within 2% over 2^20 negatives. Distinct bits and
+sub-arrays are included.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2501_18977_amd as bbfc
+import workload
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def from_dev(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+SWEEP = [(k, c, cost) for k in (7, 10, 14, 17) for c, cost in ((2, "exp"), (3, "exp"), (2, "la"), (2, "mix"))]
+
+
+@pytest.mark.parametrize("k,c,cost", SWEEP)
+def test_racing_fpr_matches_sequential(dev, k, c, cost):
+    n = 1 << 21
+    M = math.ceil(n * k / math.log(2) / 512)
+    seed = 100 * k + 10 * c + len(cost)
+    f = bbfc.Filter(M, c, k, cost, seed=seed)
+    try:
+        ref = oracle.OracleFilter(M, c, k, oracle.COST_NAMES[cost], None, list(f.params.block_mult),
+                                  list(f.params.bit_mult))
+        keys_d = workload.device_keys(seed, 0, n, device=dev)
+        f.insert(keys_d)
+        ref.insert(from_dev(keys_d))
+        words = f.download()
+        neg = workload.negative_keys(seed, n, 1 << 20)
+        got = ref.conditional_fpr(neg, words=words)
+        want = ref.conditional_fpr(neg)
+        print(f"k={k} c={c} {cost}: log2 FPR gpu {math.log2(got):.3f} oracle {math.log2(want):.3f}", flush=True)
+        assert got == pytest.approx(want, rel=0.02)
+        assert bbfc.unpack_bits(from_dev(f.query(keys_d)), n).all()
+    finally:
+        f.close()
+
+
+@pytest.mark.parametrize("distinct,sub", [(True, 0), (False, 256), (True, 512)])
+def test_racing_fpr_distinct_and_subarrays(dev, distinct, sub):
+    n, k, c = 1 << 21, 14, 3
+    M = math.ceil(n * k / math.log(2) / 512 / 512) * 512
+    T = M // sub if sub else 1
+    f = bbfc.Filter(M, c, k, "exp", seed=5, subarrays=T, bit_selection="distinct" if distinct else "random")
+    try:
+        p = f.params
+        ref = oracle.OracleFilter(M, c, k, oracle.COST_EXP, None, list(p.block_mult), list(p.bit_mult),
+                                  distinct=distinct, subarrays=T, sub_mult=p.sub_mult if T > 1 else None)
+        keys_d = workload.device_keys(5, 0, n, device=dev)
+        f.insert(keys_d)
+        ref.insert(from_dev(keys_d))
+        neg = workload.negative_keys(5, n, 1 << 20)
+        got = ref.conditional_fpr(neg, words=f.download())
+        want = ref.conditional_fpr(neg)
+        assert got == pytest.approx(want, rel=0.02)
+    finally:
+        f.close()
