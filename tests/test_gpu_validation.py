@@ -76,8 +76,13 @@ def test_load_histogram_matches_oracle(dev, M):
 @pytest.mark.parametrize("cost", ["mix", "la", "exp"])
 def test_load_histograms_follow_the_paper(dev, k, cost):
     """Default parameters are the figure's: sigma 2.5 (k = 7) / 50 (k = 14),
-    mu 3.5, beta the golden ratio; filter at the standard Bloom size."""
-    n = 1 << 18
+    mu 3.5, beta the golden ratio; filter at the standard Bloom size.
+
+    The racing build is one more random build, so the bounds are set by
+    sampling noise: two sequential builds with independent multipliers
+    differ in total variation by about 0.05 at 2^18 keys (k = 7, EXP) and
+    0.026 at 2^20, hence 2^20 keys and a bound of 0.06."""
+    n = 1 << 20
     M = math.ceil(n * k / math.log(2) / 512)
     keys = workload.positive_keys(3, n)
     kd = to_dev(keys, dev)
