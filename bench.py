@@ -77,9 +77,12 @@ def parse_args():
     return ap.parse_args()
 
 
-def run_probes(stream=None):
+def run_probes(stream=None, n_blocks=1 << 25, n_keys=1 << 30, k=11):
     """Random 64-byte line reads and random 64-bit atomic ORs (eight lanes per
-    line) over a 4 GiB buffer, beyond the Infinity Cache."""
+    line) over a 4 GiB buffer, beyond the Infinity Cache; then the insert's
+    pattern (two reads, then at most one line rewritten with a k-bit mask) for
+    n_keys keys on a zeroed buffer of the filter's size (n_blocks lines,
+    rounded down to a power of two, at most 4 GiB)."""
     import torch
 
     import paper_2501_18977_amd as bbfc
@@ -91,16 +94,18 @@ def run_probes(stream=None):
     lines = 1 << 26
     buf = torch.zeros(lines * 8, dtype=torch.int64, device=dev)
     sink = torch.zeros(1 << 16, dtype=torch.int64, device=dev)
+    pat_lines = min(lines, 1 << (max(int(n_blocks), 1).bit_length() - 1))
+    pat = buf[: pat_lines * 8]
     for name, fn, acc in (
         ("rand64_read", lambda a: bbfc.probe_gather(buf, a, 7, sink, 64, stream), 1 << 28),
         ("rand64_atomic_or", lambda a: bbfc.probe_atomic64(buf, a, 9, stream), 1 << 27),
-        # the insert's pattern over 2 GiB (the bench filter's size)
-        ("insert_pattern_2reads", lambda a: bbfc.probe_insert_pattern(buf[: 1 << 28], a, False, 11, sink, stream),
-         1 << 29),
-        ("insert_pattern_2reads_atomic",
-         lambda a: bbfc.probe_insert_pattern(buf[: 1 << 28], a, True, 13, sink, stream), 1 << 29),
+        ("insert_pattern_2reads", lambda a: bbfc.probe_insert_pattern(pat, a, 0, 11, sink, stream), n_keys),
+        ("insert_pattern_2reads_atomic", lambda a: bbfc.probe_insert_pattern(pat, a, k, 13, sink, stream), n_keys),
     ):
         fn(acc >> 4)
+        if name.startswith("insert_pattern"):
+            with torch.cuda.stream(stream):
+                pat.zero_()  # the insert starts from an empty filter
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         fn(acc)
@@ -112,7 +117,10 @@ def run_probes(stream=None):
         else:
             out[name + "_GBs"] = round(acc * 64 / (ms / 1e3) / 1e9, 1)
             out[name + "_Glines_s"] = round(acc / (ms / 1e3) / 1e9, 2)
-    del buf
+    out["insert_pattern_lines"] = pat_lines
+    out["insert_pattern_keys"] = int(n_keys)
+    out["insert_pattern_mask_bits"] = int(k)
+    del buf, pat
     return out
 
 
@@ -813,7 +821,7 @@ def main():
 
     probe = None
     if not args.no_probe:
-        probe = run_probes(stream)
+        probe = run_probes(stream, n_blocks, n, k)
         # Ceilings from the probe rates under the paper's access counts
         # (c = 2 random block reads per query; c reads plus one rewritten
         # block, an atomic line, per insert): the query at R_read / c; the

@@ -437,8 +437,8 @@ typedef struct bbfc_server *bbfc_server_handle;
  *     64..2^30; pinned host and device memory of 8 bytes per key plus
  *     answers is allocated per slot); max_pending_keys: admission limit on
  *     keys submitted but not yet staged (a request is still admitted when
- *     nothing is pending, whatever its size); poll_us: scheduler poll period
- *     while batches are in flight. Defaults (config == NULL): 4 slots,
+ *     nothing is pending, whatever its size); poll_us: period at which a slot's
+ *     worker polls its batch for completion (0: yield between polls). Defaults (config == NULL): 4 slots,
  *     2^20 keys per batch, 2^28 pending keys, 20 us. */
 typedef struct {
     uint32_t n_slots;
@@ -447,9 +447,9 @@ typedef struct {
     uint32_t poll_us;
 } bbfc_server_config;
 
-/* Starts a scheduler thread serving queries on `filter`. Requests that
- * arrive while others are in flight are admitted into the next batch as
- * slots and memory free up: the oldest pending work fills a free slot's
+/* Starts one worker thread per slot serving queries on `filter`. Requests
+ * that arrive while others are in flight are admitted into the next batch
+ * as slots and memory free up: the oldest pending work fills a free slot's
  * batch (each request's part starts on a 64-key boundary; a request larger
  * than the room left continues in the next batch), and every batch is one
  * key upload, one query launch (the filter's query shape) and one answer
@@ -459,7 +459,7 @@ typedef struct {
  * the in-flight inserts). Errors: EINVAL, EHIP. */
 bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *config, bbfc_server_handle *out);
 
-/* Waits for the admitted requests, stops the thread and frees the server. */
+/* Waits for the admitted requests, stops the threads and frees the server. */
 bbfc_status bbfc_server_destroy(bbfc_server_handle s);
 
 /* Submits a query of h_keys[0..n) (host memory). On completion
@@ -508,14 +508,18 @@ bbfc_status bbfc_probe_gather(const uint64_t *d_buf, uint64_t n_lines64, uint32_
 bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_access, uint64_t seed,
                                 hipStream_t stream);
 
-/* The insert's access pattern without its arithmetic: n_keys keys, each
- * reading two random 64-byte lines of d_buf (n_lines lines, a power of two;
- * eight lanes per line); with atomic != 0 each then ORs one 64-bit word per
- * lane into one of its two lines, chosen from the data read (so the write
- * depends on both reads, as in the insert). Writes at most one word per
+/* The insert's memory pattern with a stand-in for its arithmetic: n_keys
+ * keys, each reading two random 64-byte lines of d_buf (n_lines lines, a
+ * power of two; eight lanes per line). mask_bits == 0: reads only. mask_bits
+ * in [1, 32]: each key also draws a mask of that many random bit positions,
+ * picks the line that gains fewer new bits and ORs the mask into it with
+ * 64-bit atomics on the words that gain a bit (at most one line rewritten per
+ * key, after both reads, as in bbfc_insert). Writes at most one word per
  * workgroup into d_sink (>= 65536 words). Measures what the device sustains
- * for the insert's pattern (compare with bbfc_insert). */
-bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t atomic,
+ * for the insert's pattern (compare with bbfc_insert on a buffer of the
+ * filter's size, starting from zero). BBFC_EINVAL for null buffers, a line
+ * count that is not a power of two, or mask_bits outside [0, 32]. */
+bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t mask_bits,
                                       uint64_t seed, uint64_t *d_sink, hipStream_t stream);
 
 /* Plain copy of n_words words, to calibrate the traffic counters. With

@@ -678,11 +678,11 @@ def probe_atomic64(buf, n_access: int, seed: int, stream=None) -> None:
     _check(lib().bbfc_probe_atomic64(buf.data_ptr(), n_lines, n_access, seed, _stream_handle(stream)))
 
 
-def probe_insert_pattern(buf, n_keys: int, atomic: bool, seed: int, sink, stream=None) -> None:
-    """Two random line reads per key, and with `atomic` a dependent atomic
-    OR into one of the lines (see bbfc.h)."""
+def probe_insert_pattern(buf, n_keys: int, mask_bits: int, seed: int, sink, stream=None) -> None:
+    """Two random line reads per key, and with ``mask_bits`` > 0 a dependent
+    atomic OR of a ``mask_bits``-bit mask into one of the lines (see bbfc.h)."""
     n_lines = buf.numel() // 8
-    _check(lib().bbfc_probe_insert_pattern(buf.data_ptr(), n_lines, n_keys, int(atomic), seed, sink.data_ptr(),
+    _check(lib().bbfc_probe_insert_pattern(buf.data_ptr(), n_lines, n_keys, int(mask_bits), seed, sink.data_ptr(),
                                            _stream_handle(stream)))
 
 

@@ -810,12 +810,14 @@ bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_ac
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching atomic probe");
 }
 
-bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t atomic,
+bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t mask_bits,
                                       uint64_t seed, uint64_t *d_sink, hipStream_t stream)
 {
     if (d_buf == nullptr || d_sink == nullptr || !is_pow2(n_lines))
         return fail(BBFC_EINVAL, "probe needs buffers and a power-of-two line count");
-    hipError_t e = bbfc::launch_probe_insert_pattern(d_buf, n_lines, n_keys, atomic, seed, d_sink, stream);
+    if (mask_bits < 0 || mask_bits > 32)
+        return fail(BBFC_EINVAL, "mask_bits must be in [0, 32], got %d", mask_bits);
+    hipError_t e = bbfc::launch_probe_insert_pattern(d_buf, n_lines, n_keys, mask_bits, seed, d_sink, stream);
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching insert-pattern probe");
 }
 

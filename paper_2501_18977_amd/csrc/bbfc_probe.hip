@@ -86,14 +86,31 @@ __global__ __launch_bounds__(kProbeWG) void probe_copy_kernel(const uint4 *__res
         dst[i] = src[i];
 }
 
-// The insert's access pattern without its arithmetic: per key two random
-// 64-byte lines are read (eight lanes per line, eight keys per lane group in
-// flight) and, with ATOMIC, one 64-bit atomic OR per lane then goes to the
-// first or the second line depending on the data read, so the write waits
-// for both reads as the insert's does.
+// The insert's memory pattern with a stand-in for its arithmetic: per key
+// two random 64-byte lines are read (eight lanes per line, eight keys per
+// lane group in flight). With MASK_BITS > 0 the key then has a mask of that
+// many random bit positions (positions may repeat, as in the filter) and the
+// group picks the line that gains fewer new bits, one choice for all eight
+// lanes, and ORs the mask into it with 64-bit atomics, only on the words that
+// gain a bit. So each key rewrites at most one line, as the insert does, and
+// that write waits for both reads.
+__device__ inline uint64_t probe_mask_word(uint64_t seed, uint64_t key, uint32_t w, int mask_bits)
+{
+    uint64_t m = 0;
+    uint64_t h = 0;
+    for (int i = 0; i < mask_bits; ++i) {
+        if (i % 7 == 0)
+            h = probe_line(seed ^ 0x5851F42D4C957F2Dull, key * 5 + (uint64_t)(i / 7));
+        const uint32_t pos = (uint32_t)(h & 511);
+        h >>= 9;
+        m |= (pos >> 6) == w ? 1ull << (pos & 63) : 0ull;
+    }
+    return m;
+}
+
 template <bool ATOMIC>
 __global__ __launch_bounds__(kProbeWG) void probe_insert_pattern_kernel(uint64_t *__restrict__ buf, uint64_t line_mask,
-                                                                        uint64_t n_keys, uint64_t seed,
+                                                                        uint64_t n_keys, int mask_bits, uint64_t seed,
                                                                         uint64_t *__restrict__ sink)
 {
     const uint32_t lane = threadIdx.x & 63;
@@ -119,13 +136,20 @@ __global__ __launch_bounds__(kProbeWG) void probe_insert_pattern_kernel(uint64_t
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const uint64_t key = base + g * 8 + r;
-            if (key >= n_keys)
-                continue;
             if constexpr (ATOMIC) {
-                const uint64_t t = v0[r] | v1[r];
-                __hip_atomic_fetch_or(&buf[((t & 1) ? l1[r] : l0[r]) * 8 + w], (1ull << (key & 63)) | (t & 2),
-                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
+                // every lane takes part in the shuffles; keys past the end
+                // have an empty mask and write nothing
+                const uint64_t m = key < n_keys ? probe_mask_word(seed, key, w, mask_bits) : 0;
+                int d = __popcll(m & ~v0[r]) - __popcll(m & ~v1[r]);
+                d += __shfl_xor(d, 1);
+                d += __shfl_xor(d, 2);
+                d += __shfl_xor(d, 4);
+                const bool second = d > 0;
+                const uint64_t old = second ? v1[r] : v0[r];
+                if (m & ~old)
+                    __hip_atomic_fetch_or(&buf[(second ? l1[r] : l0[r]) * 8 + w], m, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+            } else if (key < n_keys) {
                 acc += v0[r] + v1[r];
             }
         }
@@ -194,9 +218,10 @@ hipError_t launch_probe_atomic64(uint64_t *buf, uint64_t n_lines, uint64_t n_acc
     return hipGetLastError();
 }
 
-hipError_t launch_probe_insert_pattern(uint64_t *buf, uint64_t n_lines, uint64_t n_keys, int atomic, uint64_t seed,
+hipError_t launch_probe_insert_pattern(uint64_t *buf, uint64_t n_lines, uint64_t n_keys, int mask_bits, uint64_t seed,
                                        uint64_t *sink, hipStream_t s)
 {
+    const bool atomic = mask_bits > 0;
     const void *k = atomic ? (const void *)probe_insert_pattern_kernel<true>
                            : (const void *)probe_insert_pattern_kernel<false>;
     uint32_t grid = probe_grid(k);
@@ -205,10 +230,10 @@ hipError_t launch_probe_insert_pattern(uint64_t *buf, uint64_t n_lines, uint64_t
         grid = (uint32_t)(need ? need : 1);
     if (atomic)
         hipLaunchKernelGGL(probe_insert_pattern_kernel<true>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1,
-                           n_keys, seed, sink);
+                           n_keys, mask_bits, seed, sink);
     else
         hipLaunchKernelGGL(probe_insert_pattern_kernel<false>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1,
-                           n_keys, seed, sink);
+                           n_keys, 0, seed, sink);
     return hipGetLastError();
 }
 

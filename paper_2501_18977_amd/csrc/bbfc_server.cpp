@@ -1,18 +1,20 @@
 // Query serving with continuous batching over one resident filter.
 //
-// Clients submit requests (host keys, host answer buffer). A scheduler
-// thread keeps a FIFO of admitted requests and a fixed set of slots, each
-// with its own stream and pinned and device staging of max_batch_keys keys.
-// Whenever a slot is free it packs the oldest pending work into one fused
-// batch (each request's piece starts on a 64-key boundary, so its answer
-// words can be copied out whole; a request larger than what is left of the
-// slot continues in the next batch), and enqueues key upload, one query
-// launch and answer download on the slot's stream. Batches of different
-// slots overlap on the device. Completed batches (polled with events) hand
-// their answer words back to their requests; a request is done when all its
-// pieces are. Admission is by memory: at most max_pending_keys keys are
-// queued (submit answers BBFC_EBUSY beyond that), and a batch never holds
-// more than a slot's staging.
+// Clients submit requests (host keys, host answer buffer) into one FIFO of
+// admitted requests. The server has a fixed set of slots, each with its own
+// stream, pinned and device staging of max_batch_keys keys, and its own
+// worker thread. A worker whose slot is free takes the oldest pending work
+// into one fused batch (each request's piece starts on a 64-key boundary, so
+// its answer words can be copied out whole; a request larger than what is
+// left of the slot continues in the next batch), copies the keys into its
+// pinned staging, enqueues key upload, one query launch and answer download
+// on the slot's stream, waits for the batch by polling its event, and hands
+// the answer words back to their requests; a request is done when all its
+// pieces are. Slots work in parallel, so host staging copies run on several
+// cores at once and batches of different slots overlap on the device.
+// Admission is by memory: at most max_pending_keys keys are queued (submit
+// answers BBFC_EBUSY beyond that), and a batch never holds more than a
+// slot's staging.
 #include <stdint.h>
 #include <string.h>
 
@@ -63,7 +65,7 @@ struct Slot {
     uint64_t *d_out = nullptr;
     hipEvent_t done = nullptr;
     std::vector<Piece> pieces;
-    bool busy = false;
+    std::thread worker;
 };
 
 } // namespace
@@ -73,14 +75,13 @@ struct bbfc_server {
     bbfc_server_config cfg{};
     std::vector<Slot> slots;
     std::mutex mu;
-    std::condition_variable cv_work; // scheduler: new requests or stop
+    std::condition_variable cv_work; // workers: new requests or stop
     std::condition_variable cv_done; // waiters: a request finished
     std::deque<std::shared_ptr<Request>> pending;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> by_ticket;
     uint64_t next_ticket = 1;
     uint64_t pending_keys = 0;
     bool stop = false;
-    std::thread worker;
     hipError_t error = hipSuccess;
     // statistics
     uint64_t batches = 0;
@@ -118,8 +119,8 @@ uint64_t plan_slot(bbfc_server &s, Slot &slot)
 }
 
 // Stages a planned slot's keys and enqueues upload, query and download.
-// Runs without the lock: only the scheduler touches slots, and the clients
-// keep their key buffers valid until their requests are done.
+// Runs without the lock: only the slot's worker touches the slot, and the
+// clients keep their key buffers valid until their requests are done.
 hipError_t launch_slot(bbfc_server &s, Slot &slot, uint64_t used)
 {
     for (const Piece &p : slot.pieces) {
@@ -162,84 +163,53 @@ void finish_slot(bbfc_server &s, Slot &slot, Clock::time_point now)
         }
     }
     slot.pieces.clear();
-    slot.busy = false;
 }
 
-void scheduler(bbfc_server *sp)
+// Waits for a launched batch: polls its event every poll_us (0: yields).
+hipError_t wait_slot(const bbfc_server &s, const Slot &slot)
+{
+    for (;;) {
+        const hipError_t q = hipEventQuery(slot.done);
+        if (q != hipErrorNotReady)
+            return q;
+        if (s.cfg.poll_us)
+            std::this_thread::sleep_for(std::chrono::microseconds(s.cfg.poll_us));
+        else
+            std::this_thread::yield();
+    }
+}
+
+void slot_worker(bbfc_server *sp, Slot *slot_p)
 {
     bbfc_server &s = *sp;
+    Slot &slot = *slot_p;
     bbfc::DeviceGuard guard(s.filter->device);
-    std::vector<Slot *> finished, planned;
-    std::vector<uint64_t> planned_keys;
     std::unique_lock<std::mutex> lk(s.mu);
     for (;;) {
-        // 1. batches whose answers are back
-        finished.clear();
-        for (Slot &slot : s.slots) {
-            if (!slot.busy)
-                continue;
-            const hipError_t q = hipEventQuery(slot.done);
-            if (q == hipSuccess) {
-                finished.push_back(&slot);
-            } else if (q != hipErrorNotReady) {
-                s.error = q;
-                finished.push_back(&slot);
-            }
-        }
-        if (!finished.empty()) {
-            lk.unlock();
-            for (Slot *slot : finished)
-                copy_answers(*slot);
-            const Clock::time_point now = Clock::now();
-            lk.lock();
-            for (Slot *slot : finished)
-                finish_slot(s, *slot, now);
-            s.cv_done.notify_all();
-        }
-        // 2. new batches for free slots
-        planned.clear();
-        planned_keys.clear();
-        for (Slot &slot : s.slots) {
-            if (slot.busy || s.pending.empty())
-                continue;
-            const uint64_t used = plan_slot(s, slot);
-            if (used) {
-                slot.busy = true;
-                planned.push_back(&slot);
-                planned_keys.push_back(used);
-            }
-        }
-        if (!planned.empty()) {
-            lk.unlock();
-            hipError_t err = hipSuccess;
-            for (size_t i = 0; i < planned.size(); ++i) {
-                const hipError_t e = launch_slot(s, *planned[i], planned_keys[i]);
-                if (e != hipSuccess && err == hipSuccess)
-                    err = e;
-            }
-            lk.lock();
-            for (size_t i = 0; i < planned.size(); ++i) {
-                s.batches++;
-                s.batched_keys += planned_keys[i];
-            }
-            if (err != hipSuccess) {
-                s.error = err;
-                s.cv_done.notify_all();
-            }
-        }
-        bool any_busy = false;
-        for (const Slot &slot : s.slots)
-            any_busy |= slot.busy;
-        if (s.stop && s.pending.empty() && !any_busy)
-            break;
-        if (any_busy) {
-            // poll the device; clients submit meanwhile
-            lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(s.cfg.poll_us));
-            lk.lock();
-        } else if (s.pending.empty() && !s.stop) {
-            s.cv_work.wait(lk);
-        }
+        s.cv_work.wait(lk, [&] { return s.stop || !s.pending.empty(); });
+        if (s.pending.empty())
+            break; // stopping, and nothing left to serve
+        const uint64_t used = plan_slot(s, slot);
+        if (!s.pending.empty())
+            s.cv_work.notify_one(); // more work than this slot holds: wake another worker
+        if (used == 0)
+            continue;
+        s.batches++;
+        s.batched_keys += used;
+        lk.unlock();
+        hipError_t e = launch_slot(s, slot, used);
+        if (e == hipSuccess)
+            e = wait_slot(s, slot);
+        if (e == hipSuccess)
+            copy_answers(slot);
+        else
+            (void)hipStreamSynchronize(slot.stream); // nothing of this batch may still read the staging
+        const Clock::time_point now = Clock::now();
+        lk.lock();
+        if (e != hipSuccess && s.error == hipSuccess)
+            s.error = e;
+        finish_slot(s, slot, now);
+        s.cv_done.notify_all();
     }
 }
 
@@ -326,7 +296,8 @@ bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *con
         bbfc_server_destroy(s);
         return hip_fail(e, "allocating server slots");
     }
-    s->worker = std::thread(scheduler, s);
+    for (Slot &slot : s->slots)
+        slot.worker = std::thread(slot_worker, s, &slot);
     *out = s;
     return BBFC_OK;
 }
@@ -335,14 +306,14 @@ bbfc_status bbfc_server_destroy(bbfc_server_handle s)
 {
     if (s == nullptr)
         return fail(BBFC_EINVAL, "null server");
-    if (s->worker.joinable()) {
-        {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->stop = true;
-        }
-        s->cv_work.notify_all();
-        s->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
     }
+    s->cv_work.notify_all();
+    for (Slot &slot : s->slots)
+        if (slot.worker.joinable())
+            slot.worker.join();
     bbfc::DeviceGuard guard(s->filter->device);
     for (Slot &slot : s->slots) {
         if (slot.stream)

@@ -316,9 +316,16 @@ def test_probes_run(dev):
     sink = torch.zeros(1 << 16, dtype=torch.int64, device=dev)
     bbfc.probe_gather(buf, 1 << 18, 1, sink)
     bbfc.probe_gather(buf, 1 << 18, 1, sink, access_bytes=128)
+    bbfc.probe_insert_pattern(buf, 1 << 18, 0, 3, sink)
+    torch.cuda.synchronize()
+    assert not buf.any()
+    bbfc.probe_insert_pattern(buf, 1 << 18, 11, 4, sink)
+    torch.cuda.synchronize()
+    ones = int(np.bitwise_count(buf.cpu().numpy().view(np.uint64)).sum())
+    assert 0 < ones <= 11 * (1 << 18)
+    with pytest.raises(bbfc.BBFCError, match="mask_bits"):
+        bbfc.probe_insert_pattern(buf, 1, 33, 4, sink)
     bbfc.probe_atomic64(buf, 1 << 18, 2)
-    bbfc.probe_insert_pattern(buf, 1 << 18, False, 3, sink)
-    bbfc.probe_insert_pattern(buf, 1 << 18, True, 4, sink)
     dst = torch.empty_like(buf)
     bbfc.probe_copy(buf, dst)
     torch.cuda.synchronize()

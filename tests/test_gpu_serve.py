@@ -96,6 +96,45 @@ def test_large_requests_split_across_small_batches(served):
         assert np.array_equal(g, ref.query_bits(r))
 
 
+@pytest.mark.parametrize("poll_us", [0, 20])
+def test_concurrent_clients(served, poll_us):
+    """Six client threads submit and wait at once against eight slots of
+    2048 keys, so one request's pieces are served by several slots in
+    parallel; every answer equals the oracle's."""
+    import threading
+
+    ref, f, keys = served
+    per_client = [make_requests(keys, [5000, 1, 70_000, 64, 333, 20_000, 4097], 10 + i) for i in range(6)]
+    got = [[None] * len(r) for r in per_client]
+    errors = []
+    srv = bbfc.Server(f, n_slots=8, max_batch_keys=2048, poll_us=poll_us)
+
+    def client(i):
+        try:
+            tickets = [srv.submit(r) for r in per_client[i]]
+            for j, t in enumerate(tickets):
+                got[i][j] = srv.wait(t)[0].copy()
+        except Exception as e:  # reported below, on the main thread
+            errors.append(e)
+
+    try:
+        threads = [threading.Thread(target=client, args=(i,)) for i in range(len(per_client))]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert not errors, errors
+    total = sum(len(r) for reqs in per_client for r in reqs)
+    assert stats["completed"] == sum(len(r) for r in per_client)
+    assert stats["batched_keys"] >= total
+    for reqs, answers in zip(per_client, got):
+        for r, a in zip(reqs, answers):
+            assert np.array_equal(a, ref.query_bits(r))
+
+
 def test_zero_length_request(served):
     _, f, _ = served
     srv = bbfc.Server(f)
