@@ -338,7 +338,8 @@ bbfc_status bbfc_insert_kmers(bbfc_handle h, const uint64_t *d_seq, uint64_t n_s
                               hipStream_t stream);
 
 /* bbfc_query of the sequence's keys, computed inside the query kernel;
- * the answer for key t is bit t mod 64 of d_out_bits[t/64]. */
+ * the answer for key t is bit t mod 64 of d_out_bits[t/64]. EINVAL also
+ * when the output overlaps the sequence. */
 bbfc_status bbfc_query_kmers(bbfc_handle h, const uint64_t *d_seq, uint64_t n_segments, uint64_t seg_len, uint32_t q,
                              uint64_t *d_out_bits, hipStream_t stream);
 

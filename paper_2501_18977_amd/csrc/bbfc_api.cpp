@@ -467,6 +467,12 @@ bbfc_status bbfc_query_kmers(bbfc_handle h, const uint64_t *d_seq, uint64_t n_se
         return BBFC_OK;
     if (d_out_bits == nullptr)
         return fail(BBFC_EINVAL, "null output");
+    const uint64_t seq_words = (n_segments * seg_len + 31) / 32;
+    const uint64_t out_words = (bbfc_kmer_count(n_segments, seg_len, q) + 63) / 64;
+    const uintptr_t s0 = (uintptr_t)d_seq, s1 = s0 + seq_words * 8;
+    const uintptr_t o0 = (uintptr_t)d_out_bits, o1 = o0 + out_words * 8;
+    if (s0 < o1 && o0 < s1)
+        return fail(BBFC_EINVAL, "output overlaps the sequence");
     DeviceGuard guard(h->device);
     hipError_t e = bbfc::launch_query_kmers(*h, d_seq, n_segments, seg_len, q, d_out_bits, stream);
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching q-gram query");

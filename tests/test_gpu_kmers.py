@@ -144,3 +144,11 @@ def test_kmer_argument_errors(dev):
         bbfc.kmer_keys(seq, 1, 100, 0)
     assert bbfc.kmer_count(10, 20, 31) == 0
     assert len(bbfc.kmer_keys(seq, 10, 20, 31)) == 0
+    f = bbfc.Filter(64, 2, 8, "mix", seed=1)
+    try:
+        buf = torch.zeros(64, dtype=torch.int64, device=dev)
+        with pytest.raises(bbfc.BBFCError, match="overlaps"):
+            f.query_kmers(buf[:8], 1, 256, 31, out=buf[7:])  # 226 answers in 4 words, from word 7
+        f.query_kmers(buf[:8], 1, 256, 31, out=buf[8:])
+    finally:
+        f.close()
