@@ -144,6 +144,15 @@ def copy_calibration():
     print(json.dumps(rec), flush=True)
 
 
+def device_props(props) -> dict:
+    """What the runtime reports about the device (hipDeviceProp)."""
+    out = {"arch": getattr(props, "gcnArchName", None), "hbm_bytes": props.total_memory,
+           "l2_bytes": getattr(props, "L2_cache_size", None), "warp_size": getattr(props, "warp_size", None),
+           "max_threads_per_cu": getattr(props, "max_threads_per_multi_processor", None),
+           "shared_memory_per_block": getattr(props, "shared_memory_per_block", None)}
+    return {k: v for k, v in out.items() if v is not None}
+
+
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     for rel in ("paper_2501_18977_amd/csrc/bbfc_kernels.hip", "paper_2501_18977_amd/csrc/bbfc_common.hpp",
@@ -896,6 +905,7 @@ def main():
         "cpu_baseline": cpu,
         "device": props.name,
         "cus": props.multi_processor_count,
+        "device_props": device_props(props),
         "host": host_info(),
         "paper_cpu_reference": PAPER_CPU_REFERENCE,
         "kernel_source_sha": kernel_source_sha(),
