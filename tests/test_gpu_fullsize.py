@@ -1,0 +1,161 @@
+"""The measured workloads at full size, in the launch shapes that are timed
+(GPU only).
+
+* Plain filter: 2^30 keys (SplitMix64 counters [0, 2^30) of seed 0) are
+  inserted by the racing insert into 2^25 blocks (2 GiB; c = 2, k = 11, LA,
+  default multipliers of seed 0). Then the 2^30 keys and 2^30 never-inserted
+  keys (counters [2^30, 2^31)) are queried with 8 lanes per key and 2 tiles
+  per wavefront, the autotuner's pick on this workload. Checks:
+  - every inserted key answers true;
+  - 2^20 sampled answers equal the oracle's query of the same keys on the
+    downloaded filter;
+  - every other query shape, with early exit on and off, writes the same
+    answer words;
+  - the false-positive rate over the 2^30 negatives equals, within 2%, the
+    oracle's conditional estimate for this filter. The estimate is the exact
+    hit probability of 2^22 sampled negatives given the blocks' contents.
+* DNA q-grams: a 128 Mbp uniform genome, its 127,999,970 canonical 31-mers
+  inserted (fused kernel) into 3,000,000 blocks (12 bits per key; c = 3,
+  k = 8, MIX). It is then queried with 10^7 reads of 150 bp at 1%
+  substitutions and 10^7 random reads. Checks:
+  - every genome 31-mer answers true;
+  - sampled genome windows, whose 31-mers the oracle extracts itself, are
+    all present in the downloaded filter;
+  - the answers for 4096 sampled reads of each set equal the oracle's
+    (oracle q-grams, oracle query on the downloaded filter).
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2501_18977_amd as bbfc
+import workload
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+def answer_bits(words_host: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """Answer bit t of packed words (bit t % 64 of word t // 64) for each t in idx."""
+    idx = np.asarray(idx, dtype=np.uint64)
+    return ((words_host[idx >> np.uint64(6)] >> (idx & np.uint64(63))) & np.uint64(1)).astype(bool)
+
+
+def test_plain_filter_2_pow_30_keys(dev):
+    N, M, C, K = 1 << 30, 1 << 25, 2, 11
+    bm, am = oracle.derive_multipliers(0, M, C, K)
+    keys = torch.empty(2 * N, dtype=torch.int64, device=dev)
+    workload.device_keys(0, 0, N, out=keys[:N])
+    workload.device_keys(0, N, N, out=keys[N:])
+    f = bbfc.Filter(M, C, K, "la", seed=0)
+    try:
+        assert list(f.params.block_mult) == bm and list(f.params.bit_mult) == am
+        f.set_shape(bbfc.OP_INSERT, 8, 1)
+        f.set_shape(bbfc.OP_QUERY, 8, 2)
+        print("plain: 2^30 keys into 2^25 blocks, racing insert 8x1, query 8x2", flush=True)
+        f.insert(keys[:N])
+        out = f.query(keys)
+        torch.cuda.synchronize()
+        assert bool(torch.all(out[: N // 64] == -1)), "an inserted key answered false"
+
+        # other shapes and early exit on/off: the same answer words
+        out2 = torch.empty_like(out)
+        for early in (1, 0):
+            f.set_option(bbfc.OPT_QUERY_EARLY_EXIT, early)
+            for lpk in (8, 4):
+                for tpw in (1, 2):
+                    f.set_shape(bbfc.OP_QUERY, lpk, tpw)
+                    f.query(keys, out=out2)
+                    torch.cuda.synchronize()
+                    assert torch.equal(out, out2), (lpk, tpw, early)
+        f.set_option(bbfc.OPT_QUERY_EARLY_EXIT, 1)
+        del out2
+
+        words = f.download()
+        out_h = out.cpu().numpy().view(np.uint64)
+        chk = oracle.OracleFilter(M, C, K, oracle.COST_LA, None, bm, am)
+        chk.words = words
+        # 64 runs of 16384 consecutive counters anywhere in [0, 2^31)
+        rng = np.random.default_rng(30)
+        for start in rng.integers(0, 2 * N - 16384, size=64):
+            idx = np.arange(int(start), int(start) + 16384, dtype=np.uint64)
+            sample = workload.splitmix64_keys(0, int(start), 16384)
+            assert np.array_equal(answer_bits(out_h, idx), chk.query(sample)), int(start)
+
+        fp = int(np.bitwise_count(out_h[N // 64:]).sum())
+        est = chk.conditional_fpr(workload.splitmix64_keys(0, N + 12345, 1 << 22))
+        print(f"plain: FPR over 2^30 negatives {fp / N:.4e}, oracle conditional estimate {est:.4e}", flush=True)
+        assert fp / N == pytest.approx(est, rel=0.02)
+    finally:
+        f.close()
+        del keys
+
+
+def read_bases(packed: np.ndarray, reads: np.ndarray, length: int) -> np.ndarray:
+    """Bases (one per byte) of the given reads of a packed read set."""
+    start = reads.astype(np.int64) * length
+    word = start // 32
+    off = start % 32
+    span = (length + 31) // 32 + 1
+    padded = np.concatenate([packed, np.zeros(span, dtype=np.uint64)])
+    w = padded[word[:, None] + np.arange(span)[None, :]]
+    shifts = np.arange(62, -1, -2, dtype=np.uint64)
+    b = ((w[:, :, None] >> shifts[None, None, :]) & np.uint64(3)).astype(np.uint8).reshape(len(reads), -1)
+    return b[np.arange(len(reads))[:, None], off[:, None] + np.arange(length)[None, :]]
+
+
+def test_kmer_workload_128_mbp(dev):
+    q, L, G, R = 31, 150, 128_000_000, 10_000_000
+    n_g = G - q + 1
+    M = bbfc.blocks_for(n_g, 12)
+    assert M == math.ceil(n_g * 12 / 512) == 3_000_000
+    C, K = 3, 8
+    genome = workload.device_keys(21, 0, (G + 31) // 32, device=dev)
+    reads = workload.device_reads(genome, G, R, L, 0.01, seed=22)
+    rnd = workload.device_keys(23, 0, (R * L + 31) // 32, device=dev)
+    bm, am = oracle.derive_multipliers(0, M, C, K)
+    f = bbfc.Filter(M, C, K, "mix", seed=0)
+    try:
+        assert list(f.params.block_mult) == bm and list(f.params.bit_mult) == am
+        print("kmer: 128 Mbp genome, 3,000,000 blocks, c=3 k=8 MIX, default shapes", flush=True)
+        f.insert_kmers(genome, 1, G, q)
+        g_out = f.query_kmers(genome, 1, G, q)
+        out_p = f.query_kmers(reads, R, L, q)
+        out_n = f.query_kmers(rnd, R, L, q)
+        torch.cuda.synchronize()
+        g_h = g_out.cpu().numpy().view(np.uint64)
+        assert np.all(g_h[: n_g // 64] == np.uint64(2**64 - 1))
+        assert answer_bits(g_h, np.arange(n_g // 64 * 64, n_g)).all(), "a genome 31-mer answered false"
+
+        chk = oracle.OracleFilter(M, C, K, oracle.COST_MIX, None, bm, am)
+        chk.words = f.download()
+        g_packed = genome.cpu().numpy().view(np.uint64)
+        rng = np.random.default_rng(31)
+        for s in rng.integers(0, G - 20_000, size=16):
+            bases = workload.unpack_2bit(g_packed[s // 32:(s + 20_000) // 32 + 2], 20_000 + 64)[s % 32:s % 32 + 20_000]
+            assert chk.query(oracle.qgrams(bases, 1, len(bases), q)).all(), int(s)
+
+        per = L - q + 1
+        for name, packed_d, out in (("reads", reads, out_p), ("random", rnd, out_n)):
+            packed = packed_d.cpu().numpy().view(np.uint64)
+            sel = np.sort(rng.choice(R, size=4096, replace=False))
+            bases = read_bases(packed, sel, L).reshape(-1)
+            want = chk.query(oracle.qgrams(bases, len(sel), L, q))
+            idx = (sel[:, None].astype(np.uint64) * np.uint64(per) + np.arange(per, dtype=np.uint64)[None, :]).reshape(-1)
+            got = answer_bits(out.cpu().numpy().view(np.uint64), idx)
+            print(f"kmer: {name}: sampled hit rate {got.mean():.4f}", flush=True)
+            assert np.array_equal(got, want), name
+    finally:
+        f.close()
