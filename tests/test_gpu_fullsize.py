@@ -23,6 +23,10 @@
     all present in the downloaded filter;
   - the answers for 4096 sampled reads of each set equal the oracle's
     (oracle q-grams, oracle query on the downloaded filter).
+* Batch: 256 filters of uneven sizes through a hipGraph of the persistent
+  insert and query (see its test).
+* Serving: requests of mixed sizes replayed against the 2^30-key filter
+  (see its test).
 """
 
 import math
@@ -157,5 +161,118 @@ def test_kmer_workload_128_mbp(dev):
             got = answer_bits(out.cpu().numpy().view(np.uint64), idx)
             print(f"kmer: {name}: sampled hit rate {got.mean():.4f}", flush=True)
             assert np.array_equal(got, want), name
+    finally:
+        f.close()
+
+
+def test_batch_256_filters(dev):
+    """256 filters, key counts log-uniform in [2^10, 2^24] (4.1e8 keys),
+    10-16 bits per key, c = 2, EXP; one persistent insert and one persistent
+    query replayed from a hipGraph in the shapes the autotuner picks on this
+    workload. Every inserted key answers true, every query shape writes the
+    same words, and sampled answers of 12 filters equal the oracle's on the
+    downloaded filters."""
+    specs = workload.batch_specs(3, 256)
+    filters, ns, ks, Ms = [], [], [], []
+    for f, (n, bits) in enumerate(specs):
+        k = int(round(bits * math.log(2)))
+        M = max(1, math.ceil(n * bits / 512))
+        filters.append(bbfc.Filter(M, 2, k, "exp", seed=f))
+        ns.append(n)
+        ks.append(k)
+        Ms.append(M)
+    try:
+        total = sum(ns)
+        ins = torch.empty(total, dtype=torch.int64, device=dev)
+        qry = torch.empty(2 * total, dtype=torch.int64, device=dev)
+        ko = 0
+        for f, n in enumerate(ns):
+            workload.device_keys(1000 + f, 0, n, out=ins[ko:ko + n])
+            workload.device_keys(1000 + f, 0, 2 * n, out=qry[2 * ko:2 * ko + 2 * n])
+            ko += n
+        ins_plan = bbfc.Batch(filters, ns)
+        q_plan = bbfc.Batch(filters, [2 * n for n in ns])
+        ins_plan.set_shape(bbfc.OP_INSERT, 8, 1, 0, 1)
+        q_plan.set_shape(bbfc.OP_QUERY, 8, 1, 0, 16)
+        out = torch.empty(q_plan.total_out_words, dtype=torch.int64, device=dev)
+        print(f"batch: 256 filters, {total} keys, graph of persistent insert 8x1 and query 8x1 (grabs of 16)", flush=True)
+        graph = bbfc.Graph(ins_plan, ins, q_plan, qry, out)
+        graph.launch()
+        torch.cuda.synchronize()
+        out_h = out.cpu().numpy().view(np.uint64)
+        for f, n in enumerate(ns):
+            w0 = q_plan.out_offsets[f]
+            assert answer_bits(out_h, np.arange(w0 * 64, w0 * 64 + n)).all(), f"filter {f}: a false negative"
+
+        out2 = torch.empty_like(out)
+        for lpk in (8, 4):
+            for tpw in (1, 2):
+                for grab in (0, 16):
+                    q_plan.set_shape(bbfc.OP_QUERY, lpk, tpw, 0, grab)
+                    q_plan.query(qry, out=out2)
+                    torch.cuda.synchronize()
+                    assert torch.equal(out, out2), (lpk, tpw, grab)
+
+        order = np.argsort(ns)
+        pick = list(order[:4]) + list(order[len(order) // 2 - 2:len(order) // 2 + 2]) + list(order[-4:])
+        for f in pick:
+            f = int(f)
+            n, w0 = ns[f], q_plan.out_offsets[f]
+            bm, am = oracle.derive_multipliers(f, Ms[f], 2, ks[f])
+            chk = oracle.OracleFilter(Ms[f], 2, ks[f], oracle.COST_EXP, None, bm, am)
+            chk.words = filters[f].download()
+            cnt = min(n, 8192)
+            for start in (0, n - cnt, n, 2 * n - cnt):  # first and last positives, first and last negatives
+                sample = workload.splitmix64_keys(1000 + f, start, cnt)
+                got = answer_bits(out_h, np.arange(w0 * 64 + start, w0 * 64 + start + cnt))
+                assert np.array_equal(got, chk.query(sample)), (f, start)
+    finally:
+        for fl in filters:
+            fl.close()
+
+
+def test_serve_resident_2_pow_30_filter(dev):
+    """The serving workload: 3000 requests (sizes log-uniform in [1, 65536],
+    half inserted keys) replayed at an offered 4 G keys/s through 4 slots of
+    2^20 keys against the 2^30-key filter. Each request's answers equal
+    those of one plain query over all the requests' keys, and the oracle's
+    on the downloaded filter for 300 sampled requests."""
+    n = 1 << 30
+    M = n // 32
+    f = bbfc.Filter(M, 2, 11, "la", seed=0)
+    try:
+        keys = workload.device_keys(0, 0, n, device=dev)
+        f.insert(keys)
+        torch.cuda.synchronize()
+        del keys
+        sizes, pst, nst = workload.serve_requests(11, 3000, n)
+        parts = []
+        for s, p, q in zip(sizes, pst, nst):
+            npos = (s + 1) // 2
+            parts.append(workload.splitmix64_keys(0, p, npos))
+            parts.append(workload.splitmix64_keys(0, q, s - npos))
+        flat = np.concatenate(parts)
+        offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum(sizes)
+        arrivals = np.cumsum(np.random.default_rng(5).exponential(len(flat) / len(sizes) / 4e9, size=len(sizes)))
+        srv = bbfc.Server(f, n_slots=4, max_batch_keys=1 << 20, max_pending_keys=1 << 27)
+        try:
+            answers, lat, wall = srv.replay(flat, offs, arrivals)
+        finally:
+            srv.close()
+        print(f"serve: {len(flat)} keys in {wall * 1e3:.1f} ms, p50 {np.percentile(lat, 50):.0f} us, "
+              f"p99 {np.percentile(lat, 99):.0f} us", flush=True)
+        plain = bbfc.unpack_bits(f.query(torch.from_numpy(flat.view(np.int64)).to(dev)), len(flat))
+        words = f.download()
+        chk = oracle.OracleFilter(M, 2, 11, oracle.COST_LA, None, *oracle.derive_multipliers(0, M, 2, 11))
+        chk.words = words
+        sampled = set(np.random.default_rng(6).choice(len(sizes), size=300, replace=False).tolist())
+        for i, s in enumerate(sizes):
+            a, b = int(offs[i]), int(offs[i + 1])
+            got = bbfc.unpack_bits(answers[i], s)
+            assert np.array_equal(got, plain[a:b]), i
+            assert got[: (s + 1) // 2].all(), i
+            if i in sampled:
+                assert np.array_equal(got, chk.query(flat[a:b])), i
     finally:
         f.close()
