@@ -23,6 +23,8 @@
     all present in the downloaded filter;
   - the answers for 4096 sampled reads of each set equal the oracle's
     (oracle q-grams, oracle query on the downloaded filter).
+* Large q-gram build: a 3.1 Gbp genome with 10% planted repeats in a 5.1 GB
+  filter (see its test).
 * Batch: 256 filters of uneven sizes through a hipGraph of the persistent
   insert and query (see its test).
 * Serving: requests of mixed sizes replayed against the 2^30-key filter
@@ -274,5 +276,49 @@ def test_serve_resident_2_pow_30_filter(dev):
             assert got[: (s + 1) // 2].all(), i
             if i in sampled:
                 assert np.array_equal(got, chk.query(flat[a:b])), i
+    finally:
+        f.close()
+
+
+def test_kmer_workload_3100_mbp_with_repeats(dev):
+    """The large q-gram build: a 3.1 Gbp uniform genome with 10% planted
+    repeats (300-6000 bp copies at 2% divergence), its 3.1e9 canonical
+    31-mers inserted into a filter sized for the expected distinct count at
+    14 bits per key (80,234,269 blocks, 5.1 GB; c = 3, k = 10, MIX), queried
+    with 5e7 reads of 150 bp at 1% substitutions. Sampled genome windows
+    (oracle q-grams) are all present in the downloaded filter, and the
+    answers of 4096 sampled reads equal the oracle's."""
+    q, L, G, R = 31, 150, 3_100_000_000, 50_000_000
+    n_g = G - q + 1
+    genome = workload.device_keys(21, 0, (G + 31) // 32, device=dev)
+    segs = workload.repeat_segments(24, G, 0.1)
+    genome = workload.device_plant(genome, G, segs, 0.02, seed=25)
+    reads = workload.device_reads(genome, G, R, L, 0.01, seed=22)
+    M = bbfc.blocks_for(int(n_g * (1.0 - 0.1 * 0.98 ** q)), 14)
+    assert M == 80_234_269
+    C, K = 3, 10
+    bm, am = oracle.derive_multipliers(0, M, C, K)
+    f = bbfc.Filter(M, C, K, "mix", seed=0)
+    try:
+        print(f"kmer large: {len(segs[0])} planted segments, {M} blocks", flush=True)
+        f.insert_kmers(genome, 1, G, q)
+        out = f.query_kmers(reads, R, L, q)
+        torch.cuda.synchronize()
+        chk = oracle.OracleFilter(M, C, K, oracle.COST_MIX, None, bm, am)
+        chk.words = f.download()
+        g_packed = genome.cpu().numpy().view(np.uint64)
+        rng = np.random.default_rng(32)
+        for s in rng.integers(0, G - 20_000, size=16):
+            bases = workload.unpack_2bit(g_packed[s // 32:(s + 20_000) // 32 + 2], 20_000 + 64)[s % 32:s % 32 + 20_000]
+            assert chk.query(oracle.qgrams(bases, 1, len(bases), q)).all(), int(s)
+        del g_packed
+        per = L - q + 1
+        packed = reads.cpu().numpy().view(np.uint64)
+        sel = np.sort(rng.choice(R, size=4096, replace=False))
+        want = chk.query(oracle.qgrams(read_bases(packed, sel, L).reshape(-1), len(sel), L, q))
+        idx = (sel[:, None].astype(np.uint64) * np.uint64(per) + np.arange(per, dtype=np.uint64)[None, :]).reshape(-1)
+        got = answer_bits(out.cpu().numpy().view(np.uint64), idx)
+        print(f"kmer large: sampled read hit rate {got.mean():.4f}", flush=True)
+        assert np.array_equal(got, want)
     finally:
         f.close()
