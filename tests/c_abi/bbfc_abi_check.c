@@ -1,0 +1,148 @@
+/*
+ * A C program that drives the library through its C ABI alone (no Python,
+ * no PyTorch): device buffers from hipMalloc, results checked against the
+ * sequential oracle (oracle/liboracle.so), which is linked here as test
+ * infrastructure. Exit status 0 when every check passes.
+ *
+ *  1. default multipliers of a seeded filter equal the oracle's derivation
+ *     (Section 3.4, the random multipliers coprime to their modulus);
+ *  2. the deterministic insert builds the oracle's filter word for word, and
+ *     queries of inserted and new keys give the oracle's answer bits;
+ *  3. the racing insert has no false negatives;
+ *  4. argument errors return BBFC_EINVAL with a message and enqueue nothing.
+ */
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "bbfc.h"
+
+/* oracle entry points (oracle/bbfc_oracle.c) */
+typedef struct {
+    uint64_t M, T, sub_mult;
+} bbo_layout;
+uint64_t bbo_insert(uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct, int kind, double param,
+                    const uint64_t *block_mult, const uint64_t *bit_mult, const uint64_t *keys, uint64_t n);
+uint64_t bbo_query(const uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct,
+                   const uint64_t *block_mult, const uint64_t *bit_mult, const uint64_t *keys, uint64_t n,
+                   uint64_t *out_bits);
+void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint64_t T, uint32_t c, uint32_t k, int distinct,
+                            uint64_t *block_mult, uint64_t *bit_mult, uint64_t *sub_mult);
+double bbo_default_param(int kind, uint32_t k);
+
+static int failures = 0;
+
+#define CHECK(cond, ...)                                                                                           \
+    do {                                                                                                           \
+        if (!(cond)) {                                                                                             \
+            printf("FAIL %s:%d: ", __FILE__, __LINE__);                                                            \
+            printf(__VA_ARGS__);                                                                                   \
+            printf("\n");                                                                                          \
+            failures++;                                                                                            \
+        }                                                                                                          \
+    } while (0)
+
+#define HIP(call)                                                                                                  \
+    do {                                                                                                           \
+        hipError_t e_ = (call);                                                                                    \
+        if (e_ != hipSuccess) {                                                                                    \
+            printf("HIP error %s at %s:%d\n", hipGetErrorString(e_), __FILE__, __LINE__);                          \
+            exit(2);                                                                                               \
+        }                                                                                                          \
+    } while (0)
+
+/* Counter-based SplitMix64 keys (Steele, Lea, Flood 2014): key(seed, i) is
+ * the finaliser of seed + (i + 1) * golden gamma. */
+static uint64_t key_at(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+int main(void)
+{
+    const uint64_t M = 3001; /* odd: the remainder case of the block hash */
+    const uint32_t c = 3, k = 12;
+    const uint64_t n = 50000, nq = 2 * n;
+    bbfc_cost exp_cost = {BBFC_COST_EXP, NAN};
+
+    /* 1. a seeded filter's parameters */
+    bbfc_handle a = NULL;
+    bbfc_status st = bbfc_create_seeded(M, c, k, exp_cost, 5, &a);
+    CHECK(st == BBFC_OK, "create: %s", bbfc_last_error());
+    if (st != BBFC_OK)
+        return 1;
+    uint64_t bm[4], am[32], obm[4], oam[32], osm = 0, pM = 0;
+    uint32_t pc = 0, pk = 0;
+    bbfc_cost pcost;
+    CHECK(bbfc_get_params(a, &pM, &pc, &pk, &pcost, bm, am) == BBFC_OK, "get_params");
+    bbo_derive_multipliers(5, M, 1, c, k, 0, obm, oam, &osm);
+    CHECK(pM == M && pc == c && pk == k && pcost.kind == BBFC_COST_EXP, "params");
+    CHECK(pcost.param == bbo_default_param(BBFC_COST_EXP, k), "EXP base %.17g", pcost.param);
+    CHECK(memcmp(bm, obm, c * 8) == 0 && memcmp(am, oam, k * 8) == 0, "multipliers differ from the oracle's");
+
+    /* 2. deterministic insert and query against the oracle */
+    uint64_t *h_keys = malloc(nq * 8);
+    for (uint64_t i = 0; i < nq; i++)
+        h_keys[i] = key_at(7, i); /* [0, n) inserted, [n, 2n) never inserted */
+    uint64_t *d_keys = NULL, *d_out = NULL;
+    HIP(hipMalloc((void **)&d_keys, nq * 8));
+    HIP(hipMalloc((void **)&d_out, (nq + 63) / 64 * 8));
+    HIP(hipMemcpy(d_keys, h_keys, nq * 8, hipMemcpyHostToDevice));
+    CHECK(bbfc_insert_deterministic(a, d_keys, n, NULL) == BBFC_OK, "insert_deterministic: %s", bbfc_last_error());
+    CHECK(bbfc_query(a, d_keys, nq, d_out, NULL) == BBFC_OK, "query: %s", bbfc_last_error());
+    uint64_t *got_words = malloc(M * 64), *want_words = calloc(M * 8, 8);
+    uint64_t *got_bits = malloc((nq + 63) / 64 * 8), *want_bits = malloc((nq + 63) / 64 * 8);
+    CHECK(bbfc_download(a, got_words, NULL) == BBFC_OK, "download");
+    HIP(hipMemcpy(got_bits, d_out, (nq + 63) / 64 * 8, hipMemcpyDeviceToHost));
+    const bbo_layout L = {M, 1, 0};
+    bbo_insert(want_words, &L, c, k, 0, BBFC_COST_EXP, bbo_default_param(BBFC_COST_EXP, k), bm, am, h_keys, n);
+    const uint64_t hits = bbo_query(want_words, &L, c, k, 0, bm, am, h_keys, nq, want_bits);
+    CHECK(memcmp(got_words, want_words, M * 64) == 0, "deterministic insert differs from the oracle");
+    CHECK(memcmp(got_bits, want_bits, (nq + 63) / 64 * 8) == 0, "query bits differ from the oracle");
+    CHECK(hits >= n && hits < nq, "oracle hits %llu", (unsigned long long)hits);
+
+    /* 3. racing insert: every inserted key answers true */
+    bbfc_handle b = NULL;
+    bbfc_cost la = {BBFC_COST_LA, NAN};
+    CHECK(bbfc_create(4096, 2, 11, la, &b) == BBFC_OK, "create: %s", bbfc_last_error());
+    CHECK(bbfc_insert(b, d_keys, n, NULL) == BBFC_OK, "insert: %s", bbfc_last_error());
+    CHECK(bbfc_query(b, d_keys, n, d_out, NULL) == BBFC_OK, "query: %s", bbfc_last_error());
+    HIP(hipMemcpy(got_bits, d_out, (n + 63) / 64 * 8, hipMemcpyDeviceToHost));
+    uint64_t answered = 0;
+    for (uint64_t t = 0; t < n; t++)
+        answered += (got_bits[t / 64] >> (t % 64)) & 1;
+    CHECK(answered == n, "racing insert: %llu of %llu keys answer true", (unsigned long long)answered,
+          (unsigned long long)n);
+
+    /* 4. argument errors */
+    bbfc_handle bad = NULL;
+    CHECK(bbfc_create(0, 2, 11, la, &bad) == BBFC_EINVAL && bad == NULL, "n_blocks 0 accepted");
+    CHECK(strlen(bbfc_last_error()) > 0, "no error text");
+    CHECK(bbfc_create(64, 2, 33, la, &bad) == BBFC_EINVAL, "k = 33 accepted");
+    CHECK(bbfc_create(64, 1, 8, la, &bad) == BBFC_EINVAL, "one choice with a cost accepted");
+    CHECK(bbfc_query(b, d_keys, 1024, d_keys + 8, NULL) == BBFC_EINVAL, "overlapping output accepted");
+    CHECK(bbfc_insert(b, NULL, 10, NULL) == BBFC_EINVAL, "null keys accepted");
+    CHECK(bbfc_insert(b, NULL, 0, NULL) == BBFC_OK, "an empty insert is not a no-op");
+    CHECK(strcmp(bbfc_status_string(BBFC_EINVAL), "invalid argument") == 0, "status string");
+
+    CHECK(bbfc_destroy(a) == BBFC_OK, "destroy");
+    CHECK(bbfc_destroy(b) == BBFC_OK, "destroy");
+    HIP(hipFree(d_keys));
+    HIP(hipFree(d_out));
+    free(h_keys);
+    free(got_words);
+    free(want_words);
+    free(got_bits);
+    free(want_bits);
+    if (failures) {
+        printf("%d check(s) failed\n", failures);
+        return 1;
+    }
+    printf("c abi check ok: M=%llu c=%u k=%u n=%llu; oracle hits %llu of %llu\n", (unsigned long long)M, c, k,
+           (unsigned long long)n, (unsigned long long)hits, (unsigned long long)nq);
+    return 0;
+}
