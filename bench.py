@@ -162,18 +162,18 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(op: str, kernel: str):
+def measured_traffic(op: str, kernel: str, config: dict):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
     calibration), or None if the summary is absent, was taken on a different
-    kernel source, or has no such launch shape."""
+    kernel source or workload configuration, or has no such launch shape."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha") != kernel_source_sha():
+    if rec.get("source_sha") != kernel_source_sha() or rec.get("config") != config:
         return None
     return rec.get("bytes_per_launch", {}).get(kernel)
 
@@ -794,6 +794,9 @@ def main():
         dom, dom_ms, dom_bytes = "query", avg_qry, QUERY_BYTES_PER_KEY * n_q
         dom_kernel = kernel_name("query", c, filt.get_shape(bbfc.OP_QUERY))
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
+    # the workload the committed counters were taken on must be this one
+    traffic_cfg = {"n_keys": n, "n_blocks": n_blocks, "bit_selection": args.bits, "subarrays": T,
+                   "insert": args.insert}
 
     def with_traffic(rec, traffic, ms):
         # HBM bytes the counters saw per launch (each random 64-byte block
@@ -814,7 +817,7 @@ def main():
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "bytes_per_launch_algorithmic": int(dom_bytes),
         "launch_ms": round(dom_ms, 3),
-    }, measured_traffic(dom, dom_kernel), dom_ms)
+    }, measured_traffic(dom, dom_kernel, traffic_cfg), dom_ms)
     q_kernel = kernel_name("query", c, filt.get_shape(bbfc.OP_QUERY))
     q_bytes = QUERY_BYTES_PER_KEY * n_q
     roofline_query = with_traffic({
@@ -826,7 +829,7 @@ def main():
         "frac": round(q_bytes / (avg_qry / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         "bytes_per_launch_algorithmic": int(q_bytes),
         "launch_ms": round(avg_qry, 3),
-    }, measured_traffic("query", q_kernel), avg_qry)
+    }, measured_traffic("query", q_kernel, traffic_cfg), avg_qry)
 
     probe = None
     if not args.no_probe:
