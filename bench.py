@@ -314,6 +314,8 @@ def bench_batch(args):
         for fl, o, wo, n in zip(filters, ins_plan.key_offsets, q_plan.out_offsets, ns):
             fl.query(qry[2 * o:2 * o + 2 * n], out=out[wo:], stream=stream)
 
+    # each timing is the mean over args.steps runs (HIP events on the launch
+    # stream); inserts start from cleared filters, outside the timed region
     def timed(fn, reps):
         ms = []
         for _ in range(reps):
@@ -324,11 +326,13 @@ def bench_batch(args):
             e1.record(stream)
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
-        return min(ms)
+        return sum(ms) / len(ms)
 
     def measure(tag, ins_fn, q_fn, both_fn=None):
-        ins_fn()  # warm-up
-        q_fn()
+        for _ in range(max(1, args.warmup)):
+            clear_all()
+            ins_fn()
+            q_fn()
         torch.cuda.synchronize()
         ti = timed(ins_fn, args.steps)
         ins_fn()
@@ -349,7 +353,7 @@ def bench_batch(args):
             e1.record(stream)
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
-        return min(ms)
+        return sum(ms) / len(ms)
 
     results = {}
     measure("plain_per_filter", plain_insert, plain_query)
@@ -388,7 +392,7 @@ def bench_batch(args):
         "unit": "Mkeys/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": 1,
+        "warmup": max(1, args.warmup),
         "ms_per_step": t_best,
         "higher_is_better": True,
         "scaling": "weak",
@@ -611,18 +615,17 @@ def bench_kmer(args):
         return [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
 
     def timed(fn):
-        fn()
-        torch.cuda.synchronize()
-        best = None
-        for _ in range(args.steps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
+        # args.warmup untimed steps, then args.steps steps between two events
+        for _ in range(max(1, args.warmup)):
             fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            best = ms if best is None else min(best, ms)
-        return best
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
 
     t_fused = timed(fused)
     t_unfused = timed(unfused) if not args.no_unfused else None
@@ -643,7 +646,7 @@ def bench_kmer(args):
         "unit": "Mkeys/s",
         "n_gpus": 1,
         "steps": args.steps,
-        "warmup": 1,
+        "warmup": max(1, args.warmup),
         "ms_per_step": round(t_fused, 3),
         "higher_is_better": True,
         "scaling": "weak",
