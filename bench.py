@@ -268,11 +268,12 @@ PAPER_CPU_REFERENCE = {
 def bench_batch(args):
     """256 filters with key counts log-uniform in [2^10, 2^24], 10-16 bits
     per key (k = round(b ln 2)), 2 choices, EXP cost; each filter gets its
-    own seeded keys and is queried with as many never-inserted keys. Four
+    own seeded keys and is queried with as many never-inserted keys. Five
     ways to run one insert pass and one query pass over all filters:
-    one plain launch per filter and operation, one persistent launch per
-    operation, the persistent launches in a hipGraph, and the same after the
-    autotuner picked each operation's launch shape."""
+    one plain launch per filter and operation (on one stream, and spread
+    over 8 streams), one persistent launch per operation, the persistent
+    launches in a hipGraph, and the same after the autotuner picked each
+    operation's launch shape."""
     import numpy as np
     import torch
 
@@ -313,6 +314,36 @@ def bench_batch(args):
     def plain_query():
         for fl, o, wo, n in zip(filters, ins_plan.key_offsets, q_plan.out_offsets, ns):
             fl.query(qry[2 * o:2 * o + 2 * n], out=out[wo:], stream=stream)
+
+    # the same plain launches spread over 8 streams (default priority), so
+    # the filters' launches overlap on the device; the launch stream waits
+    # for all of them
+    side = [torch.cuda.Stream(device=dev) for _ in range(8)]
+
+    def on_side_streams(launch):
+        start = torch.cuda.Event()
+        start.record(stream)
+        done = []
+        for i, s_i in enumerate(side):
+            s_i.wait_event(start)
+        for f_i in range(len(filters)):
+            launch(f_i, side[f_i % len(side)])
+        for s_i in side:
+            ev = torch.cuda.Event()
+            ev.record(s_i)
+            done.append(ev)
+        for ev in done:
+            stream.wait_event(ev)
+
+    def plain_insert_streams():
+        on_side_streams(lambda i, st: filters[i].insert(ins[ins_plan.key_offsets[i]:ins_plan.key_offsets[i] + ns[i]],
+                                                        st))
+
+    def plain_query_streams():
+        def q(i, st):
+            o, n = ins_plan.key_offsets[i], ns[i]
+            filters[i].query(qry[2 * o:2 * o + 2 * n], out=out[q_plan.out_offsets[i]:], stream=st)
+        on_side_streams(q)
 
     # each timing is the mean over args.steps runs (HIP events on the launch
     # stream); inserts start from cleared filters, outside the timed region
@@ -357,6 +388,7 @@ def bench_batch(args):
 
     results = {}
     measure("plain_per_filter", plain_insert, plain_query)
+    measure("plain_per_filter_8_streams", plain_insert_streams, plain_query_streams)
     measure("persistent", lambda: ins_plan.insert(ins, stream), lambda: q_plan.query(qry, out=out, stream=stream))
     graph = bbfc.Graph(insert_batch=ins_plan, insert_keys=ins, query_batch=q_plan, query_keys=qry, out=out)
     measure("persistent_graph", lambda: ins_plan.insert(ins, stream), lambda: q_plan.query(qry, out=out, stream=stream),
