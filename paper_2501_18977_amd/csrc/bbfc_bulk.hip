@@ -17,11 +17,15 @@
 // together against the state left by all earlier windows.
 //
 // Kernels, per radix pass p (digits of h_0, least significant first):
-//   bulk_hist_kernel     per tile of 4096 keys, the count of each digit
-//   scan kernels         exclusive prefix over (digit, tile), digit-major
-//   bulk_scatter_kernel  stable scatter of each tile, staged in LDS so the
-//                        writes go out as runs
-// then bulk_insert_kernel over the sorted keys.
+//   bulk_hist_kernel     per group of up to 16 tiles of 4096 keys, the
+//                        count of each digit
+//   scan kernels         exclusive prefix over (digit, group), digit-major
+//   bulk_scatter_kernel  one workgroup per group: stable scatter of each of
+//                        its tiles in order, staged in LDS so the writes go
+//                        out as runs
+// then bulk_insert_kernel over the sorted keys. Counting per group rather
+// than per tile keeps the count table (read and written with one 4-byte
+// access per digit and group) small next to the keys.
 #include <stdint.h>
 
 #include <utility>
@@ -39,6 +43,7 @@ constexpr int kPartThreads = 256;
 constexpr int kPartPerLane = 16;
 constexpr int kPartTile = kPartThreads * kPartPerLane; // 4096 keys per tile
 constexpr int kPartWaveKeys = kWave * kPartPerLane;    // 1024 keys per wavefront of a tile
+constexpr uint32_t kMaxTilesPerGroup = 16; // counted groups: up to 16 tiles, at least ~2048 groups
 constexpr int kMaxDigitBits = 9;
 constexpr int kMaxDigits = 1 << kMaxDigitBits;
 constexpr int kScanThreads = 256;
@@ -79,22 +84,24 @@ __device__ __forceinline__ uint64_t lanemask_lt(uint32_t lane)
 template <int MODE>
 __global__ __launch_bounds__(kPartThreads) void bulk_hist_kernel(const uint64_t *__restrict__ keys, uint64_t n,
                                                                  Digit dg, uint32_t n_digits,
-                                                                 uint32_t *__restrict__ counts, uint32_t n_tiles)
+                                                                 uint32_t *__restrict__ counts, uint32_t n_groups,
+                                                                 uint32_t tiles_per_group)
 {
     __shared__ uint32_t h[kMaxDigits];
     for (uint32_t i = threadIdx.x; i < n_digits; i += kPartThreads)
         h[i] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kPartTile;
+    const uint64_t base = (uint64_t)blockIdx.x * tiles_per_group * kPartTile;
+    const uint32_t rounds = kPartPerLane * tiles_per_group;
 #pragma unroll 8
-    for (int r = 0; r < kPartPerLane; ++r) {
+    for (uint32_t r = 0; r < rounds; ++r) {
         const uint64_t idx = base + (uint64_t)r * kPartThreads + threadIdx.x;
         if (idx < n)
             atomicAdd(&h[dg.of<MODE>(keys[idx])], 1u);
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < n_digits; i += kPartThreads)
-        counts[(uint64_t)i * n_tiles + blockIdx.x] = h[i];
+        counts[(uint64_t)i * n_groups + blockIdx.x] = h[i];
 }
 
 // Exclusive scan of uint32 counts in three launches: block sums, a scan of
@@ -176,19 +183,21 @@ __global__ __launch_bounds__(kScanThreads) void scan_apply_kernel(uint32_t *__re
     }
 }
 
-// Stable scatter of one tile. Wavefront w owns the tile's keys
-// [w*1024, (w+1)*1024), lane l round r takes key w*1024 + 64r + l, so key
-// order is (w, r, l). 1) per-wavefront digit counts; 2) where each
+// Stable scatter of one group of tiles, tile after tile. The scan gives the
+// group's run start for each digit; each tile takes the current start and
+// moves it past its own keys of that digit. Inside a tile, wavefront w owns
+// the keys [w*1024, (w+1)*1024), lane l round r takes key w*1024 + 64r + l,
+// so key order is (w, r, l). 1) per-wavefront digit counts; 2) where each
 // (wavefront, digit) run starts inside the tile's staging area; 3) every
 // round ranks its keys among equal digits of the round (ballot matching)
 // and stages them; 4) the staged tile, now ordered by digit, is written to
-// the digit runs the scan assigned to this tile.
+// the tile's digit runs.
 template <int MODE>
 __global__ __launch_bounds__(kPartThreads) void bulk_scatter_kernel(const uint64_t *__restrict__ in,
                                                                     uint64_t *__restrict__ out, uint64_t n, Digit dg,
                                                                     uint32_t n_digits,
                                                                     const uint32_t *__restrict__ offsets,
-                                                                    uint32_t n_tiles)
+                                                                    uint32_t n_groups, uint32_t tiles_per_group)
 {
     extern __shared__ uint64_t staged[]; // kPartTile keys
     __shared__ uint32_t wcnt[kPartThreads / kWave][kMaxDigits];
@@ -197,87 +206,103 @@ __global__ __launch_bounds__(kPartThreads) void bulk_scatter_kernel(const uint64
     __shared__ uint32_t scan_sh[kPartThreads];
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t w = threadIdx.x / kWave;
-    const uint64_t tile_base = (uint64_t)blockIdx.x * kPartTile;
-    const uint64_t wave_base = tile_base + (uint64_t)w * kPartWaveKeys;
-
-    uint64_t key[kPartPerLane];
-#pragma unroll
-    for (int r = 0; r < kPartPerLane; ++r) {
-        const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
-        key[r] = idx < n ? in[idx] : 0;
-    }
-    for (uint32_t d = lane; d < n_digits; d += kWave)
-        wcnt[w][d] = 0;
-    wave_sync();
-#pragma unroll
-    for (int r = 0; r < kPartPerLane; ++r) {
-        const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
-        if (idx < n)
-            atomicAdd(&wcnt[w][dg.of<MODE>(key[r])], 1u);
-    }
-    __syncthreads();
-
-    // digit totals of the tile, their exclusive prefix, and the per-wavefront
-    // run starts (digits d = t and t + 256 for thread t)
-    uint32_t tot[2] = {0, 0};
+    // thread t owns digits t and t + 256: its running output position for each
+    uint32_t run_at[2] = {0, 0};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint32_t d = threadIdx.x + h * kPartThreads;
         if (d < n_digits)
-            for (int ww = 0; ww < kPartThreads / kWave; ++ww)
-                tot[h] += wcnt[ww][d];
+            run_at[h] = offsets[(uint64_t)d * n_groups + blockIdx.x];
     }
-    uint32_t total0;
-    const uint32_t pre0 = block_exclusive_scan(tot[0], scan_sh, total0);
-    uint32_t total1;
-    const uint32_t pre1 = block_exclusive_scan(tot[1], scan_sh, total1) + total0;
+    for (uint32_t tg = 0; tg < tiles_per_group; ++tg) {
+        const uint64_t tile_base = ((uint64_t)blockIdx.x * tiles_per_group + tg) * kPartTile;
+        if (tile_base >= n)
+            break;
+        const uint64_t wave_base = tile_base + (uint64_t)w * kPartWaveKeys;
+
+        uint64_t key[kPartPerLane];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const uint32_t d = threadIdx.x + h * kPartThreads;
-        if (d < n_digits) {
-            uint32_t run = h == 0 ? pre0 : pre1;
-            tpre[d] = run;
-            gofs[d] = offsets[(uint64_t)d * n_tiles + blockIdx.x];
-            for (int ww = 0; ww < kPartThreads / kWave; ++ww) {
-                const uint32_t c = wcnt[ww][d];
-                wcnt[ww][d] = run;
-                run += c;
+        for (int r = 0; r < kPartPerLane; ++r) {
+            const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
+            key[r] = idx < n ? in[idx] : 0;
+        }
+        for (uint32_t d = lane; d < n_digits; d += kWave)
+            wcnt[w][d] = 0;
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < kPartPerLane; ++r) {
+            const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
+            if (idx < n)
+                atomicAdd(&wcnt[w][dg.of<MODE>(key[r])], 1u);
+        }
+        __syncthreads();
+
+        // digit totals of the tile, their exclusive prefix, and the per-wavefront
+        // run starts (digits d = t and t + 256 for thread t)
+        uint32_t tot[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t d = threadIdx.x + h * kPartThreads;
+            if (d < n_digits)
+                for (int ww = 0; ww < kPartThreads / kWave; ++ww)
+                    tot[h] += wcnt[ww][d];
+        }
+        uint32_t total0;
+        const uint32_t pre0 = block_exclusive_scan(tot[0], scan_sh, total0);
+        uint32_t total1;
+        const uint32_t pre1 = block_exclusive_scan(tot[1], scan_sh, total1) + total0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t d = threadIdx.x + h * kPartThreads;
+            if (d < n_digits) {
+                uint32_t run = h == 0 ? pre0 : pre1;
+                tpre[d] = run;
+                gofs[d] = run_at[h];
+                run_at[h] += tot[h];
+                for (int ww = 0; ww < kPartThreads / kWave; ++ww) {
+                    const uint32_t c = wcnt[ww][d];
+                    wcnt[ww][d] = run;
+                    run += c;
+                }
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    static_for(
-        [&](auto rc) __attribute__((always_inline)) {
-            constexpr int r = decltype(rc)::value;
-            const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
-            const bool valid = idx < n;
-            const uint32_t d = valid ? dg.of<MODE>(key[r]) : 0;
-            uint64_t peers = __ballot(valid);
+        static_for(
+            [&](auto rc) __attribute__((always_inline)) {
+                constexpr int r = decltype(rc)::value;
+                const uint64_t idx = wave_base + (uint64_t)r * kWave + lane;
+                const bool valid = idx < n;
+                const uint32_t d = valid ? dg.of<MODE>(key[r]) : 0;
+                uint64_t peers = __ballot(valid);
 #pragma unroll
-            for (int b = 0; b < kMaxDigitBits; ++b) { // bits above the digit are zero in every lane
-                const uint64_t m = __ballot((d >> b) & 1);
-                peers &= ((d >> b) & 1) ? m : ~m;
-            }
-            if (valid) {
-                const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt(lane));
-                const uint32_t pos = wcnt[w][d] + rank;
-                staged[pos] = key[r];
-            }
-            wave_sync(); // every lane has read its run start before the leader moves it
-            if (valid && (peers & lanemask_lt(lane)) == 0)
-                wcnt[w][d] += (uint32_t)__popcll(peers);
-            wave_sync();
-        },
-        std::make_integer_sequence<int, kPartPerLane>{});
-    __syncthreads();
+                for (int b = 0; b < kMaxDigitBits; ++b) { // bits above the digit are zero in every lane
+                    const uint64_t m = __ballot((d >> b) & 1);
+                    peers &= ((d >> b) & 1) ? m : ~m;
+                }
+                if (valid) {
+                    const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt(lane));
+                    const uint32_t pos = wcnt[w][d] + rank;
+                    staged[pos] = key[r];
+                }
+                wave_sync(); // every lane has read its run start before the leader moves it
+                if (valid && (peers & lanemask_lt(lane)) == 0)
+                    wcnt[w][d] += (uint32_t)__popcll(peers);
+                wave_sync();
+            },
+            std::make_integer_sequence<int, kPartPerLane>{});
+        __syncthreads();
 
-    const uint64_t left = n - tile_base;
-    const uint32_t in_tile = left < (uint64_t)kPartTile ? (uint32_t)left : (uint32_t)kPartTile;
-    for (uint32_t i = threadIdx.x; i < in_tile; i += kPartThreads) {
-        const uint64_t x = staged[i];
-        const uint32_t d = dg.of<MODE>(x);
-        out[(uint64_t)gofs[d] + (i - tpre[d])] = x;
+        const uint64_t left = n - tile_base;
+        const uint32_t in_tile = left < (uint64_t)kPartTile ? (uint32_t)left : (uint32_t)kPartTile;
+        for (uint32_t i = threadIdx.x; i < in_tile; i += kPartThreads) {
+            const uint64_t x = staged[i];
+            const uint32_t d = dg.of<MODE>(x);
+            const uint64_t at = (uint64_t)gofs[d] + (uint32_t)(i - tpre[d]);
+            if (at < n) // always true for consistent counts; keeps a stray index inside the buffer
+                out[at] = x;
+        }
+        __syncthreads(); // the next tile reuses the staging, counts and run starts
     }
 }
 
@@ -521,8 +546,9 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
 struct Plan {
     uint32_t passes = 0;
     uint32_t bits[3] = {0, 0, 0};
-    uint64_t n_tiles = 0;
-    uint64_t counts_len = 0; // max over passes of n_digits * n_tiles
+    uint32_t tiles_per_group = 1;
+    uint64_t n_groups = 0;   // groups of tiles_per_group tiles (the counted unit)
+    uint64_t counts_len = 0; // max over passes of n_digits * n_groups
     uint64_t n_scan_blocks = 0;
     int sub_max = 0;         // LDS sub-array capacity in blocks
     // workspace layout (bytes, 256-aligned)
@@ -552,11 +578,14 @@ Plan make_plan(const bbfc_filter &f, uint64_t n)
     for (uint32_t q = 0; q < pl.passes; ++q) { // spread the bits evenly over the passes
         pl.bits[q] = tbits / pl.passes + (q < tbits % pl.passes ? 1 : 0);
     }
-    pl.n_tiles = (n + kPartTile - 1) / kPartTile;
+    const uint64_t n_tiles = (n + kPartTile - 1) / kPartTile;
+    const uint64_t tpg = n_tiles / 2048;
+    pl.tiles_per_group = tpg < 1 ? 1 : (tpg > kMaxTilesPerGroup ? kMaxTilesPerGroup : (uint32_t)tpg);
+    pl.n_groups = (n_tiles + pl.tiles_per_group - 1) / pl.tiles_per_group;
     uint32_t max_bits = 0;
     for (uint32_t q = 0; q < pl.passes; ++q)
         max_bits = pl.bits[q] > max_bits ? pl.bits[q] : max_bits;
-    pl.counts_len = ((uint64_t)1 << max_bits) * pl.n_tiles;
+    pl.counts_len = ((uint64_t)1 << max_bits) * pl.n_groups;
     pl.n_scan_blocks = (pl.counts_len + kScanBlock - 1) / kScanBlock;
     pl.sub_max = sub_capacity(f.S);
     uint64_t at = 0;
@@ -622,51 +651,51 @@ hipError_t launch_insert_c(const bbfc_filter &f, int sub_max, const uint64_t *so
 }
 
 template <int MODE>
-hipError_t launch_hist_m(uint32_t n_tiles, hipStream_t s, const uint64_t *src, uint64_t n, const Digit &dg,
+hipError_t launch_hist_m(uint32_t n_groups, uint32_t tpg, hipStream_t s, const uint64_t *src, uint64_t n, const Digit &dg,
                          uint32_t n_digits, uint32_t *counts)
 {
-    hipLaunchKernelGGL(bulk_hist_kernel<MODE>, dim3(n_tiles), dim3(kPartThreads), 0, s, src, n, dg, n_digits, counts,
-                       n_tiles);
+    hipLaunchKernelGGL(bulk_hist_kernel<MODE>, dim3(n_groups), dim3(kPartThreads), 0, s, src, n, dg, n_digits, counts,
+                       n_groups, tpg);
     return hipGetLastError();
 }
 
-hipError_t launch_hist(uint32_t mode, uint32_t n_tiles, hipStream_t s, const uint64_t *src, uint64_t n,
+hipError_t launch_hist(uint32_t mode, uint32_t n_groups, uint32_t tpg, hipStream_t s, const uint64_t *src, uint64_t n,
                        const Digit &dg, uint32_t n_digits, uint32_t *counts)
 {
     switch (mode) {
     case kModePow2:
-        return launch_hist_m<kModePow2>(n_tiles, s, src, n, dg, n_digits, counts);
+        return launch_hist_m<kModePow2>(n_groups, tpg, s, src, n, dg, n_digits, counts);
     case kModeEven:
-        return launch_hist_m<kModeEven>(n_tiles, s, src, n, dg, n_digits, counts);
+        return launch_hist_m<kModeEven>(n_groups, tpg, s, src, n, dg, n_digits, counts);
     default:
-        return launch_hist_m<kModeOdd>(n_tiles, s, src, n, dg, n_digits, counts);
+        return launch_hist_m<kModeOdd>(n_groups, tpg, s, src, n, dg, n_digits, counts);
     }
 }
 
 template <int MODE>
-hipError_t launch_scatter_m(uint32_t n_tiles, hipStream_t s, const uint64_t *src, uint64_t *dst, uint64_t n,
+hipError_t launch_scatter_m(uint32_t n_groups, uint32_t tpg, hipStream_t s, const uint64_t *src, uint64_t *dst, uint64_t n,
                             const Digit &dg, uint32_t n_digits, const uint32_t *offsets)
 {
     hipError_t e = hipFuncSetAttribute((const void *)bulk_scatter_kernel<MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kPartTile * 8);
     if (e != hipSuccess)
         return e;
-    hipLaunchKernelGGL(bulk_scatter_kernel<MODE>, dim3(n_tiles), dim3(kPartThreads), kPartTile * 8, s, src, dst, n,
-                       dg, n_digits, offsets, n_tiles);
+    hipLaunchKernelGGL(bulk_scatter_kernel<MODE>, dim3(n_groups), dim3(kPartThreads), kPartTile * 8, s, src, dst, n,
+                       dg, n_digits, offsets, n_groups, tpg);
     return hipGetLastError();
 }
 
 // Radix passes run only with T > 1 sub-arrays, so the mode of T is never One.
-hipError_t launch_scatter(uint32_t mode, uint32_t n_tiles, hipStream_t s, const uint64_t *src, uint64_t *dst,
+hipError_t launch_scatter(uint32_t mode, uint32_t n_groups, uint32_t tpg, hipStream_t s, const uint64_t *src, uint64_t *dst,
                           uint64_t n, const Digit &dg, uint32_t n_digits, const uint32_t *offsets)
 {
     switch (mode) {
     case kModePow2:
-        return launch_scatter_m<kModePow2>(n_tiles, s, src, dst, n, dg, n_digits, offsets);
+        return launch_scatter_m<kModePow2>(n_groups, tpg, s, src, dst, n, dg, n_digits, offsets);
     case kModeEven:
-        return launch_scatter_m<kModeEven>(n_tiles, s, src, dst, n, dg, n_digits, offsets);
+        return launch_scatter_m<kModeEven>(n_groups, tpg, s, src, dst, n, dg, n_digits, offsets);
     default:
-        return launch_scatter_m<kModeOdd>(n_tiles, s, src, dst, n, dg, n_digits, offsets);
+        return launch_scatter_m<kModeOdd>(n_groups, tpg, s, src, dst, n, dg, n_digits, offsets);
     }
 }
 
@@ -702,10 +731,11 @@ hipError_t launch_bulk_insert(const bbfc_filter &f, const uint64_t *keys, uint64
         dg.shift = shift;
         dg.mask = (1u << pl.bits[q]) - 1;
         const uint32_t n_digits = 1u << pl.bits[q];
-        const uint64_t len = (uint64_t)n_digits * pl.n_tiles;
+        const uint64_t len = (uint64_t)n_digits * pl.n_groups;
         const uint64_t n_blocks = (len + kScanBlock - 1) / kScanBlock;
         uint64_t *dst = bufs[q & 1];
-        hipError_t e = launch_hist(f.sub.mode, (uint32_t)pl.n_tiles, s, src, n, dg, n_digits, counts);
+        hipError_t e = launch_hist(f.sub.mode, (uint32_t)pl.n_groups, pl.tiles_per_group, s, src, n, dg, n_digits,
+                                   counts);
         if (e != hipSuccess)
             return e;
         hipLaunchKernelGGL(scan_reduce_kernel, dim3((uint32_t)n_blocks), dim3(kScanThreads), 0, s, counts, len,
@@ -714,7 +744,8 @@ hipError_t launch_bulk_insert(const bbfc_filter &f, const uint64_t *keys, uint64
                            (uint32_t)n_blocks);
         hipLaunchKernelGGL(scan_apply_kernel, dim3((uint32_t)n_blocks), dim3(kScanThreads), 0, s, counts, len,
                            partial);
-        e = launch_scatter(f.sub.mode, (uint32_t)pl.n_tiles, s, src, dst, n, dg, n_digits, counts);
+        e = launch_scatter(f.sub.mode, (uint32_t)pl.n_groups, pl.tiles_per_group, s, src, dst, n, dg, n_digits,
+                           counts);
         if (e != hipSuccess)
             return e;
         src = dst;

@@ -6,7 +6,8 @@
 * the bulk insert (stable partition by h_0, one wavefront per sub-array in
   LDS) bit-exact with the oracle's sequential build for every hash case of
   T and S, one to three radix passes, ragged sizes, repeated keys, distinct
-  bits, c = 1..4, and over several calls;
+  bits, c = 1..4, partition counts per tile and per group of tiles, and
+  over several calls;
 * at 2^26 keys, sampled sub-arrays of the GPU build equal the oracle's
   build of the keys h_0 sends to them, and every key answers true.
 """
@@ -114,6 +115,7 @@ BULK = [
     (512 * 300, 300, 2, 32, "exp", True, 512 * 300 * 10),       # k = 32, distinct
     (256, 256, 2, 5, "la", False, 1),
     (256, 256, 2, 5, "la", False, 65),
+    (1 << 19, 1 << 11, 2, 11, "la", False, 2 * 2048 * 4096 + 12345),  # partition counts groups of 2 tiles
 ]
 
 
