@@ -3,7 +3,9 @@
 * a filter of 2^30 + 1 blocks (64 GiB, odd M): the deterministic insert's
   touched blocks equal the oracle's word for word (read back block by block),
   and queries match the oracle bit for bit;
-* one query call of 2^32 + 2^16 keys: the answers past index 2^32 are right.
+* one query call of 2^32 + 2^16 keys: the answers past index 2^32 are right;
+* one bulk insert call of more than 2^31 keys (split into pieces): sampled
+  sub-arrays equal the oracle's sequential build.
 The oracle's filter array is allocated lazily by the OS, so only the touched
 blocks take host memory.
 """
@@ -96,5 +98,44 @@ def test_query_call_beyond_2_pow_32_keys(dev):
         fpr = ones / float(1 << 32)
         print(f"FPR of 2^32 negatives on a 2^16-key, 2^20-block filter: {fpr:.3e}", flush=True)
         assert fpr < 1e-6
+    finally:
+        f.close()
+
+
+def test_bulk_insert_beyond_2_pow_31_keys(dev):
+    """One bulk insert call of 2^31 + 2^20 + 7 keys, which the library splits
+    into pieces of at most 2^31 keys (32-bit offsets inside a piece), into
+    2^14 sub-arrays of 256 blocks: every key answers true, and four sampled
+    sub-arrays equal the oracle's build of exactly the keys h_0 routes there,
+    in index order, across the piece boundary."""
+    n = (1 << 31) + (1 << 20) + 7
+    T, S = 1 << 14, 256
+    M = T * S
+    f = bbfc.Filter(M, 2, 11, "la", seed=13, subarrays=T)
+    try:
+        keys = workload.device_keys(13, 0, n, device=dev)
+        f.bulk_insert(keys)
+        hits = f.query(keys)
+        torch.cuda.synchronize()
+        full = n // 64
+        assert bool(torch.all(hits[:full] == -1)), "an inserted key answered false"
+        assert bbfc.unpack_bits(hits[full:].cpu().numpy(), n - full * 64).all()
+        del hits
+        words = f.download()
+        sm = f.params.sub_mult
+        # the paper's h_0 for T = 2^14: the top 14 bits of sub_mult * x mod 2^64
+        sm_signed = sm - (1 << 64) if sm >= (1 << 63) else sm
+        h0 = ((keys * sm_signed) >> 50) & (T - 1)
+        rng = np.random.default_rng(13)
+        for v in rng.choice(T, size=4, replace=False):
+            # masked selection in chunks below 2^31 elements, in index order
+            mine = np.concatenate([part[hp == int(v)].cpu().numpy().view(np.uint64)
+                                   for part, hp in zip(torch.split(keys, 1 << 30), torch.split(h0, 1 << 30))])
+            assert len(mine) > 100_000
+            ref = oracle.OracleFilter(S, 2, 11, oracle.COST_LA, None, list(f.params.block_mult),
+                                      list(f.params.bit_mult))
+            ref.insert(mine)
+            assert np.array_equal(words[8 * S * int(v):8 * S * (int(v) + 1)], ref.words), int(v)
+        del keys, h0
     finally:
         f.close()
