@@ -51,6 +51,7 @@ constexpr int kScanPerThread = 16;
 constexpr int kScanBlock = kScanThreads * kScanPerThread; // 4096 counts per scan block
 constexpr int kScanTopThreads = 1024;
 constexpr int kClaimSlots = 256;                          // hashed claim table entries per wavefront
+constexpr int kBulkSlotDw = 16;                           // LDS dwords per key mask in the bulk insert
 
 // One radix digit of h_0: (h_0(x) >> shift) & mask; MODE is the hash mode
 // of the number of sub-arrays, fixed per launch.
@@ -308,12 +309,14 @@ __global__ __launch_bounds__(kPartThreads) void bulk_scatter_kernel(const uint64
 
 // --------------------------------------------------------------- insert
 
-// LDS of one wavefront of the insert kernel.
+// LDS of one wavefront of the insert kernel. Every byte counts: the
+// wavefronts that fit in a CU's LDS next to the rank table set how much
+// latency is hidden (at k = 11 and S = 256: seven).
 template <int SUB, int C>
 struct WaveLds {
     static constexpr size_t kSub = (size_t)SUB * 64;                    // the staged sub-array
-    static constexpr size_t kSlots = (size_t)kTile * kSlotDw * 4;       // key masks
-    static constexpr size_t kClaim = (size_t)kClaimSlots * 8;          // claim bits
+    static constexpr size_t kSlots = (size_t)kTile * kBulkSlotDw * 4;   // key masks
+    static constexpr size_t kClaim = (size_t)kClaimSlots * 4;          // claim bits of 32 lanes
     static constexpr size_t kBytes = kSub + kSlots + kClaim;
 };
 
@@ -358,7 +361,7 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
     uint8_t *mine = lds + rank_bytes + (size_t)wv * WL::kBytes;
     uint64_t *sub = reinterpret_cast<uint64_t *>(mine);
     uint32_t *smask = reinterpret_cast<uint32_t *>(mine + WL::kSub);
-    uint64_t *claim = reinterpret_cast<uint64_t *>(mine + WL::kSub + WL::kSlots);
+    uint32_t *claim = reinterpret_cast<uint32_t *>(mine + WL::kSub + WL::kSlots);
     for (int i = lane; i < kClaimSlots; i += kWave)
         claim[i] = 0;
 
@@ -427,7 +430,7 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
             }
 
             // key masks into LDS slots, candidate blocks (inside the sub-array) in registers
-            uint32_t *slot = smask + lane * kSlotDw;
+            uint32_t *slot = smask + lane * kBulkSlotDw;
 #pragma unroll
             for (int d = 0; d < 16; d += 2)
                 *reinterpret_cast<uint2 *>(slot + d) = make_uint2(0, 0);
@@ -452,24 +455,34 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
 
             // P: earlier keys of the same 8-key round that share a candidate
             // (claim bits hashed into kClaimSlots entries; a collision only
-            // splits a window)
-            if (valid) {
-#pragma unroll
-                for (int i = 0; i < C; ++i)
-                    atomicOr((unsigned long long *)&claim[cand[i] % kClaimSlots], 1ull << lane);
-            }
-            wave_sync();
+            // splits a window). A round never spans the two halves of the
+            // wavefront, so each half claims in turn with 32-bit entries.
             uint64_t P = 0;
 #pragma unroll
-            for (int i = 0; i < C; ++i)
-                P |= claim[cand[i] % kClaimSlots];
-            P &= lanemask_lt(lane) & ~lanemask_lt(lane & ~7u);
-            wave_sync();
-            if (valid) {
+            for (uint32_t half = 0; half < 2; ++half) {
+                const bool mine_half = (lane >> 5) == half;
+                if (valid && mine_half) {
 #pragma unroll
-                for (int i = 0; i < C; ++i)
-                    claim[cand[i] % kClaimSlots] = 0;
+                    for (int i = 0; i < C; ++i)
+                        atomicOr(&claim[cand[i] % kClaimSlots], 1u << (lane & 31));
+                }
+                wave_sync();
+                if (mine_half) {
+                    uint32_t q = 0;
+#pragma unroll
+                    for (int i = 0; i < C; ++i)
+                        q |= claim[cand[i] % kClaimSlots];
+                    P = (uint64_t)q << (32 * half);
+                }
+                wave_sync();
+                if (valid && mine_half) {
+#pragma unroll
+                    for (int i = 0; i < C; ++i)
+                        claim[cand[i] % kClaimSlots] = 0;
+                }
+                wave_sync();
             }
+            P &= lanemask_lt(lane) & ~lanemask_lt(lane & ~7u);
 
             // Round r takes keys 8r..8r+7, group g key 8r+g: its candidates
             // and its mask word w0, fetched for all rounds before any round runs.
@@ -481,7 +494,7 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
 #pragma unroll
                 for (int i = 0; i < C; ++i)
                     rc[r][i] = (uint32_t)__shfl((int)cand[i], src);
-                const uint32_t *ks = smask + src * kSlotDw + 2 * w0;
+                const uint32_t *ks = smask + src * kBulkSlotDw + 2 * w0;
                 mw[r] = *reinterpret_cast<const uint64_t *>(ks);
             }
 
