@@ -242,6 +242,90 @@ def cpu_baseline(n_blocks, c, k, target_s, distinct=False, subarrays=1):
     }
 
 
+def cpu_baseline_batch(specs, target_s):
+    """The sequential oracle on a bounded sample of the batch workload: the
+    filters in order, each built from its own keys and queried with as many
+    never-inserted keys, until about target_s seconds of inserts."""
+    import oracle
+    import workload
+
+    t_ins = t_q = 0.0
+    n_ins = n_q = 0
+    used = 0
+    for f, (n, bits) in enumerate(specs):
+        k = int(round(bits * math.log(2)))
+        M = max(1, math.ceil(n * bits / 512))
+        ref = oracle.OracleFilter(M, 2, k, oracle.COST_EXP, None, seed=f)
+        keys = workload.splitmix64_keys(1000 + f, 0, 2 * n)
+        t = time.perf_counter()
+        ref.insert(keys[:n])
+        t_ins += time.perf_counter() - t
+        t = time.perf_counter()
+        ref.count_hits(keys)
+        t_q += time.perf_counter() - t
+        n_ins += n
+        n_q += 2 * n
+        used += 1
+        if t_ins + t_q >= target_s:
+            break
+    r_ins, r_q = n_ins / t_ins, n_q / t_q
+    return {
+        "value": round(3.0 / (1.0 / r_ins + 2.0 / r_q) / 1e6, 3),
+        "unit": "Mkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"sequential oracle, 1 thread: the first {used} of the {len(specs)} filters ({n_ins} inserts, "
+                   f"{n_q} queries), {t_ins + t_q:.1f} s; rates combined with the pass's 1 insert : 2 queries mix"),
+        "insert_mkeys_s": round(r_ins / 1e6, 3),
+        "query_mkeys_s": round(r_q / 1e6, 3),
+    }
+
+
+def cpu_baseline_kmer(M, k, genome_seed, n_genome_kmers, n_query_kmers, target_s):
+    """The sequential oracle on a bounded sample of the q-gram workload: the
+    canonical 31-mers of a prefix of the same genome (extraction included)
+    inserted into a filter of the same shape, then the 31-mers of as many
+    uniform random bases queried (extraction included)."""
+    import oracle
+    import workload
+
+    ref = oracle.OracleFilter(M, 3, k, oracle.COST_MIX, None, seed=0)
+    q = 31
+    bases_n = 1 << 20
+    total_ins = total_q = 0
+    t_ins = t_q = 0.0
+    start = 0
+    while t_ins < target_s / 2:
+        bases = workload.unpack_2bit(workload.splitmix64_keys(genome_seed, start // 32, bases_n // 32), bases_n)
+        t = time.perf_counter()
+        keys = oracle.qgrams(bases, 1, bases_n, q)
+        ref.insert(keys)
+        t_ins += time.perf_counter() - t
+        total_ins += len(keys)
+        start += bases_n
+    rnd_seed = 0
+    while t_q < target_s / 2:
+        bases = workload.random_bases(977 + rnd_seed, bases_n)
+        t = time.perf_counter()
+        ref.count_hits(oracle.qgrams(bases, 1, bases_n, q))
+        t_q += time.perf_counter() - t
+        total_q += bases_n - q + 1
+        rnd_seed += 1
+    r_ins, r_q = total_ins / t_ins, total_q / t_q
+    total = n_genome_kmers + n_query_kmers
+    return {
+        "value": round(total / (n_genome_kmers / r_ins + n_query_kmers / r_q) / 1e6, 3),
+        "unit": "Mkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"sequential oracle, 1 thread: q-gram extraction and insert of {total_ins} 31-mers of the same "
+                   f"genome's first {start} bases, extraction and query of {total_q} 31-mers of random bases, "
+                   f"{t_ins + t_q:.1f} s; rates combined with the step's insert : query mix"),
+        "insert_mkeys_s": round(r_ins / 1e6, 3),
+        "query_mkeys_s": round(r_q / 1e6, 3),
+    }
+
+
 def host_info() -> dict:
     model = ""
     try:
@@ -442,7 +526,7 @@ def bench_batch(args):
         "roofline": {"bound": "hbm", "kernel": f"batch_{dom}_kernel", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launch_ms": dom_ms},
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_batch(specs, args.cpu_seconds),
         "kernel_source_sha": kernel_source_sha(),
     }
     for fl in filters:
@@ -707,7 +791,7 @@ def bench_kmer(args):
         "roofline": {"bound": "hbm", "kernel": f"{dom}_kernel<3, ..., KmerKeys>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launch_ms": round(dom_ms, 3)},
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_kmer(M, args.kmer_k, 21, n_g, n_q, args.cpu_seconds),
         "kernel_source_sha": kernel_source_sha(),
     }
     filt.close()
