@@ -326,6 +326,21 @@ def cpu_baseline_kmer(M, k, genome_seed, n_genome_kmers, n_query_kmers, target_s
     }
 
 
+def cpu_baseline_serve(n_blocks, target_s):
+    """Queries only: the query legs of the plain workload's oracle sample
+    (half inserted, half never inserted keys on the same filter shape)."""
+    b = cpu_baseline(n_blocks, 2, 11, target_s)
+    return {
+        "value": b["query_mkeys_s"],
+        "unit": "Mkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": b["sample"] + "; value = the queries alone",
+        "query_threads": b["query_threads"],
+        "query_all_threads_mkeys_s": b["query_all_threads_mkeys_s"],
+    }
+
+
 def host_info() -> dict:
     model = ""
     try:
@@ -643,7 +658,7 @@ def bench_serve(args):
         "server_stats": stats,
         "zero_false_negatives": fn_free,
         "roofline": None,
-        "cpu_baseline": None,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_serve(n // 32, args.cpu_seconds),
         "kernel_source_sha": kernel_source_sha(),
     }
     filt.close()
