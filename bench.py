@@ -610,6 +610,9 @@ def bench_serve(args):
                 "p99_us": round(float(np.percentile(base_lat, 99)), 1)}
 
     srv = bbfc.Server(filt, n_slots=4, max_batch_keys=1 << 20, max_pending_keys=1 << 27)
+    # untimed warm-up: the first 1000 requests at once (worker threads, staging pages)
+    n_warm = min(1000, len(sizes))
+    srv.replay(flat[: int(offs[n_warm])], offs[: n_warm + 1], np.zeros(n_warm))
     loads = []
     rng = np.random.default_rng(5)
     best = None
