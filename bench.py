@@ -542,6 +542,7 @@ def bench_batch(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launch_ms": dom_ms},
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_batch(specs, args.cpu_seconds),
+        "host": host_info(),
         "kernel_source_sha": kernel_source_sha(),
     }
     for fl in filters:
@@ -660,6 +661,7 @@ def bench_serve(args):
         "zero_false_negatives": fn_free,
         "roofline": None,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_serve(n // 32, args.cpu_seconds),
+        "host": host_info(),
         "kernel_source_sha": kernel_source_sha(),
     }
     filt.close()
@@ -808,6 +810,7 @@ def bench_kmer(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "launch_ms": round(dom_ms, 3)},
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_kmer(M, args.kmer_k, 21, n_g, n_q, args.cpu_seconds),
+        "host": host_info(),
         "kernel_source_sha": kernel_source_sha(),
     }
     filt.close()
