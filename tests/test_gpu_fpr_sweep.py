@@ -82,3 +82,31 @@ def test_racing_fpr_distinct_and_subarrays(dev, distinct, sub):
         assert got == pytest.approx(want, rel=0.02)
     finally:
         f.close()
+
+
+def test_in_flight_cap_keeps_the_fpr(dev):
+    """The racing insert caps its keys in flight at M/32: a decision can miss
+    bits that in-flight keys are about to set, and with every key of the call
+    in flight at once the FPR rises well beyond the 2% tolerance. M = 2^15,
+    n = 2^20, k = 14, LA (16 bits per key)."""
+    M, n, k = 1 << 15, 1 << 20, 14
+    f = bbfc.Filter(M, 2, k, "la", seed=77)
+    try:
+        ref = oracle.OracleFilter(M, 2, k, oracle.COST_LA, None, list(f.params.block_mult), list(f.params.bit_mult))
+        keys_d = workload.device_keys(77, 0, n, device=dev)
+        ref.insert(from_dev(keys_d))
+        neg = workload.negative_keys(77, n, 1 << 20)
+        want = ref.conditional_fpr(neg)
+        got = {}
+        for cap in (0, 1 << 20):  # 0: the default, M/32
+            f.clear()
+            f.set_option(bbfc.OPT_INSERT_INFLIGHT, cap)
+            f.insert(keys_d)
+            got[cap] = ref.conditional_fpr(neg, words=f.download())
+            assert bbfc.unpack_bits(from_dev(f.query(keys_d)), n).all()
+        print(f"conditional FPR: sequential {want:.4e}, cap M/32 {got[0]:.4e}, all in flight {got[1 << 20]:.4e}",
+              flush=True)
+        assert got[0] == pytest.approx(want, rel=0.02)
+        assert got[1 << 20] > 1.05 * want
+    finally:
+        f.close()
