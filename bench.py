@@ -998,8 +998,10 @@ def main():
         probe = run_probes(stream, n_blocks, n, k)
         # Ceilings from the probe rates under the paper's access counts
         # (c = 2 random block reads per query; c reads plus one rewritten
-        # block, an atomic line, per insert): the query at R_read / c; the
-        # insert between reads and atomics serialised and fully overlapped.
+        # block, an atomic line, per insert): the query at R_read / c (all c
+        # blocks read; with early exit the query reads fewer, so its
+        # fraction can exceed 1); the insert between reads and atomics
+        # serialised and fully overlapped.
         r_read = probe["rand64_read_Glines_s"] * 1e3  # Mlines/s
         r_atom = probe["rand64_atomic_or_Glines_s"] * 1e3
         q_ceil = r_read / c
