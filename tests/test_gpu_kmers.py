@@ -51,8 +51,9 @@ def test_extraction_matches_oracle(dev, q, n_seg, seg_len):
     assert np.array_equal(got[:len(want)], want)
 
 
+@pytest.mark.parametrize("shape", [(8, 1), (8, 2), (4, 1), (4, 2)])
 @pytest.mark.parametrize("c,cost", [(3, "mix"), (2, "la"), (1, "none")])
-def test_fused_query_matches_oracle(dev, c, cost):
+def test_fused_query_matches_oracle(dev, c, cost, shape):
     q = 31
     genome = workload.random_bases(11, 200_000)
     gkeys = oracle.qgrams(genome, 1, len(genome), q)
@@ -63,6 +64,7 @@ def test_fused_query_matches_oracle(dev, c, cost):
     ref.insert(gkeys)
     f = bbfc.Filter(M, c, 8, cost, block_mult=bm, bit_mult=am)
     try:
+        f.set_shape(bbfc.OP_QUERY, *shape)
         f.upload(ref.words)
         # reads: copies of genome windows (positives) and random sequence
         starts = np.random.default_rng(1).integers(0, len(genome) - 150, size=300)
@@ -75,8 +77,9 @@ def test_fused_query_matches_oracle(dev, c, cost):
         f.close()
 
 
+@pytest.mark.parametrize("shape", [(8, 1), (4, 2)])
 @pytest.mark.parametrize("c,cost", [(1, "none"), (3, "mix")])
-def test_fused_insert(dev, c, cost):
+def test_fused_insert(dev, c, cost, shape):
     q = 31
     genome = workload.random_bases(21, 300_000)
     gkeys = oracle.qgrams(genome, 1, len(genome), q)
@@ -86,6 +89,7 @@ def test_fused_insert(dev, c, cost):
     ref = oracle.OracleFilter(M, c, 8, oracle.COST_NAMES[cost], None, bm, am)
     f = bbfc.Filter(M, c, 8, cost, block_mult=bm, bit_mult=am)
     try:
+        f.set_shape(bbfc.OP_INSERT, *shape)
         seq = to_dev(workload.pack_2bit(genome), dev)
         f.insert_kmers(seq, 1, len(genome), q)
         words = f.download()
