@@ -340,3 +340,28 @@ def test_probes_run(dev):
         bbfc.probe_copy(src[:1000], d64[:1000], request_bytes=64)
     with pytest.raises(bbfc.BBFCError):
         bbfc.probe_copy(src, d64, request_bytes=32)
+
+
+def test_query_concurrent_with_insert_sees_a_subset(dev):
+    """An insert and a query of the same filter on two streams at once: bits
+    are only ever set, so every answer of the concurrent query is also an
+    answer of a query after the insert (the concurrent one sees some subset
+    of the in-flight insert), and the later query has no false negatives."""
+    M, n = 1 << 16, 1 << 21
+    gpu = bbfc.Filter(M, 2, 11, "la", seed=31)
+    try:
+        keys = workload.device_keys(31, 0, 2 * n, device=dev)  # n inserted, n never inserted
+        s_ins, s_q = torch.cuda.Stream(), torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s_ins):
+            gpu.insert(keys[:n])
+        with torch.cuda.stream(s_q):
+            during = gpu.query(keys)
+        torch.cuda.synchronize()
+        after = gpu.query(keys)
+        torch.cuda.synchronize()
+        d, a = from_dev(during), from_dev(after)
+        assert not np.any(d & ~a), "the concurrent query saw a bit the finished filter does not have"
+        assert bbfc.unpack_bits(a, 2 * n)[:n].all()
+    finally:
+        gpu.close()
