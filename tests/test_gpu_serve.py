@@ -181,3 +181,32 @@ def test_wait_unknown_ticket(served):
             srv.wait(12345)
     finally:
         srv.close()
+
+
+def test_serving_while_inserting(dev):
+    """Requests served while an insert into the same filter runs on another
+    stream: every served answer is also an answer after the insert (bits are
+    only set), and after it every inserted key answers true."""
+    M, n = 1 << 16, 1 << 21
+    f = bbfc.Filter(M, 2, 11, "la", seed=41)
+    srv = bbfc.Server(f, n_slots=4, max_batch_keys=1 << 16)
+    try:
+        keys_d = workload.device_keys(41, 0, n, device=dev)
+        torch.cuda.synchronize()
+        host = keys_d.cpu().numpy().view(np.uint64)
+        reqs = [host[i * 50_000:(i + 1) * 50_000] for i in range(20)]
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            f.insert(keys_d)
+        tickets = [srv.submit(r) for r in reqs]
+        during = [srv.wait(t)[0].copy() for t in tickets]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(r) for r in reqs]
+        after = [srv.wait(t)[0].copy() for t in tickets]
+    finally:
+        srv.close()
+        f.close()
+    for r, d, a in zip(reqs, during, after):
+        assert not np.any(d & ~a)
+        assert bbfc.unpack_bits(a, len(r)).all()
