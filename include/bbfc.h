@@ -22,6 +22,7 @@
  *     hipFree in destroy). The caller owns key and output buffers, which are
  *     device pointers on the filter's device and must stay valid until the
  *     stream has executed the work that reads or writes them.
+ *   - A call takes at most 2^56 keys (BBFC_EINVAL beyond).
  *   - Keys are 64-bit unsigned integers, hashed as u = 64-bit words
  *     (Section 3.4) whatever their meaningful width (a canonical 31-mer
  *     uses 62 bits).

@@ -90,6 +90,10 @@ bool is_pow2(uint64_t v) { return v != 0 && (v & (v - 1)) == 0; }
 // Keys per bulk-insert launch (offsets inside a launch are 32-bit).
 constexpr uint64_t kBulkPiece = 1ull << 31;
 
+// Keys per call: 2^56 keys are 512 PiB, far beyond any device; the bound
+// keeps every byte and tile count of a call free of 64-bit overflow.
+constexpr uint64_t kMaxKeys = 1ull << 56;
+
 // The paper's parameter values: sigma (MIX) is printed for k = 7 (2.5) and
 // k = 14 (50) in App. C; other k take the value of the nearer printed k.
 // mu = 3.5 (App. C); beta = golden ratio (Section 4, App. C).
@@ -373,6 +377,8 @@ bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipSt
         return BBFC_OK;
     if (d_keys == nullptr)
         return fail(BBFC_EINVAL, "null keys with n = %llu", (unsigned long long)n);
+    if (n > kMaxKeys)
+        return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
     DeviceGuard guard(h->device);
     hipError_t e = bbfc::launch_insert(*h, d_keys, n, stream);
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching insert");
@@ -386,6 +392,8 @@ bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uin
         return BBFC_OK;
     if (d_keys == nullptr)
         return fail(BBFC_EINVAL, "null keys with n = %llu", (unsigned long long)n);
+    if (n > kMaxKeys)
+        return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
     DeviceGuard guard(h->device);
     hipError_t e = bbfc::launch_insert_det(*h, d_keys, n, stream);
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching deterministic insert");
@@ -399,6 +407,8 @@ bbfc_status bbfc_query(bbfc_handle h, const uint64_t *d_keys, uint64_t n, uint64
         return BBFC_OK;
     if (d_keys == nullptr || d_out_bits == nullptr)
         return fail(BBFC_EINVAL, "null keys or output with n = %llu", (unsigned long long)n);
+    if (n > kMaxKeys)
+        return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
     const uintptr_t k0 = (uintptr_t)d_keys, k1 = k0 + n * 8;
     const uintptr_t o0 = (uintptr_t)d_out_bits, o1 = o0 + ((n + 63) / 64) * 8;
     if (k0 < o1 && o0 < k1)
@@ -560,6 +570,8 @@ bbfc_status bbfc_bulk_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, 
         return BBFC_OK;
     if (d_keys == nullptr)
         return fail(BBFC_EINVAL, "null keys");
+    if (n > kMaxKeys)
+        return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
     uint64_t need = 0;
     bbfc_status st = bbfc_bulk_insert_workspace(h, n, &need);
     if (st != BBFC_OK)
@@ -671,6 +683,8 @@ bbfc_status bbfc_tune(bbfc_handle h, int32_t op, const uint64_t *d_keys, uint64_
 {
     if (h == nullptr || d_keys == nullptr || n == 0 || (op == BBFC_OP_QUERY && d_out_bits == nullptr))
         return fail(BBFC_EINVAL, "null handle, keys or output, or no keys");
+    if (n > kMaxKeys)
+        return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
     if (op != BBFC_OP_INSERT && op != BBFC_OP_QUERY)
         return fail(BBFC_EINVAL, "op must be BBFC_OP_INSERT or BBFC_OP_QUERY");
     if (reps == 0)

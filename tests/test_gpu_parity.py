@@ -301,6 +301,24 @@ def test_option_validation(dev):
         gpu.close()
 
 
+def test_key_count_bound(dev):
+    """More than 2^56 keys in one call is an argument error, caught before
+    anything is launched (the library never reads the buffers here)."""
+    lib = bbfc.lib()
+    gpu = bbfc.Filter(64, 2, 8, "la", seed=1, subarrays=2)
+    try:
+        buf = torch.zeros(64, dtype=torch.int64, device=dev)
+        big = (1 << 56) + 1
+        assert lib.bbfc_insert(gpu.handle, buf.data_ptr(), big, None) == -1
+        assert lib.bbfc_insert_deterministic(gpu.handle, buf.data_ptr(), big, None) == -1
+        assert lib.bbfc_query(gpu.handle, buf.data_ptr(), big, buf[32:].data_ptr(), None) == -1
+        assert lib.bbfc_bulk_insert(gpu.handle, buf.data_ptr(), big, buf.data_ptr(), 8, None) == -1
+        assert b"2^56" in lib.bbfc_last_error()
+        torch.cuda.synchronize()
+    finally:
+        gpu.close()
+
+
 def test_overlapping_output_rejected(dev):
     gpu = bbfc.Filter(64, 2, 8, "la", seed=1)
     try:
