@@ -439,8 +439,9 @@ typedef struct bbfc_server *bbfc_server_handle;
  *     64..2^30; pinned host and device memory of 8 bytes per key plus
  *     answers is allocated per slot); max_pending_keys: admission limit on
  *     keys submitted but not yet staged (a request is still admitted when
- *     nothing is pending, whatever its size); poll_us: period at which a slot's
- *     worker polls its batch for completion (0: yield between polls). Defaults (config == NULL): 4 slots,
+ *     nothing is pending, whatever its size); poll_us: a slot's worker polls
+ *     its batch for completion, yielding between polls for the first 1 ms
+ *     and then sleeping poll_us between polls (0: yielding throughout). Defaults (config == NULL): 4 slots,
  *     2^20 keys per batch, 2^28 pending keys, 20 us. */
 typedef struct {
     uint32_t n_slots;

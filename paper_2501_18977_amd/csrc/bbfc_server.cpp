@@ -165,14 +165,20 @@ void finish_slot(bbfc_server &s, Slot &slot, Clock::time_point now)
     slot.pieces.clear();
 }
 
-// Waits for a launched batch: polls its event every poll_us (0: yields).
+// Waits for a launched batch by polling its event: yielding between polls
+// for the first kSpinUs (a batch of up to 2^20 keys is back within a few
+// hundred microseconds, and a sleep would add its timer slack to the
+// latency), then sleeping poll_us between polls (0: yielding throughout).
+constexpr int kSpinUs = 1000;
+
 hipError_t wait_slot(const bbfc_server &s, const Slot &slot)
 {
+    const Clock::time_point spin_until = Clock::now() + std::chrono::microseconds(kSpinUs);
     for (;;) {
         const hipError_t q = hipEventQuery(slot.done);
         if (q != hipErrorNotReady)
             return q;
-        if (s.cfg.poll_us)
+        if (s.cfg.poll_us && Clock::now() >= spin_until)
             std::this_thread::sleep_for(std::chrono::microseconds(s.cfg.poll_us));
         else
             std::this_thread::yield();
