@@ -210,3 +210,16 @@ def test_serving_while_inserting(dev):
     for r, d, a in zip(reqs, during, after):
         assert not np.any(d & ~a)
         assert bbfc.unpack_bits(a, len(r)).all()
+
+
+def test_close_with_requests_in_flight(served):
+    """Closing the server with admitted requests that nobody waited for
+    serves them first: their answer buffers are filled when close returns."""
+    ref, f, keys = served
+    reqs = make_requests(keys, [70_000, 5, 4096, 200_000], 7)
+    srv = bbfc.Server(f, n_slots=2, max_batch_keys=1 << 14)
+    tickets = [srv.submit(r) for r in reqs]
+    outs = [srv._live[t][1] for t in tickets]
+    srv.close()
+    for r, o in zip(reqs, outs):
+        assert np.array_equal(o[: (len(r) + 63) // 64], ref.query_bits(r))
