@@ -19,7 +19,8 @@
  *             i is block h_0(x) S + h_i(x); T = 1 is a single array
  *                                      (Section 3.4, "Parallelization")
  *   F(x)      { f_i(x) : i = 1..k }, f_i random-strategy bit hashes into
- *             [512]                  (Section 3.1 eq. bitset; Section 3.3)
+ *             [512]                  (Section 3.1 eq. bitset; Section 3.3),
+ *             or k distinct addresses by the insertion procedure of App. B
  *   j, a      for a candidate block with bit set F':
  *             j = |F' u F(x)|, a = |F(x) \ F'|    (Section 3.2; App. A)
  *   insert    no-op if some candidate already holds all of F(x); otherwise
