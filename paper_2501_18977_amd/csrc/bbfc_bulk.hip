@@ -345,7 +345,14 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
                                                            uint32_t waves_per_wg, uint64_t n_waves)
 {
     using WL = WaveLds<SUB, C>;
-    constexpr int LPK = 8;
+    // Four lanes per key, two block words each: a round decides up to 16 keys,
+    // so a window of disjoint candidates holds more keys than with 8 lanes per
+    // key; with 2 lanes per key the wider per-lane reductions cost more than
+    // the longer windows save (measured on 2^30 keys, 256 blocks per sub-array).
+    constexpr int LPK = 4;
+    constexpr int KW = 8 / LPK;      // words per lane
+    constexpr int KPR = kWave / LPK; // keys per round
+    constexpr int R = LPK;           // rounds per 64-key chunk
     extern __shared__ __align__(16) uint8_t lds[];
     uint16_t *s_rank = reinterpret_cast<uint16_t *>(lds);
     const size_t rank_bytes = C > 1 ? (((size_t)(p.k + 1) * kRankStride * 2 + 15) & ~(size_t)15) : 0;
@@ -387,7 +394,7 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
     }
 
     const uint32_t g = lane / LPK;
-    const uint32_t w0 = lane % LPK;
+    const uint32_t w0 = (lane % LPK) * KW;
     constexpr int kSubIters = SUB * 8 / (2 * kWave); // 16-byte pieces per lane of a staged sub-array
     constexpr int kBatch = kSubIters < 8 ? kSubIters : 8;
     const uint64_t n_words = S * 8;
@@ -453,7 +460,7 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
             const bool more = n_valid == (uint32_t)kWave;
             const uint64_t x_next = more && nidx < n ? sorted[nidx] : 0;
 
-            // P: earlier keys of the same 8-key round that share a candidate
+            // P: earlier keys of the same KPR-key round that share a candidate
             // (claim bits hashed into kClaimSlots entries; a collision only
             // splits a window). A round never spans the two halves of the
             // wavefront, so each half claims in turn with 32-bit entries.
@@ -482,54 +489,61 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
                 }
                 wave_sync();
             }
-            P &= lanemask_lt(lane) & ~lanemask_lt(lane & ~7u);
+            P &= lanemask_lt(lane) & ~lanemask_lt(lane & ~(uint32_t)(KPR - 1));
 
-            // Round r takes keys 8r..8r+7, group g key 8r+g: its candidates
-            // and its mask word w0, fetched for all rounds before any round runs.
-            uint32_t rc[8][C];
-            uint64_t mw[8];
+            // Round r takes keys KPR*r .. KPR*r+KPR-1, lane group g key KPR*r+g:
+            // its candidates and its mask words w0 .. w0+KW-1, fetched for all
+            // rounds before any round runs.
+            uint32_t rc[R][C];
+            uint64_t mw[R][KW];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int src = 8 * r + (int)g;
+            for (int r = 0; r < R; ++r) {
+                const int src = KPR * r + (int)g;
 #pragma unroll
                 for (int i = 0; i < C; ++i)
                     rc[r][i] = (uint32_t)__shfl((int)cand[i], src);
                 const uint32_t *ks = smask + src * kBulkSlotDw + 2 * w0;
-                mw[r] = *reinterpret_cast<const uint64_t *>(ks);
+#pragma unroll
+                for (int q = 0; q < KW; ++q)
+                    mw[r][q] = *reinterpret_cast<const uint64_t *>(ks + 2 * q);
             }
 
             static_for(
                 [&](auto rconst) __attribute__((always_inline)) {
                     constexpr int r = decltype(rconst)::value;
-                    const uint32_t lo = 8 * r;
-                    const uint32_t hi = lo + 8 < n_valid ? lo + 8 : n_valid;
+                    const uint32_t lo = KPR * r;
+                    const uint32_t hi = lo + KPR < n_valid ? lo + KPR : n_valid;
                     uint32_t s = lo;
                     while (s < hi) {
                         const uint64_t conflict = __ballot(lane > s && lane < hi && (P >> s) != 0);
                         const uint32_t e = conflict ? (uint32_t)__builtin_ctzll(conflict) : hi;
                         const uint32_t t = lo + g;
                         const bool active = t >= s && t < e;
-                        uint64_t B[C][1];
+                        uint64_t B[C][KW];
 #pragma unroll
                         for (int i = 0; i < C; ++i)
-                            B[i][0] = sub[(uint64_t)rc[r][i] * 8 + w0];
-                        const uint64_t m[1] = {mw[r]};
-                        const JA<C> ja = reduce_ja<C, LPK, 1>(B, m);
+#pragma unroll
+                            for (int q = 0; q < KW; ++q)
+                                B[i][q] = sub[(uint64_t)rc[r][i] * 8 + w0 + q];
+                        const JA<C> ja = reduce_ja<C, LPK, KW>(B, mw[r]);
                         const int best = decide<C>(ja, s_rank);
                         if (active && best >= 0) {
                             uint32_t blk = rc[r][0];
 #pragma unroll
                             for (int i = 1; i < C; ++i)
                                 blk = best == i ? rc[r][i] : blk;
-                            const uint64_t old = pick<C, 1>(B, best, 0);
-                            if (m[0] & ~old)
-                                sub[(uint64_t)blk * 8 + w0] = old | m[0];
+#pragma unroll
+                            for (int q = 0; q < KW; ++q) {
+                                const uint64_t old = pick<C, KW>(B, best, q);
+                                if (mw[r][q] & ~old)
+                                    sub[(uint64_t)blk * 8 + w0 + q] = old | mw[r][q];
+                            }
                         }
                         wave_sync();
                         s = e;
                     }
                 },
-                std::make_integer_sequence<int, 8>{});
+                std::make_integer_sequence<int, R>{});
             pos += n_valid;
             if (!more)
                 break;
