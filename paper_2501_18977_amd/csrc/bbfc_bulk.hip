@@ -12,9 +12,12 @@
 // The result equals inserting the keys one at a time in index order
 // (Section 3.2 applied key by key): the partition is stable, so every
 // sub-array sees its keys in index order, and inside a sub-array the
-// wavefront takes the keys in windows of consecutive keys whose candidate
-// blocks are pairwise disjoint, so the keys of a window can be decided
-// together against the state left by all earlier windows.
+// wavefront decides a key only after every earlier key that shares one of
+// its candidate blocks. A key's candidate blocks change only when a key that
+// shares one of them is inserted, and such keys are decided before it if they
+// come earlier and after it if later, so every key sees its candidates as in
+// the one-at-a-time order. Keys decided in the same step share no candidate
+// and are decided together.
 //
 // Kernels, per radix pass p (digits of h_0, least significant first):
 //   bulk_hist_kernel     per group of up to 16 tiles of 4096 keys, the
@@ -78,6 +81,34 @@ __device__ __forceinline__ void static_for(F &&f, std::integer_sequence<int, R..
 __device__ __forceinline__ uint64_t lanemask_lt(uint32_t lane)
 {
     return lane == 0 ? 0 : (~0ull >> (64 - lane));
+}
+
+// Set bits of m below bit `lane`.
+__device__ __forceinline__ uint32_t count_below(uint64_t m, uint32_t lane)
+{
+    return (uint32_t)__popcll(m & lanemask_lt(lane));
+}
+
+// v / D for v < 48 (D = 3) or v < 56 (D = 7), with a 24-bit multiply.
+template <int D>
+__device__ __forceinline__ uint32_t div_by(uint32_t v)
+{
+    static_assert(D == 3 || D == 7, "divisor 3 or 7");
+    if constexpr (D == 3)
+        return (v * 43u) >> 7;
+    else
+        return (v * 37u) >> 8;
+}
+
+// The value of the first lane of each aligned group of LPK (4 or 8) lanes.
+template <int LPK>
+__device__ __forceinline__ uint32_t group_first(uint32_t v)
+{
+    static_assert(LPK == 4 || LPK == 8, "groups of 4 or 8 lanes");
+    if constexpr (LPK == 4)
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x00, 0xF, 0xF, false); // quad_perm 0,0,0,0
+    else
+        return (uint32_t)__shfl((int)v, (int)(__lane_id() & ~7u));
 }
 
 // ----------------------------------------------------------- partition
@@ -338,21 +369,21 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
 
 // Each wavefront takes the sub-arrays whose run of sorted keys starts in its
 // share [c0, c1) of the positions, and for each: stages the sub-array in
-// LDS, inserts the run's keys in order in windows of disjoint candidates,
-// and writes the sub-array back. S <= SUB blocks per sub-array.
+// LDS, inserts the run's keys in steps of keys with disjoint candidates
+// (each after the earlier keys it conflicts with), and writes the sub-array
+// back. S <= SUB blocks per sub-array.
 template <int C, int SUB>
 __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint64_t *__restrict__ sorted, uint64_t n,
                                                            uint32_t waves_per_wg, uint64_t n_waves)
 {
     using WL = WaveLds<SUB, C>;
-    // Four lanes per key, two block words each: a round decides up to 16 keys,
-    // so a window of disjoint candidates holds more keys than with 8 lanes per
-    // key; with 2 lanes per key the wider per-lane reductions cost more than
-    // the longer windows save (measured on 2^30 keys, 256 blocks per sub-array).
+    // Four lanes per key, two block words each: a step decides up to 16
+    // keys. Measured on 2^30 keys with 256 blocks per sub-array, this beats
+    // eight lanes per key (steps of 8 keys) and two (each lane reduces four
+    // words).
     constexpr int LPK = 4;
     constexpr int KW = 8 / LPK;      // words per lane
-    constexpr int KPR = kWave / LPK; // keys per round
-    constexpr int R = LPK;           // rounds per 64-key chunk
+    constexpr int KPR = kWave / LPK; // keys per step
     extern __shared__ __align__(16) uint8_t lds[];
     uint16_t *s_rank = reinterpret_cast<uint16_t *>(lds);
     const size_t rank_bytes = C > 1 ? (((size_t)(p.k + 1) * kRankStride * 2 + 15) & ~(size_t)15) : 0;
@@ -460,10 +491,10 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
             const bool more = n_valid == (uint32_t)kWave;
             const uint64_t x_next = more && nidx < n ? sorted[nidx] : 0;
 
-            // P: earlier keys of the same KPR-key round that share a candidate
-            // (claim bits hashed into kClaimSlots entries; a collision only
-            // splits a window). A round never spans the two halves of the
-            // wavefront, so each half claims in turn with 32-bit entries.
+            // P: the earlier keys of the chunk that share a candidate (claim
+            // bits hashed into kClaimSlots 32-bit entries; a collision only
+            // adds a dependency). The lower half claims first and both halves
+            // read; then the upper half claims and reads.
             uint64_t P = 0;
 #pragma unroll
             for (uint32_t half = 0; half < 2; ++half) {
@@ -474,12 +505,12 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
                         atomicOr(&claim[cand[i] % kClaimSlots], 1u << (lane & 31));
                 }
                 wave_sync();
-                if (mine_half) {
+                if ((lane >> 5) >= half) {
                     uint32_t q = 0;
 #pragma unroll
                     for (int i = 0; i < C; ++i)
                         q |= claim[cand[i] % kClaimSlots];
-                    P = (uint64_t)q << (32 * half);
+                    P |= (uint64_t)q << (32 * half);
                 }
                 wave_sync();
                 if (valid && mine_half) {
@@ -489,61 +520,67 @@ __global__ __launch_bounds__(512) void bulk_insert_kernel(KParams p, const uint6
                 }
                 wave_sync();
             }
-            P &= lanemask_lt(lane) & ~lanemask_lt(lane & ~(uint32_t)(KPR - 1));
+            P &= lanemask_lt(lane);
 
-            // Round r takes keys KPR*r .. KPR*r+KPR-1, lane group g key KPR*r+g:
-            // its candidates and its mask words w0 .. w0+KW-1, fetched for all
-            // rounds before any round runs.
-            uint32_t rc[R][C];
-            uint64_t mw[R][KW];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int src = KPR * r + (int)g;
+            // Steps: each takes the first KPR pending keys whose earlier
+            // conflicting keys are all done. The keys of a step share no
+            // candidate, and every key is decided after each earlier key
+            // that shares one, so the result is the sequential one. The
+            // lowest pending key is always ready: at most 64 steps.
+            uint64_t done = 0;
+            while (done != vb) {
+                const bool ready = valid && !((done >> lane) & 1) && (P & ~done) == 0;
+                const uint64_t rb = __ballot(ready);
+                const bool take = ready && count_below(rb, lane) < (uint32_t)KPR;
+                const uint64_t tb = __ballot(take);
+                const uint32_t cnt = (uint32_t)__popcll(tb);
+                // taken key number r goes to lane LPK*r; the other lanes fill the
+                // remaining lanes in order, so that the push is a permutation
+                const uint32_t tr = count_below(tb, lane);
+                uint32_t dest;
+                if (take) {
+                    dest = LPK * tr;
+                } else {
+                    const uint32_t nr = lane - tr;
+                    const uint32_t gap = (LPK - 1) * cnt;
+                    dest = nr < gap ? LPK * div_by<LPK - 1>(nr) + 1 + (nr - (LPK - 1) * div_by<LPK - 1>(nr))
+                                    : LPK * cnt + (nr - gap);
+                }
+                const int daddr = (int)(dest * 4);
+                uint32_t rc[C];
 #pragma unroll
                 for (int i = 0; i < C; ++i)
-                    rc[r][i] = (uint32_t)__shfl((int)cand[i], src);
+                    rc[i] = group_first<LPK>((uint32_t)__builtin_amdgcn_ds_permute(daddr, (int)cand[i]));
+                const uint32_t src = group_first<LPK>((uint32_t)__builtin_amdgcn_ds_permute(daddr, (int)lane));
+                const bool active = g < cnt;
+                uint64_t mw[KW];
                 const uint32_t *ks = smask + src * kBulkSlotDw + 2 * w0;
 #pragma unroll
                 for (int q = 0; q < KW; ++q)
-                    mw[r][q] = *reinterpret_cast<const uint64_t *>(ks + 2 * q);
-            }
-
-            static_for(
-                [&](auto rconst) __attribute__((always_inline)) {
-                    constexpr int r = decltype(rconst)::value;
-                    const uint32_t lo = KPR * r;
-                    const uint32_t hi = lo + KPR < n_valid ? lo + KPR : n_valid;
-                    uint32_t s = lo;
-                    while (s < hi) {
-                        const uint64_t conflict = __ballot(lane > s && lane < hi && (P >> s) != 0);
-                        const uint32_t e = conflict ? (uint32_t)__builtin_ctzll(conflict) : hi;
-                        const uint32_t t = lo + g;
-                        const bool active = t >= s && t < e;
-                        uint64_t B[C][KW];
+                    mw[q] = *reinterpret_cast<const uint64_t *>(ks + 2 * q);
+                uint64_t B[C][KW];
 #pragma unroll
-                        for (int i = 0; i < C; ++i)
+                for (int i = 0; i < C; ++i)
 #pragma unroll
-                            for (int q = 0; q < KW; ++q)
-                                B[i][q] = sub[(uint64_t)rc[r][i] * 8 + w0 + q];
-                        const JA<C> ja = reduce_ja<C, LPK, KW>(B, mw[r]);
-                        const int best = decide<C>(ja, s_rank);
-                        if (active && best >= 0) {
-                            uint32_t blk = rc[r][0];
+                    for (int q = 0; q < KW; ++q)
+                        B[i][q] = sub[(uint64_t)rc[i] * 8 + w0 + q];
+                const JA<C> ja = reduce_ja<C, LPK, KW>(B, mw);
+                const int best = decide<C>(ja, s_rank);
+                if (active && best >= 0) {
+                    uint32_t blk = rc[0];
 #pragma unroll
-                            for (int i = 1; i < C; ++i)
-                                blk = best == i ? rc[r][i] : blk;
+                    for (int i = 1; i < C; ++i)
+                        blk = best == i ? rc[i] : blk;
 #pragma unroll
-                            for (int q = 0; q < KW; ++q) {
-                                const uint64_t old = pick<C, KW>(B, best, q);
-                                if (mw[r][q] & ~old)
-                                    sub[(uint64_t)blk * 8 + w0 + q] = old | mw[r][q];
-                            }
-                        }
-                        wave_sync();
-                        s = e;
+                    for (int q = 0; q < KW; ++q) {
+                        const uint64_t old = pick<C, KW>(B, best, q);
+                        if (mw[q] & ~old)
+                            sub[(uint64_t)blk * 8 + w0 + q] = old | mw[q];
                     }
-                },
-                std::make_integer_sequence<int, R>{});
+                }
+                wave_sync();
+                done |= tb;
+            }
             pos += n_valid;
             if (!more)
                 break;
