@@ -177,9 +177,10 @@ bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipSt
 
 /* Insert d_keys[0..n) with exactly the sequential semantics: the result is
  * the filter obtained by inserting the keys one at a time in index order
- * (Section 3.2 applied key by key). Runs on a single wavefront; consecutive
- * keys whose candidate blocks are pairwise disjoint are processed together.
- * Meant for small inputs and for checking. Errors as bbfc_insert. */
+ * (Section 3.2 applied key by key), on any layout. Runs on one workgroup:
+ * each step decides together every held key that no older held key shares
+ * a candidate block with. For filters with sub-arrays, bbfc_bulk_insert
+ * gives the same result much faster. Errors as bbfc_insert. */
 bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uint64_t n,
                                       hipStream_t stream);
 

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbbfc.so")
-SOURCES = ["bbfc_api.cpp", "bbfc_kernels.hip", "bbfc_batch.hip", "bbfc_server.cpp", "bbfc_probe.hip", "bbfc_bulk.hip"]
+SOURCES = ["bbfc_api.cpp", "bbfc_kernels.hip", "bbfc_batch.hip", "bbfc_server.cpp", "bbfc_probe.hip", "bbfc_bulk.hip", "bbfc_ordered.hip"]
 HEADERS = ["bbfc_common.hpp", "bbfc_internal.hpp", "bbfc_tile.hpp"]
 ARCH = os.environ.get("BBFC_OFFLOAD_ARCH", "gfx950")
 

@@ -57,70 +57,6 @@ __global__ __launch_bounds__(kWGSize) void insert_kernel(KParams p, Src keys, ui
         insert_tiles<C, LPK, T>(p, s_rank, keys, n, u * T * kTile, lane, s_mask[wv], s_blk[wv]);
 }
 
-// Sequential-semantics insert on a single wavefront. Within a tile the
-// keys are taken in index order in windows of up to eight: the window is cut
-// before the first key that shares a candidate block with an earlier key of
-// the window, so the keys processed together touch disjoint blocks and the
-// outcome is that of inserting them one after another. Block words are read
-// with agent-scope atomic loads (no stale per-CU cache line) and every
-// window's writes complete before the next window reads.
-template <int C>
-__global__ __launch_bounds__(kWave) void insert_det_kernel(KParams p, const uint64_t *__restrict__ keys, uint64_t n,
-                                                           uint64_t n_tiles)
-{
-    constexpr uint64_t kGroupLsb = 0x0101010101010101ull;
-    __shared__ uint32_t smask[kTile * kSlotDw];
-    __shared__ uint64_t sblk[kTile * C];
-    extern __shared__ uint16_t s_rank[];
-    load_rank_table<C>(p, s_rank);
-
-    const uint32_t lane = threadIdx.x;
-    const uint32_t g = lane >> 3;
-    const uint32_t w = lane & 7;
-
-    for (uint64_t tile = 0; tile < n_tiles; ++tile) {
-        const uint64_t base = tile * kTile;
-        phase_a<C>(p, ArrayKeys{keys}, n, base, lane, smask, sblk);
-        wave_sync();
-        const uint32_t in_tile = (uint32_t)((n - base) < (uint64_t)kTile ? (n - base) : (uint64_t)kTile);
-        uint32_t pos = 0;
-        while (pos < in_tile) {
-            const uint32_t t = pos + g;
-            const bool active = t < in_tile;
-            bool conflict = false;
-            if (active) {
-                for (uint32_t q = 0; q < g; ++q) {
-#pragma unroll
-                    for (int i = 0; i < C; ++i)
-#pragma unroll
-                        for (int i2 = 0; i2 < C; ++i2)
-                            conflict |= sblk[t * C + i] == sblk[(pos + q) * C + i2];
-                }
-            }
-            // First group that is inactive or conflicts ends the window; group
-            // 0 is always active and conflict-free, so the window is non-empty.
-            const uint64_t stop = __ballot(!active || conflict) & kGroupLsb;
-            const uint32_t width = stop ? (uint32_t)(__builtin_ctzll(stop) >> 3) : 8u;
-            if (g < width) {
-                uint64_t m[1];
-                mask_words<1>(smask, t, w, m);
-                uint64_t B[C][1];
-#pragma unroll
-                for (int i = 0; i < C; ++i)
-                    B[i][0] = __hip_atomic_load(&p.words[sblk[t * C + i] * 8 + w], __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                const JA<C> ja = reduce_ja<C, 8, 1>(B, m);
-                const int best = decide<C>(ja, s_rank);
-                if (best >= 0 && (m[0] & ~pick<C, 1>(B, best, 0)))
-                    atomic_or_word(&p.words[sblk[t * C + best] * 8 + w], m[0]);
-            }
-            __builtin_amdgcn_s_waitcnt(0); // this window's atomics are done before the next reads
-            pos += width;
-        }
-        wave_sync();
-    }
-}
-
 __global__ void fill_zero_kernel(uint64_t *p, uint64_t n_words)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -277,15 +213,6 @@ hipError_t query_c(const bbfc_filter &f, const Src &keys, uint64_t n, uint64_t *
     });
 }
 
-template <int C>
-hipError_t insert_det_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
-{
-    const uint64_t n_tiles = (n + kTile - 1) / kTile;
-    hipLaunchKernelGGL((insert_det_kernel<C>), dim3(1), dim3(kWave), rank_lds_bytes(f.c, f.k), s, make_kparams(f), keys,
-                       n, n_tiles);
-    return hipGetLastError();
-}
-
 template <typename Src>
 hipError_t insert_any(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s)
 {
@@ -373,22 +300,6 @@ hipError_t launch_kmer_keys(const uint64_t *seq, uint64_t n_segments, uint64_t s
         blocks = 65536;
     hipLaunchKernelGGL(kmer_keys_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, src, n, out);
     return hipGetLastError();
-}
-
-hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
-{
-    switch (f.c) {
-    case 1:
-        return insert_det_c<1>(f, keys, n, s);
-    case 2:
-        return insert_det_c<2>(f, keys, n, s);
-    case 3:
-        return insert_det_c<3>(f, keys, n, s);
-    case 4:
-        return insert_det_c<4>(f, keys, n, s);
-    default:
-        return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)

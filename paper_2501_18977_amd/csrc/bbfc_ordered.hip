@@ -1,0 +1,242 @@
+// Insert with the sequential semantics on any filter layout (Section 3.2
+// applied key by key, in index order).
+//
+// One workgroup of kOrdThreads threads; each thread holds one key at a time,
+// with its 512-bit mask in an LDS slot and its candidate blocks in registers.
+// A step
+//   1) hands the next keys, in index order, to the threads whose key is done;
+//   2) lets every pending key claim its candidate blocks in a hashed LDS
+//      table that keeps the oldest claimer of each entry;
+//   3) decides together every pending key that is the oldest claimer of all
+//      its entries, reading its candidates from memory and writing the chosen
+//      block back.
+// A key decided in step 3 has no older pending key that shares a candidate
+// with it, and two keys decided together share none. A key's candidate
+// blocks change only when a key that shares one is inserted; such keys are
+// decided before it if older and after it if younger, so every key sees its
+// candidates as in the one-at-a-time order. The oldest pending key wins all
+// its entries, so each step decides at least one key. A hash collision in the
+// table only defers a key to a later step.
+//
+// All waves of the workgroup run on one CU, so they share its L1 and its L2.
+// Block words are read with agent-scope atomic loads (served by the L2, never
+// a stale L1 line), eight lanes per key so that a load reads whole blocks,
+// and every step's stores complete before the next step's reads.
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "bbfc_common.hpp"
+#include "bbfc_internal.hpp"
+#include "bbfc_tile.hpp"
+
+namespace bbfc {
+namespace {
+
+constexpr int kOrdThreads = 1024;
+constexpr int kOrdWaves = kOrdThreads / kWave;
+constexpr uint32_t kOrdClaims = 8192; // claim table entries, a power of two
+constexpr int kOrdSlotDw = 16;        // LDS dwords per key mask
+
+__host__ __device__ constexpr size_t align16(size_t b)
+{
+    return (b + 15) & ~(size_t)15;
+}
+
+// LDS: rank table | key masks | claim table | per-wave counts.
+__host__ __device__ constexpr size_t ordered_lds_bytes(size_t rank_bytes)
+{
+    return align16(rank_bytes) + (size_t)kOrdThreads * kOrdSlotDw * 4 + (size_t)kOrdClaims * 4 + kOrdWaves * 4;
+}
+
+// Lane src's 64-bit value.
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
+{
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t claim_entry(uint64_t blk)
+{
+    return (uint32_t)blk & (kOrdClaims - 1);
+}
+
+template <int C>
+__global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, const uint64_t *__restrict__ keys,
+                                                                     uint64_t n, uint32_t rank_bytes)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint16_t *s_rank = reinterpret_cast<uint16_t *>(lds);
+    uint32_t *smask = reinterpret_cast<uint32_t *>(lds + align16(rank_bytes));
+    uint32_t *claim = smask + kOrdThreads * kOrdSlotDw;
+    uint32_t *wsum = claim + kOrdClaims;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & (kWave - 1);
+    const uint32_t wv = tid / kWave;
+    for (uint32_t i = tid; i < kOrdClaims; i += kOrdThreads)
+        claim[i] = 0;
+    if constexpr (C > 1) {
+        const uint32_t nr = (p.k + 1) * kRankStride;
+        for (uint32_t i = tid; i < nr; i += kOrdThreads)
+            s_rank[i] = p.rank[i];
+    }
+    __syncthreads();
+
+    uint32_t *slot = smask + tid * kOrdSlotDw;
+    uint64_t next = 0; // the next key to hand out (the same in every thread)
+    uint64_t my = 0;   // index of this thread's key
+    bool pending = false;
+    uint64_t cand[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+        cand[i] = 0;
+
+    for (;;) {
+        // 1) keys next, next+1, ... to the free threads in thread order
+        const uint64_t fb = __ballot(!pending);
+        if (lane == 0)
+            wsum[wv] = (uint32_t)__popcll(fb);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kOrdWaves; ++w) {
+            const uint32_t c = wsum[w];
+            before += (uint32_t)w < wv ? c : 0;
+            total += c;
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(fb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fb, 0));
+        if (!pending && next + before + below < n) {
+            my = next + before + below;
+            const uint64_t x = keys[my];
+#pragma unroll
+            for (int d = 0; d < kOrdSlotDw; d += 4)
+                *reinterpret_cast<uint4 *>(slot + d) = make_uint4(0, 0, 0, 0);
+            auto set_bit = [slot](uint32_t f) { atomicOr(slot + (f >> 5), 1u << (f & 31)); };
+            if (p.distinct)
+                distinct_bits(p.bit_mult, p.k, x, set_bit);
+            else
+                random_bits(p.bit_mult, p.k, x, set_bit);
+            const uint64_t first = sub_base(p, x);
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                cand[i] = first + block_hash_rt(p, p.block_mult[i], x);
+            pending = true;
+        }
+        next = n - next > total ? next + total : n;
+        if (!__syncthreads_or(pending))
+            break;
+
+        // 2) claims: the oldest pending key (largest age) keeps each entry.
+        // A key stays pending for at most kOrdThreads steps (each step decides
+        // the oldest pending key, and every older key is already held), so
+        // ages stay below kOrdThreads * (kOrdThreads + 1) and are distinct.
+        const uint32_t age = (uint32_t)(next - my);
+        if (pending) {
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                atomicMax(&claim[claim_entry(cand[i])], age);
+        }
+        __syncthreads();
+        bool ready = pending;
+        if (pending) {
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                ready = ready && claim[claim_entry(cand[i])] == age;
+        }
+        __syncthreads();
+        if (pending) {
+#pragma unroll
+            for (int i = 0; i < C; ++i)
+                claim[claim_entry(cand[i])] = 0;
+        }
+
+        // 3) decide the ready keys, eight lanes per key as in the racing
+        // insert: round r of a wave takes the wave's keys 8r .. 8r+7, lane
+        // group g key 8r+g and block word lane % 8, so each load instruction
+        // reads eight whole blocks. The ready keys share no candidate, so all
+        // their reads are issued before any write.
+        const uint64_t rb = __ballot(ready);
+        const uint32_t g = lane / 8;
+        const uint32_t w = lane % 8;
+        constexpr int RB = C <= 2 ? 8 : 4; // rounds whose reads are in flight together
+#pragma unroll
+        for (int r0 = 0; r0 < 8; r0 += RB) {
+            uint64_t B[RB][C][1];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const uint32_t src = 8 * (r0 + r) + g;
+                const bool take = (rb >> src) & 1;
+#pragma unroll
+                for (int i = 0; i < C; ++i) {
+                    const uint64_t blk = shfl_u64(cand[i], (int)src);
+                    B[r][i][0] = take ? __hip_atomic_load(&p.words[blk * 8 + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                      : 0;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                if (((rb >> (8 * (r0 + r))) & 0xFF) == 0)
+                    continue;
+                const uint32_t src = 8 * (r0 + r) + g;
+                const bool take = (rb >> src) & 1;
+                const uint32_t *ks = smask + (wv * kWave + src) * kOrdSlotDw + 2 * w;
+                const uint64_t m[1] = {(uint64_t)ks[0] | ((uint64_t)ks[1] << 32)};
+                const JA<C> ja = reduce_ja<C, 8, 1>(B[r], m);
+                const int best = decide<C>(ja, s_rank);
+                uint64_t blk = shfl_u64(cand[0], (int)src);
+#pragma unroll
+                for (int i = 1; i < C; ++i) {
+                    const uint64_t bi = shfl_u64(cand[i], (int)src);
+                    blk = best == i ? bi : blk;
+                }
+                if (take && best >= 0) {
+                    const uint64_t old = pick<C, 1>(B[r], best, 0);
+                    if (m[0] & ~old)
+                        __hip_atomic_store(&p.words[blk * 8 + w], old | m[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+        if (ready)
+            pending = false;
+        __builtin_amdgcn_s_waitcnt(0); // this step's stores are done before any thread reads again
+        __syncthreads();
+    }
+}
+
+template <int C>
+hipError_t launch_ordered_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+{
+    const size_t rank = rank_lds_bytes(f.c, f.k);
+    const size_t lds = ordered_lds_bytes(rank);
+    if (f.max_lds < lds)
+        return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void *)insert_ordered_kernel<C>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((insert_ordered_kernel<C>), dim3(1), dim3(kOrdThreads), lds, s, make_kparams(f), keys, n,
+                       (uint32_t)rank);
+    return hipGetLastError();
+}
+
+} // namespace
+
+hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+{
+    switch (f.c) {
+    case 1:
+        return launch_ordered_c<1>(f, keys, n, s);
+    case 2:
+        return launch_ordered_c<2>(f, keys, n, s);
+    case 3:
+        return launch_ordered_c<3>(f, keys, n, s);
+    case 4:
+        return launch_ordered_c<4>(f, keys, n, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+} // namespace bbfc
