@@ -141,6 +141,25 @@ def test_deterministic_insert_is_bit_exact(dev, M, c, k, cost, n):
         gpu.close()
 
 
+# The sequential insert holds 1024 keys at a time and refills as keys are
+# decided: here with every key in conflict (8 blocks), with blocks that share a
+# claim-table entry (block indices 8192 apart), and over many refills.
+@pytest.mark.parametrize(
+    "M,c,k,cost,n",
+    [(8, 2, 6, "la", 50_000), (3 * 8192, 2, 11, "exp", 200_000), (1 << 16, 3, 9, "mix", 1 << 20)],
+)
+def test_deterministic_insert_over_many_steps(dev, M, c, k, cost, n):
+    ref, gpu = make_pair(M, c, k, cost, seed=5 * M + c + k)
+    try:
+        keys = workload.positive_keys(M + 3 * k, n)
+        print(f"sequential insert M={M} c={c} k={k} n={n}", flush=True)
+        ref.insert(keys)
+        gpu.insert_deterministic(to_dev(keys, dev))
+        assert np.array_equal(gpu.download(), ref.words)
+    finally:
+        gpu.close()
+
+
 def test_deterministic_insert_default_parameters_match_oracle_derivation(dev):
     """bbfc_create draws multipliers from SplitMix64 seed 0; the oracle
     derives its own from the same published generator."""
