@@ -4,12 +4,13 @@
 // One workgroup of kOrdThreads threads; each thread holds one key at a time,
 // with its 512-bit mask in an LDS slot and its candidate blocks in registers.
 // A step
-//   1) hands the next keys, in index order, to the threads whose key is done;
+//   1) hashes the keys handed to it by the previous step;
 //   2) lets every pending key claim its candidate blocks in a hashed LDS
 //      table that keeps the oldest claimer of each entry;
 //   3) decides together every pending key that is the oldest claimer of all
 //      its entries, reading its candidates from memory and writing the chosen
-//      block back.
+//      block back, while the next keys, in index order, are loaded for the
+//      threads whose key is decided or that held none.
 // A key decided in step 3 has no older pending key that shares a candidate
 // with it, and two keys decided together share none. A key's candidate
 // blocks change only when a key that shares one is inserted; such keys are
@@ -85,48 +86,36 @@ __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, 
     __syncthreads();
 
     uint32_t *slot = smask + tid * kOrdSlotDw;
-    uint64_t next = 0; // the next key to hand out (the same in every thread)
-    uint64_t my = 0;   // index of this thread's key
-    bool pending = false;
+    // the first keys go to threads 0, 1, ...; later ones to the threads whose
+    // key was decided, in thread order
+    uint64_t my = tid;                                             // index of this thread's key
+    bool fresh = my < n;                                           // holds a key not hashed yet
+    uint64_t xk = fresh ? keys[my] : 0;                            // that key
+    uint64_t next = n > (uint64_t)kOrdThreads ? kOrdThreads : n;   // keys handed out (the same in every thread)
+    bool pending = false;                                          // holds a key not decided yet
     uint64_t cand[C];
 #pragma unroll
     for (int i = 0; i < C; ++i)
         cand[i] = 0;
 
     for (;;) {
-        // 1) keys next, next+1, ... to the free threads in thread order
-        const uint64_t fb = __ballot(!pending);
-        if (lane == 0)
-            wsum[wv] = (uint32_t)__popcll(fb);
-        __syncthreads();
-        uint32_t before = 0, total = 0;
-#pragma unroll
-        for (int w = 0; w < kOrdWaves; ++w) {
-            const uint32_t c = wsum[w];
-            before += (uint32_t)w < wv ? c : 0;
-            total += c;
-        }
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(fb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fb, 0));
-        if (!pending && next + before + below < n) {
-            my = next + before + below;
-            const uint64_t x = keys[my];
+        // 1) hash the keys handed out by the previous step
+        if (fresh) {
 #pragma unroll
             for (int d = 0; d < kOrdSlotDw; d += 4)
                 *reinterpret_cast<uint4 *>(slot + d) = make_uint4(0, 0, 0, 0);
             auto set_bit = [slot](uint32_t f) { atomicOr(slot + (f >> 5), 1u << (f & 31)); };
             if (p.distinct)
-                distinct_bits(p.bit_mult, p.k, x, set_bit);
+                distinct_bits(p.bit_mult, p.k, xk, set_bit);
             else
-                random_bits(p.bit_mult, p.k, x, set_bit);
-            const uint64_t first = sub_base(p, x);
+                random_bits(p.bit_mult, p.k, xk, set_bit);
+            const uint64_t first = sub_base(p, xk);
 #pragma unroll
             for (int i = 0; i < C; ++i)
-                cand[i] = first + block_hash_rt(p, p.block_mult[i], x);
+                cand[i] = first + block_hash_rt(p, p.block_mult[i], xk);
             pending = true;
+            fresh = false;
         }
-        next = n - next > total ? next + total : n;
-        if (!__syncthreads_or(pending))
-            break;
 
         // 2) claims: the oldest pending key (largest age) keeps each entry.
         // A key stays pending for at most kOrdThreads steps (each step decides
@@ -145,7 +134,31 @@ __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, 
             for (int i = 0; i < C; ++i)
                 ready = ready && claim[claim_entry(cand[i])] == age;
         }
+        const bool free_next = !pending || ready;
+        const uint64_t fb = __ballot(free_next);
+        if (lane == 0)
+            wsum[wv] = (uint32_t)__popcll(fb);
         __syncthreads();
+
+        // the next keys, next, next+1, ..., to the threads free after this
+        // step; their loads overlap this step's block reads
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kOrdWaves; ++w) {
+            const uint32_t c = wsum[w];
+            before += (uint32_t)w < wv ? c : 0;
+            total += c;
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(fb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)fb, 0));
+        if (free_next && next + before + below < n) {
+            my = next + before + below;
+            xk = keys[my];
+            fresh = true;
+        }
+        const uint64_t handed = n - next < total ? n - next : total;
+        next += handed;
+        // anything left: keys still pending after this step, or keys just handed out
+        const bool more = total < (uint32_t)kOrdThreads || handed > 0;
         if (pending) {
 #pragma unroll
             for (int i = 0; i < C; ++i)
@@ -202,6 +215,8 @@ __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, 
             pending = false;
         __builtin_amdgcn_s_waitcnt(0); // this step's stores are done before any thread reads again
         __syncthreads();
+        if (!more)
+            break;
     }
 }
 
