@@ -146,7 +146,12 @@ def test_deterministic_insert_is_bit_exact(dev, M, c, k, cost, n):
 # claim-table entry (block indices 8192 apart), and over many refills.
 @pytest.mark.parametrize(
     "M,c,k,cost,n",
-    [(8, 2, 6, "la", 50_000), (3 * 8192, 2, 11, "exp", 200_000), (1 << 16, 3, 9, "mix", 1 << 20)],
+    [
+        (8, 2, 6, "la", 50_000),
+        (3 * 8192, 2, 11, "exp", 200_000),
+        (1 << 16, 3, 9, "mix", 1 << 20),
+        (501, 4, 32, "mix", 20_000),  # the largest LDS: c = 4, k = 32
+    ],
 )
 def test_deterministic_insert_over_many_steps(dev, M, c, k, cost, n):
     ref, gpu = make_pair(M, c, k, cost, seed=5 * M + c + k)
