@@ -50,7 +50,7 @@ typedef enum {
     BBFC_EINVAL = -1,      /* bad argument; nothing was enqueued             */
     BBFC_ENOMEM = -2,      /* device allocation failed                       */
     BBFC_EHIP = -3,        /* a HIP runtime call or kernel launch failed     */
-    BBFC_EUNSUPPORTED = -4, /* valid request this build does not implement   */
+    BBFC_EUNSUPPORTED = -4, /* valid request the library does not implement  */
     BBFC_EBUSY = -5         /* not now: admission full or not finished yet    */
 } bbfc_status;
 
@@ -79,7 +79,7 @@ typedef struct {
     double param;
 } bbfc_cost;
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define BBFC_MAX_CHOICES 4u
 #define BBFC_MAX_BITS_PER_KEY 32u
 
