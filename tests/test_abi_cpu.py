@@ -203,3 +203,23 @@ def test_workload_generators_agree():
     for i, v in enumerate(keys):
         assert int(v) == workload.splitmix64_scalar(123, 1000 + i)
     assert len(set(workload.positive_keys(0, 5000)) & set(workload.negative_keys(0, 5000, 5000))) == 0
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library the binding raises; there is no CPU path."""
+    import subprocess
+    import sys
+
+    code = (
+        "import paper_2501_18977_amd as bbfc\n"
+        "bbfc._LIB_PATH = '/nonexistent/libbbfc.so'\n"
+        "try:\n"
+        "    bbfc.Filter(1024, 2, 8, 'la', seed=1)\n"
+        "except RuntimeError as e:\n"
+        "    assert 'no fallback' in str(e), e\n"
+        "    print('raised')\n"
+    )
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "raised"
