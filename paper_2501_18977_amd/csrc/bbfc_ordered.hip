@@ -19,10 +19,10 @@
 // its entries, so each step decides at least one key. A hash collision in the
 // table only defers a key to a later step.
 //
-// All waves of the workgroup run on one CU, so they share its L1 and its L2.
-// Block words are read with agent-scope atomic loads (served by the L2, never
-// a stale L1 line), eight lanes per key so that a load reads whole blocks,
-// and every step's stores complete before the next step's reads.
+// Block words are read and written with plain accesses, eight lanes per key
+// so that a load reads whole blocks: every thread is in one workgroup, and the
+// barrier that ends a step makes its stores visible to the next step's loads
+// (workgroup scope; the step also waits for its stores before the barrier).
 #include <stdint.h>
 
 #include <hip/hip_runtime.h>
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, 
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const uint64_t blk = shfl_u64(cand[i], (int)src);
-                    B[r][i][0] = take ? __hip_atomic_load(&p.words[blk * 8 + w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                    B[r][i][0] = take ? p.words[blk * 8 + w]
                                       : 0;
                 }
             }
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, 
                 if (take && best >= 0) {
                     const uint64_t old = pick<C, 1>(B[r], best, 0);
                     if (m[0] & ~old)
-                        __hip_atomic_store(&p.words[blk * 8 + w], old | m[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        p.words[blk * 8 + w] = old | m[0];
                 }
             }
         }
