@@ -9,7 +9,10 @@
  *  2. the deterministic insert builds the oracle's filter word for word, and
  *     queries of inserted and new keys give the oracle's answer bits;
  *  3. the racing insert has no false negatives;
- *  4. argument errors return BBFC_EINVAL with a message and enqueue nothing.
+ *  4. argument errors return BBFC_EINVAL with a message and enqueue nothing;
+ *  5. a filter with sub-arrays (Section 3.4) from bbfc_create_config, filled
+ *     by the bulk insert in a caller-owned workspace, is the oracle's
+ *     one-at-a-time build word for word.
  */
 #include <math.h>
 #include <stdio.h>
@@ -128,6 +131,42 @@ int main(void)
     CHECK(bbfc_insert(b, NULL, 10, NULL) == BBFC_EINVAL, "null keys accepted");
     CHECK(bbfc_insert(b, NULL, 0, NULL) == BBFC_OK, "an empty insert is not a no-op");
     CHECK(strcmp(bbfc_status_string(BBFC_EINVAL), "invalid argument") == 0, "status string");
+
+    /* 5. sub-arrays and the bulk insert */
+    {
+        const uint64_t M5 = 1u << 14, T5 = 64; /* 256 blocks per sub-array */
+        const uint32_t c5 = 2, k5 = 11;
+        bbfc_config cfg;
+        memset(&cfg, 0, sizeof cfg);
+        cfg.n_blocks = M5;
+        cfg.choices = c5;
+        cfg.bits_per_key = k5;
+        cfg.cost = la;
+        cfg.bit_selection = BBFC_BITS_RANDOM;
+        cfg.seed = 11;
+        cfg.subarrays = T5;
+        bbfc_handle s5 = NULL;
+        CHECK(bbfc_create_config(&cfg, &s5) == BBFC_OK, "create_config: %s", bbfc_last_error());
+        uint64_t ws_bytes = 0, T_got = 0, sm5 = 0, bm5[4], am5[32];
+        bbfc_cost cost5;
+        CHECK(bbfc_bulk_insert_workspace(s5, nq, &ws_bytes) == BBFC_OK && ws_bytes > 0, "workspace size");
+        void *d_ws = NULL;
+        HIP(hipMalloc(&d_ws, ws_bytes));
+        CHECK(bbfc_bulk_insert(s5, d_keys, nq, d_ws, ws_bytes, NULL) == BBFC_OK, "bulk_insert: %s",
+              bbfc_last_error());
+        CHECK(bbfc_get_params(s5, NULL, NULL, NULL, &cost5, bm5, am5) == BBFC_OK, "get_params");
+        CHECK(bbfc_get_subarrays(s5, &T_got, &sm5) == BBFC_OK && T_got == T5, "get_subarrays");
+        uint64_t *got5 = malloc(M5 * 64), *want5 = calloc(M5 * 8, 8);
+        CHECK(bbfc_download(s5, got5, NULL) == BBFC_OK, "download");
+        const bbo_layout L5 = {M5, T5, sm5};
+        bbo_insert(want5, &L5, c5, k5, 0, BBFC_COST_LA, cost5.param, bm5, am5, h_keys, nq);
+        CHECK(memcmp(got5, want5, M5 * 64) == 0, "bulk insert with sub-arrays differs from the oracle");
+        CHECK(bbfc_bulk_insert(s5, d_keys, nq, d_ws, ws_bytes - 1, NULL) == BBFC_EINVAL, "small workspace accepted");
+        HIP(hipFree(d_ws));
+        free(got5);
+        free(want5);
+        CHECK(bbfc_destroy(s5) == BBFC_OK, "destroy");
+    }
 
     CHECK(bbfc_destroy(a) == BBFC_OK, "destroy");
     CHECK(bbfc_destroy(b) == BBFC_OK, "destroy");
