@@ -177,10 +177,14 @@ bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipSt
 
 /* Insert d_keys[0..n) with exactly the sequential semantics: the result is
  * the filter obtained by inserting the keys one at a time in index order
- * (Section 3.2 applied key by key), on any layout. Runs on one workgroup:
- * each step decides together every held key that no older held key shares
- * a candidate block with. For filters with sub-arrays, bbfc_bulk_insert
- * gives the same result much faster. Errors as bbfc_insert. */
+ * (Section 3.2 applied key by key), on any layout. Each step decides
+ * together every pending key that no older pending key shares a candidate
+ * block with: on one workgroup below 2^16 keys, else on the whole device in
+ * windows of 2^16 keys. The first large call allocates 33 MB of scratch that
+ * the filter keeps until bbfc_destroy. Calls on one filter must not overlap.
+ * For filters with sub-arrays, bbfc_bulk_insert gives the same result
+ * faster. Errors as bbfc_insert, and ENOMEM if the scratch cannot be
+ * allocated. */
 bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uint64_t n,
                                       hipStream_t stream);
 

@@ -359,13 +359,16 @@ bbfc_status bbfc_destroy(bbfc_handle h)
     hipError_t e = hipDeviceSynchronize();
     hipError_t e1 = hipFree(h->d_words);
     hipError_t e2 = h->d_rank ? hipFree(h->d_rank) : hipSuccess;
+    for (void *q : {(void *)h->d_ord_claims, (void *)h->d_ord_pend, (void *)h->d_ord_tail})
+        if (q != nullptr && e2 == hipSuccess)
+            e2 = hipFree(q);
     delete h;
     if (e != hipSuccess)
         return hip_fail(e, "synchronising before destroy");
     if (e1 != hipSuccess)
         return hip_fail(e1, "freeing the filter");
     if (e2 != hipSuccess)
-        return hip_fail(e2, "freeing the rank table");
+        return hip_fail(e2, "freeing the rank table or scratch");
     return BBFC_OK;
 }
 
@@ -396,6 +399,8 @@ bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uin
         return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
     DeviceGuard guard(h->device);
     hipError_t e = bbfc::launch_insert_det(*h, d_keys, n, stream);
+    if (e == hipErrorOutOfMemory)
+        return fail(BBFC_ENOMEM, "no device memory for the sequential insert's scratch");
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching deterministic insert");
 }
 

@@ -31,6 +31,11 @@ struct bbfc_filter {
     // launch shape per operation, [BBFC_OP_INSERT] and [BBFC_OP_QUERY]
     bbfc_launch_shape shape[2] = {{8, 1, 0, 0, 0.0f}, {8, 1, 0, 0, 0.0f}};
     size_t max_lds = 65536;       // LDS bytes a workgroup may use on this device
+    // scratch of the sequential insert on large inputs, allocated on first use
+    uint64_t *d_ord_claims = nullptr; // claim table
+    uint8_t *d_ord_pend = nullptr;    // pending flags of a window
+    uint64_t *d_ord_tail = nullptr;   // a window's remaining keys, then their count
+    uint64_t ord_tag = 0;             // last step tag used on this filter
 };
 
 namespace bbfc {
@@ -62,7 +67,7 @@ size_t rank_lds_bytes(uint32_t c, uint32_t k);
 uint64_t insert_inflight(const bbfc_filter &f);
 
 hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
-hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
+hipError_t launch_insert_det(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out,
                         hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s);

@@ -65,8 +65,11 @@ __device__ __forceinline__ uint32_t claim_entry(uint64_t blk)
 
 template <int C>
 __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, const uint64_t *__restrict__ keys,
-                                                                     uint64_t n, uint32_t rank_bytes)
+                                                                     uint64_t n, const uint64_t *__restrict__ n_dev,
+                                                                     uint32_t rank_bytes)
 {
+    if (n_dev != nullptr) // the key count is known on the device only
+        n = *n_dev;
     extern __shared__ __align__(16) uint8_t lds[];
     uint16_t *s_rank = reinterpret_cast<uint16_t *>(lds);
     uint32_t *smask = reinterpret_cast<uint32_t *>(lds + align16(rank_bytes));
@@ -184,8 +187,7 @@ __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, 
 #pragma unroll
                 for (int i = 0; i < C; ++i) {
                     const uint64_t blk = shfl_u64(cand[i], (int)src);
-                    B[r][i][0] = take ? p.words[blk * 8 + w]
-                                      : 0;
+                    B[r][i][0] = take ? p.words[blk * 8 + w] : 0;
                 }
             }
 #pragma unroll
@@ -221,7 +223,8 @@ __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, 
 }
 
 template <int C>
-hipError_t launch_ordered_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+hipError_t launch_ordered_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, const uint64_t *n_dev,
+                            hipStream_t s)
 {
     const size_t rank = rank_lds_bytes(f.c, f.k);
     const size_t lds = ordered_lds_bytes(rank);
@@ -232,23 +235,260 @@ hipError_t launch_ordered_c(const bbfc_filter &f, const uint64_t *keys, uint64_t
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL((insert_ordered_kernel<C>), dim3(1), dim3(kOrdThreads), lds, s, make_kparams(f), keys, n,
-                       (uint32_t)rank);
+                       n_dev, (uint32_t)rank);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ wide steps
+//
+// Large inputs go window by window (kWideWindow keys, in index order) through
+// the whole device. A window's keys first claim their candidate blocks in a
+// device table (kWideClaims entries, hashed by block index) with the value
+// (step tag, age): atomicMax keeps the oldest claimer of the current step.
+// Then a step decides, across the grid, every pending key of the window that
+// still holds all its entries, and the keys that do not claim again for the
+// next step; the keys of a step share no candidate and no older pending key
+// shares one with them, exactly as in the one-workgroup kernel. A key that
+// reads a claim of the next step while checking the current one is only
+// deferred. Tags grow with every step of every call, so old entries never
+// need clearing. After kWideSteps steps the one-workgroup kernel inserts the
+// window's remaining keys in index order. Kernel boundaries order the steps.
+
+constexpr uint32_t kWideWindow = 1u << 16;    // keys per window
+constexpr uint64_t kWideClaims = 1ull << 22;  // claim table entries (32 MB), a power of two
+constexpr int kWideSteps = 3;
+constexpr int kWideThreads = 256;
+
+// Claim of a key: its step's tag above its age (1 .. kWideWindow, larger is older).
+__device__ __forceinline__ uint64_t claim_value(uint64_t tag, uint32_t age)
+{
+    return (tag << 24) | age;
+}
+
+template <int C>
+__device__ __forceinline__ void candidates(const KParams &p, uint64_t x, uint64_t (&cand)[C])
+{
+    const uint64_t first = sub_base(p, x);
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+        cand[i] = first + block_hash_rt(p, p.block_mult[i], x);
+}
+
+template <int C>
+__global__ __launch_bounds__(kWideThreads) void wide_claim_kernel(KParams p, const uint64_t *__restrict__ keys,
+                                                                  uint32_t w, uint64_t *__restrict__ claims,
+                                                                  uint64_t tag)
+{
+    const uint32_t i = blockIdx.x * kWideThreads + threadIdx.x;
+    if (i >= w)
+        return;
+    uint64_t cand[C];
+    candidates<C>(p, keys[i], cand);
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        atomicMax((unsigned long long *)&claims[cand[c] & (kWideClaims - 1)],
+                  (unsigned long long)claim_value(tag, w - i));
+}
+
+// One step over a window: thread i holds key i while it is pending.
+template <int C>
+__global__ __launch_bounds__(kWideThreads) void wide_step_kernel(KParams p, const uint64_t *__restrict__ keys,
+                                                                 uint32_t w, uint64_t *__restrict__ claims,
+                                                                 uint8_t *__restrict__ pend, uint64_t tag,
+                                                                 uint64_t next_tag, int first_step)
+{
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint16_t *s_rank = reinterpret_cast<uint16_t *>(lds);
+    const size_t rank_bytes = C > 1 ? align16((size_t)(p.k + 1) * kRankStride * 2) : 0;
+    uint32_t *smask = reinterpret_cast<uint32_t *>(lds + rank_bytes);
+    if constexpr (C > 1) {
+        const uint32_t nr = (p.k + 1) * kRankStride;
+        for (uint32_t t = threadIdx.x; t < nr; t += kWideThreads)
+            s_rank[t] = p.rank[t];
+    }
+    __syncthreads();
+
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t i = blockIdx.x * kWideThreads + threadIdx.x;
+    const bool pending = i < w && (first_step || pend[i]);
+    const uint64_t x = pending ? keys[i] : 0;
+    uint64_t cand[C];
+    candidates<C>(p, x, cand);
+    const uint64_t mine = claim_value(tag, w - i);
+    bool ready = pending;
+    if (pending) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            ready = ready && __hip_atomic_load(&claims[cand[c] & (kWideClaims - 1)], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT) == mine;
+    }
+    uint32_t *slot = smask + (wv * kWave + lane) * kOrdSlotDw;
+    if (ready) {
+#pragma unroll
+        for (int d = 0; d < kOrdSlotDw; d += 4)
+            *reinterpret_cast<uint4 *>(slot + d) = make_uint4(0, 0, 0, 0);
+        auto set_bit = [slot](uint32_t f) { atomicOr(slot + (f >> 5), 1u << (f & 31)); };
+        if (p.distinct)
+            distinct_bits(p.bit_mult, p.k, x, set_bit);
+        else
+            random_bits(p.bit_mult, p.k, x, set_bit);
+    }
+    wave_sync();
+
+    // the ready keys of the wavefront, eight lanes per key (as in the racing insert)
+    const uint64_t rb = __ballot(ready);
+    const uint32_t g = lane / 8;
+    const uint32_t wd = lane % 8;
+    constexpr int RB = C <= 2 ? 8 : 4;
+#pragma unroll
+    for (int r0 = 0; r0 < 8; r0 += RB) {
+        uint64_t B[RB][C][1];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const uint32_t src = 8 * (r0 + r) + g;
+            const bool take = (rb >> src) & 1;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const uint64_t blk = shfl_u64(cand[c], (int)src);
+                B[r][c][0] = take ? p.words[blk * 8 + wd] : 0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (((rb >> (8 * (r0 + r))) & 0xFF) == 0)
+                continue;
+            const uint32_t src = 8 * (r0 + r) + g;
+            const bool take = (rb >> src) & 1;
+            const uint32_t *ks = smask + (wv * kWave + src) * kOrdSlotDw + 2 * wd;
+            const uint64_t m[1] = {(uint64_t)ks[0] | ((uint64_t)ks[1] << 32)};
+            const JA<C> ja = reduce_ja<C, 8, 1>(B[r], m);
+            const int best = decide<C>(ja, s_rank);
+            uint64_t blk = shfl_u64(cand[0], (int)src);
+#pragma unroll
+            for (int c = 1; c < C; ++c) {
+                const uint64_t bc = shfl_u64(cand[c], (int)src);
+                blk = best == c ? bc : blk;
+            }
+            if (take && best >= 0) {
+                const uint64_t old = pick<C, 1>(B[r], best, 0);
+                if (m[0] & ~old)
+                    p.words[blk * 8 + wd] = old | m[0];
+            }
+        }
+    }
+
+    // the others stay pending and claim for the next step
+    if (i < w)
+        pend[i] = pending && !ready;
+    if (pending && !ready && next_tag != 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            atomicMax((unsigned long long *)&claims[cand[c] & (kWideClaims - 1)],
+                      (unsigned long long)claim_value(next_tag, w - i));
+    }
+}
+
+// The window's keys still pending, in index order, into tail[0 .. *count).
+__global__ __launch_bounds__(1024) void wide_tail_kernel(const uint64_t *__restrict__ keys, uint32_t w,
+                                                         const uint8_t *__restrict__ pend,
+                                                         uint64_t *__restrict__ tail, uint64_t *__restrict__ count)
+{
+    __shared__ uint32_t wsum[1024 / kWave];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave;
+    uint32_t at = 0; // keys written by earlier chunks
+    for (uint32_t base = 0; base < w; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const bool mine = i < w && pend[i];
+        const uint64_t b = __ballot(mine);
+        if (lane == 0)
+            wsum[wv] = (uint32_t)__popcll(b);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (uint32_t v = 0; v < 1024 / kWave; ++v) {
+            before += v < wv ? wsum[v] : 0;
+            total += wsum[v];
+        }
+        if (mine)
+            tail[at + before + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] =
+                keys[i];
+        at += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *count = at;
+}
+
+template <int C>
+hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+{
+    if (f.d_ord_claims == nullptr) {
+        // scratch of the filter, kept until it is destroyed
+        hipError_t e = hipMalloc((void **)&f.d_ord_claims, kWideClaims * 8);
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&f.d_ord_pend, kWideWindow);
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&f.d_ord_tail, (size_t)kWideWindow * 8 + 8);
+        if (e != hipSuccess) {
+            // leave nothing half allocated; a later call tries again
+            for (void *q : {(void *)f.d_ord_claims, (void *)f.d_ord_pend, (void *)f.d_ord_tail})
+                if (q != nullptr)
+                    (void)hipFree(q);
+            f.d_ord_claims = nullptr;
+            f.d_ord_pend = nullptr;
+            f.d_ord_tail = nullptr;
+            return hipErrorOutOfMemory;
+        }
+        e = launch_fill_zero(f.d_ord_claims, kWideClaims, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    const KParams kp = make_kparams(f);
+    const size_t lds = align16(rank_lds_bytes(f.c, f.k)) + (size_t)kWideThreads * kOrdSlotDw * 4;
+    uint64_t *count = f.d_ord_tail + kWideWindow;
+    for (uint64_t base = 0; base < n; base += kWideWindow) {
+        const uint32_t w = (uint32_t)(n - base < kWideWindow ? n - base : kWideWindow);
+        const uint32_t grid = (w + kWideThreads - 1) / kWideThreads;
+        const uint64_t *wk = keys + base;
+        uint64_t tag = ++f.ord_tag;
+        hipLaunchKernelGGL((wide_claim_kernel<C>), dim3(grid), dim3(kWideThreads), 0, s, kp, wk, w, f.d_ord_claims,
+                           tag);
+        for (int step = 0; step < kWideSteps; ++step) {
+            const uint64_t next = step + 1 < kWideSteps ? ++f.ord_tag : 0;
+            hipLaunchKernelGGL((wide_step_kernel<C>), dim3(grid), dim3(kWideThreads), lds, s, kp, wk, w,
+                               f.d_ord_claims, f.d_ord_pend, tag, next, step == 0 ? 1 : 0);
+            tag = next;
+        }
+        hipLaunchKernelGGL(wide_tail_kernel, dim3(1), dim3(1024), 0, s, wk, w, f.d_ord_pend, f.d_ord_tail, count);
+        hipError_t e = launch_ordered_c<C>(f, f.d_ord_tail, 0, count, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipGetLastError();
+}
+
+template <int C>
+hipError_t launch_det_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+{
+    if (n < kWideWindow)
+        return launch_ordered_c<C>(f, keys, n, nullptr, s);
+    return launch_wide_c<C>(f, keys, n, s);
 }
 
 } // namespace
 
-hipError_t launch_insert_det(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+hipError_t launch_insert_det(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
     switch (f.c) {
     case 1:
-        return launch_ordered_c<1>(f, keys, n, s);
+        return launch_det_c<1>(f, keys, n, s);
     case 2:
-        return launch_ordered_c<2>(f, keys, n, s);
+        return launch_det_c<2>(f, keys, n, s);
     case 3:
-        return launch_ordered_c<3>(f, keys, n, s);
+        return launch_det_c<3>(f, keys, n, s);
     case 4:
-        return launch_ordered_c<4>(f, keys, n, s);
+        return launch_det_c<4>(f, keys, n, s);
     default:
         return hipErrorInvalidValue;
     }

@@ -151,6 +151,8 @@ def test_deterministic_insert_is_bit_exact(dev, M, c, k, cost, n):
         (3 * 8192, 2, 11, "exp", 200_000),
         (1 << 16, 3, 9, "mix", 1 << 20),
         (501, 4, 32, "mix", 20_000),  # the largest LDS: c = 4, k = 32
+        (8, 2, 6, "la", 150_000),  # windows of 2^16 keys whose steps leave most keys to the tail
+        (1 << 16, 2, 11, "la", 3 * (1 << 16) + 4321),  # several windows and a ragged one
     ],
 )
 def test_deterministic_insert_over_many_steps(dev, M, c, k, cost, n):
