@@ -180,8 +180,9 @@ bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipSt
  * (Section 3.2 applied key by key), on any layout. Each step decides
  * together every pending key that no older pending key shares a candidate
  * block with: on one workgroup below 2^16 keys, else on the whole device in
- * windows of 2^16 keys. The first large call allocates 33 MB of scratch that
- * the filter keeps until bbfc_destroy. Calls on one filter must not overlap.
+ * windows of 2^16 or 2^18 keys. The first large call allocates scratch that
+ * the filter keeps until bbfc_destroy: 33 MB, or 130 MB for filters of 2^24
+ * blocks or more. Calls on one filter must not overlap.
  * For filters with sub-arrays, bbfc_bulk_insert gives the same result
  * faster. Errors as bbfc_insert, and ENOMEM if the scratch cannot be
  * allocated. */

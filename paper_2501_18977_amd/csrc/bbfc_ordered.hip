@@ -241,9 +241,9 @@ hipError_t launch_ordered_c(const bbfc_filter &f, const uint64_t *keys, uint64_t
 
 // ------------------------------------------------------------ wide steps
 //
-// Large inputs go window by window (kWideWindow keys, in index order) through
-// the whole device. A window's keys first claim their candidate blocks in a
-// device table (kWideClaims entries, hashed by block index) with the value
+// Large inputs go window by window (in index order) through the whole
+// device. A window's keys first claim their candidate blocks in a device
+// table (hashed by block index) with the value
 // (step tag, age): atomicMax keeps the oldest claimer of the current step.
 // Then a step decides, across the grid, every pending key of the window that
 // still holds all its entries, and the keys that do not claim again for the
@@ -251,15 +251,32 @@ hipError_t launch_ordered_c(const bbfc_filter &f, const uint64_t *keys, uint64_t
 // shares one with them, exactly as in the one-workgroup kernel. A key that
 // reads a claim of the next step while checking the current one is only
 // deferred. Tags grow with every step of every call, so old entries never
-// need clearing. After kWideSteps steps the one-workgroup kernel inserts the
+// need clearing. After the plan's steps the one-workgroup kernel inserts the
 // window's remaining keys in index order. Kernel boundaries order the steps.
 
-constexpr uint32_t kWideWindow = 1u << 16;    // keys per window
-constexpr uint64_t kWideClaims = 1ull << 22;  // claim table entries (32 MB), a power of two
-constexpr int kWideSteps = 3;
+constexpr uint32_t kWideMinKeys = 1u << 16;   // inputs below this stay on one workgroup
+constexpr uint32_t kWideMaxWindow = 1u << 18; // the window's scratch is sized for this
 constexpr int kWideThreads = 256;
 
-// Claim of a key: its step's tag above its age (1 .. kWideWindow, larger is older).
+// Window, claim table and steps per filter size. A large filter has few
+// conflicts per window: long windows and three steps amortise the launches.
+// A small one has many: shorter windows and more steps leave fewer keys to
+// the one-workgroup tail. (Measured on 2^24 keys into 2^25 blocks and 2^22
+// keys into 2^17 blocks; every choice gives the same bits.)
+struct WidePlan {
+    uint32_t window;
+    uint64_t claims; // entries, a power of two
+    int steps;
+};
+
+WidePlan wide_plan(uint64_t n_blocks)
+{
+    if (n_blocks >= (1ull << 24))
+        return {1u << 18, 1ull << 24, 3};
+    return {1u << 16, 1ull << 22, 8};
+}
+
+// Claim of a key: its step's tag above its age (1 .. window, larger is older).
 __device__ __forceinline__ uint64_t claim_value(uint64_t tag, uint32_t age)
 {
     return (tag << 24) | age;
@@ -277,7 +294,7 @@ __device__ __forceinline__ void candidates(const KParams &p, uint64_t x, uint64_
 template <int C>
 __global__ __launch_bounds__(kWideThreads) void wide_claim_kernel(KParams p, const uint64_t *__restrict__ keys,
                                                                   uint32_t w, uint64_t *__restrict__ claims,
-                                                                  uint64_t tag)
+                                                                  uint64_t hmask, uint64_t tag)
 {
     const uint32_t i = blockIdx.x * kWideThreads + threadIdx.x;
     if (i >= w)
@@ -286,16 +303,15 @@ __global__ __launch_bounds__(kWideThreads) void wide_claim_kernel(KParams p, con
     candidates<C>(p, keys[i], cand);
 #pragma unroll
     for (int c = 0; c < C; ++c)
-        atomicMax((unsigned long long *)&claims[cand[c] & (kWideClaims - 1)],
-                  (unsigned long long)claim_value(tag, w - i));
+        atomicMax((unsigned long long *)&claims[cand[c] & hmask], (unsigned long long)claim_value(tag, w - i));
 }
 
 // One step over a window: thread i holds key i while it is pending.
 template <int C>
 __global__ __launch_bounds__(kWideThreads) void wide_step_kernel(KParams p, const uint64_t *__restrict__ keys,
                                                                  uint32_t w, uint64_t *__restrict__ claims,
-                                                                 uint8_t *__restrict__ pend, uint64_t tag,
-                                                                 uint64_t next_tag, int first_step)
+                                                                 uint64_t hmask, uint8_t *__restrict__ pend,
+                                                                 uint64_t tag, uint64_t next_tag, int first_step)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     uint16_t *s_rank = reinterpret_cast<uint16_t *>(lds);
@@ -320,7 +336,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_step_kernel(KParams p, cons
     if (pending) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            ready = ready && __hip_atomic_load(&claims[cand[c] & (kWideClaims - 1)], __ATOMIC_RELAXED,
+            ready = ready && __hip_atomic_load(&claims[cand[c] & hmask], __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT) == mine;
     }
     uint32_t *slot = smask + (wv * kWave + lane) * kOrdSlotDw;
@@ -384,8 +400,7 @@ __global__ __launch_bounds__(kWideThreads) void wide_step_kernel(KParams p, cons
     if (pending && !ready && next_tag != 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            atomicMax((unsigned long long *)&claims[cand[c] & (kWideClaims - 1)],
-                      (unsigned long long)claim_value(next_tag, w - i));
+            atomicMax((unsigned long long *)&claims[cand[c] & hmask], (unsigned long long)claim_value(next_tag, w - i));
     }
 }
 
@@ -423,13 +438,14 @@ __global__ __launch_bounds__(1024) void wide_tail_kernel(const uint64_t *__restr
 template <int C>
 hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
+    const WidePlan plan = wide_plan(f.M);
     if (f.d_ord_claims == nullptr) {
         // scratch of the filter, kept until it is destroyed
-        hipError_t e = hipMalloc((void **)&f.d_ord_claims, kWideClaims * 8);
+        hipError_t e = hipMalloc((void **)&f.d_ord_claims, plan.claims * 8);
         if (e == hipSuccess)
-            e = hipMalloc((void **)&f.d_ord_pend, kWideWindow);
+            e = hipMalloc((void **)&f.d_ord_pend, kWideMaxWindow);
         if (e == hipSuccess)
-            e = hipMalloc((void **)&f.d_ord_tail, (size_t)kWideWindow * 8 + 8);
+            e = hipMalloc((void **)&f.d_ord_tail, (size_t)kWideMaxWindow * 8 + 8);
         if (e != hipSuccess) {
             // leave nothing half allocated; a later call tries again
             for (void *q : {(void *)f.d_ord_claims, (void *)f.d_ord_pend, (void *)f.d_ord_tail})
@@ -440,24 +456,25 @@ hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipSt
             f.d_ord_tail = nullptr;
             return hipErrorOutOfMemory;
         }
-        e = launch_fill_zero(f.d_ord_claims, kWideClaims, s);
+        e = launch_fill_zero(f.d_ord_claims, plan.claims, s);
         if (e != hipSuccess)
             return e;
     }
     const KParams kp = make_kparams(f);
+    const uint64_t hmask = plan.claims - 1;
     const size_t lds = align16(rank_lds_bytes(f.c, f.k)) + (size_t)kWideThreads * kOrdSlotDw * 4;
-    uint64_t *count = f.d_ord_tail + kWideWindow;
-    for (uint64_t base = 0; base < n; base += kWideWindow) {
-        const uint32_t w = (uint32_t)(n - base < kWideWindow ? n - base : kWideWindow);
+    uint64_t *count = f.d_ord_tail + kWideMaxWindow;
+    for (uint64_t base = 0; base < n; base += plan.window) {
+        const uint32_t w = (uint32_t)(n - base < plan.window ? n - base : plan.window);
         const uint32_t grid = (w + kWideThreads - 1) / kWideThreads;
         const uint64_t *wk = keys + base;
         uint64_t tag = ++f.ord_tag;
         hipLaunchKernelGGL((wide_claim_kernel<C>), dim3(grid), dim3(kWideThreads), 0, s, kp, wk, w, f.d_ord_claims,
-                           tag);
-        for (int step = 0; step < kWideSteps; ++step) {
-            const uint64_t next = step + 1 < kWideSteps ? ++f.ord_tag : 0;
+                           hmask, tag);
+        for (int step = 0; step < plan.steps; ++step) {
+            const uint64_t next = step + 1 < plan.steps ? ++f.ord_tag : 0;
             hipLaunchKernelGGL((wide_step_kernel<C>), dim3(grid), dim3(kWideThreads), lds, s, kp, wk, w,
-                               f.d_ord_claims, f.d_ord_pend, tag, next, step == 0 ? 1 : 0);
+                               f.d_ord_claims, hmask, f.d_ord_pend, tag, next, step == 0 ? 1 : 0);
             tag = next;
         }
         hipLaunchKernelGGL(wide_tail_kernel, dim3(1), dim3(1024), 0, s, wk, w, f.d_ord_pend, f.d_ord_tail, count);
@@ -471,7 +488,7 @@ hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipSt
 template <int C>
 hipError_t launch_det_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
-    if (n < kWideWindow)
+    if (n < kWideMinKeys)
         return launch_ordered_c<C>(f, keys, n, nullptr, s);
     return launch_wide_c<C>(f, keys, n, s);
 }

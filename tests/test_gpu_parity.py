@@ -153,6 +153,7 @@ def test_deterministic_insert_is_bit_exact(dev, M, c, k, cost, n):
         (501, 4, 32, "mix", 20_000),  # the largest LDS: c = 4, k = 32
         (8, 2, 6, "la", 150_000),  # windows of 2^16 keys whose steps leave most keys to the tail
         (1 << 16, 2, 11, "la", 3 * (1 << 16) + 4321),  # several windows and a ragged one
+        (1 << 24, 2, 11, "la", 2 * (1 << 18) + 777),  # a large filter's plan: windows of 2^18 keys
     ],
 )
 def test_deterministic_insert_over_many_steps(dev, M, c, k, cost, n):
