@@ -63,8 +63,9 @@ def parse_args():
                     help="plain workload: bit selection strategy (Section 3.3)")
     ap.add_argument("--subarray-blocks", type=int, default=0,
                     help="plain workload: blocks per sub-array (Section 3.4; 0 = one array)")
-    ap.add_argument("--insert", choices=["racing", "bulk"], default="racing",
-                    help="plain workload: racing atomic insert, or the sequential bulk insert (needs sub-arrays)")
+    ap.add_argument("--insert", choices=["racing", "bulk", "exact"], default="racing",
+                    help="plain workload: racing atomic insert, the sequential bulk insert (needs sub-arrays), "
+                         "or the sequential insert on any layout (bbfc_insert_deterministic)")
     ap.add_argument("--filters", type=int, default=256, help="batch workload: number of filters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
@@ -898,12 +899,14 @@ def main():
     def do_insert(stream):
         if args.insert == "bulk":
             filt.bulk_insert(keys[:n], workspace=ws, stream=stream)
+        elif args.insert == "exact":
+            filt.insert_deterministic(keys[:n], stream)
         else:
             filt.insert(keys[:n], stream)
 
     stream = torch.cuda.current_stream()
     tuned = None
-    if not args.no_tune and args.insert == "bulk":
+    if not args.no_tune and args.insert in ("bulk", "exact"):
         do_insert(stream)
         tuned = {"query": filt.tune(bbfc.OP_QUERY, keys, out=out, reps=2, stream=stream)}
     elif not args.no_tune:
