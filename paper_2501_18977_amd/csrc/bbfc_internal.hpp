@@ -34,7 +34,7 @@ struct bbfc_filter {
     // scratch of the sequential insert on large inputs, allocated on first use
     uint64_t *d_ord_claims = nullptr; // claim table
     uint8_t *d_ord_pend = nullptr;    // pending flags of a window
-    uint64_t *d_ord_tail = nullptr;   // a window's remaining keys, then their count
+    uint64_t *d_ord_tail = nullptr;   // a window's remaining keys, their count, the count the last step saw
     uint64_t ord_tag = 0;             // last step tag used on this filter
 };
 

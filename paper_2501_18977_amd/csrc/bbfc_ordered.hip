@@ -294,9 +294,12 @@ __device__ __forceinline__ void candidates(const KParams &p, uint64_t x, uint64_
 template <int C>
 __global__ __launch_bounds__(kWideThreads) void wide_claim_kernel(KParams p, const uint64_t *__restrict__ keys,
                                                                   uint32_t w, uint64_t *__restrict__ claims,
-                                                                  uint64_t hmask, uint64_t tag)
+                                                                  uint64_t hmask, uint64_t tag,
+                                                                  unsigned long long *__restrict__ left)
 {
     const uint32_t i = blockIdx.x * kWideThreads + threadIdx.x;
+    if (i == 0)
+        *left = 0; // the window's last step counts its keys still pending here
     if (i >= w)
         return;
     uint64_t cand[C];
@@ -311,7 +314,8 @@ template <int C>
 __global__ __launch_bounds__(kWideThreads) void wide_step_kernel(KParams p, const uint64_t *__restrict__ keys,
                                                                  uint32_t w, uint64_t *__restrict__ claims,
                                                                  uint64_t hmask, uint8_t *__restrict__ pend,
-                                                                 uint64_t tag, uint64_t next_tag, int first_step)
+                                                                 uint64_t tag, uint64_t next_tag, int first_step,
+                                                                 unsigned long long *__restrict__ left)
 {
     extern __shared__ __align__(16) uint8_t lds[];
     uint16_t *s_rank = reinterpret_cast<uint16_t *>(lds);
@@ -394,9 +398,15 @@ __global__ __launch_bounds__(kWideThreads) void wide_step_kernel(KParams p, cons
         }
     }
 
-    // the others stay pending and claim for the next step
+    // the others stay pending and claim for the next step (after the last
+    // step, they are counted for the tail)
     if (i < w)
         pend[i] = pending && !ready;
+    if (next_tag == 0) {
+        const uint64_t lb = __ballot(pending && !ready);
+        if (lane == 0 && lb != 0)
+            atomicAdd(left, (unsigned long long)__popcll(lb));
+    }
     if (pending && !ready && next_tag != 0) {
 #pragma unroll
         for (int c = 0; c < C; ++c)
@@ -405,29 +415,58 @@ __global__ __launch_bounds__(kWideThreads) void wide_step_kernel(KParams p, cons
 }
 
 // The window's keys still pending, in index order, into tail[0 .. *count).
+// Each thread reads 16 flags at a time; nothing is read when the last step
+// left no key.
 __global__ __launch_bounds__(1024) void wide_tail_kernel(const uint64_t *__restrict__ keys, uint32_t w,
                                                          const uint8_t *__restrict__ pend,
+                                                         const unsigned long long *__restrict__ left,
                                                          uint64_t *__restrict__ tail, uint64_t *__restrict__ count)
 {
     __shared__ uint32_t wsum[1024 / kWave];
+    if (*left == 0) {
+        if (threadIdx.x == 0)
+            *count = 0;
+        return;
+    }
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave;
     uint32_t at = 0; // keys written by earlier chunks
-    for (uint32_t base = 0; base < w; base += 1024) {
-        const uint32_t i = base + threadIdx.x;
-        const bool mine = i < w && pend[i];
-        const uint64_t b = __ballot(mine);
-        if (lane == 0)
-            wsum[wv] = (uint32_t)__popcll(b);
+    for (uint32_t base = 0; base < w; base += 1024 * 16) {
+        const uint32_t i0 = base + threadIdx.x * 16;
+        uint32_t flags = 0; // bit j: key i0 + j is pending
+        if (i0 + 16 <= w) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(pend + i0);
+            const uint32_t word[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                flags |= ((word[j / 4] >> (8 * (j % 4))) & 0xFF ? 1u : 0u) << j;
+        } else {
+            for (uint32_t j = 0; i0 + j < w && j < 16; ++j)
+                flags |= (pend[i0 + j] ? 1u : 0u) << j;
+        }
+        // exclusive prefix of the per-thread counts over the workgroup
+        const uint32_t mine = (uint32_t)__popc(flags);
+        uint32_t x = mine;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t y = (uint32_t)__shfl_up((int)x, off);
+            if (lane >= (uint32_t)off)
+                x += y;
+        }
+        if (lane == kWave - 1)
+            wsum[wv] = x;
         __syncthreads();
         uint32_t before = 0, total = 0;
         for (uint32_t v = 0; v < 1024 / kWave; ++v) {
             before += v < wv ? wsum[v] : 0;
             total += wsum[v];
         }
-        if (mine)
-            tail[at + before + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0))] =
-                keys[i];
+        uint32_t o = at + before + x - mine;
+        while (flags != 0) {
+            const uint32_t j = (uint32_t)__builtin_ctz(flags);
+            tail[o++] = keys[i0 + j];
+            flags &= flags - 1;
+        }
         at += total;
         __syncthreads();
     }
@@ -445,7 +484,7 @@ hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipSt
         if (e == hipSuccess)
             e = hipMalloc((void **)&f.d_ord_pend, kWideMaxWindow);
         if (e == hipSuccess)
-            e = hipMalloc((void **)&f.d_ord_tail, (size_t)kWideMaxWindow * 8 + 8);
+            e = hipMalloc((void **)&f.d_ord_tail, (size_t)kWideMaxWindow * 8 + 16);
         if (e != hipSuccess) {
             // leave nothing half allocated; a later call tries again
             for (void *q : {(void *)f.d_ord_claims, (void *)f.d_ord_pend, (void *)f.d_ord_tail})
@@ -464,20 +503,22 @@ hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipSt
     const uint64_t hmask = plan.claims - 1;
     const size_t lds = align16(rank_lds_bytes(f.c, f.k)) + (size_t)kWideThreads * kOrdSlotDw * 4;
     uint64_t *count = f.d_ord_tail + kWideMaxWindow;
+    unsigned long long *left = reinterpret_cast<unsigned long long *>(f.d_ord_tail + kWideMaxWindow + 1);
     for (uint64_t base = 0; base < n; base += plan.window) {
         const uint32_t w = (uint32_t)(n - base < plan.window ? n - base : plan.window);
         const uint32_t grid = (w + kWideThreads - 1) / kWideThreads;
         const uint64_t *wk = keys + base;
         uint64_t tag = ++f.ord_tag;
         hipLaunchKernelGGL((wide_claim_kernel<C>), dim3(grid), dim3(kWideThreads), 0, s, kp, wk, w, f.d_ord_claims,
-                           hmask, tag);
+                           hmask, tag, left);
         for (int step = 0; step < plan.steps; ++step) {
             const uint64_t next = step + 1 < plan.steps ? ++f.ord_tag : 0;
             hipLaunchKernelGGL((wide_step_kernel<C>), dim3(grid), dim3(kWideThreads), lds, s, kp, wk, w,
-                               f.d_ord_claims, hmask, f.d_ord_pend, tag, next, step == 0 ? 1 : 0);
+                               f.d_ord_claims, hmask, f.d_ord_pend, tag, next, step == 0 ? 1 : 0, left);
             tag = next;
         }
-        hipLaunchKernelGGL(wide_tail_kernel, dim3(1), dim3(1024), 0, s, wk, w, f.d_ord_pend, f.d_ord_tail, count);
+        hipLaunchKernelGGL(wide_tail_kernel, dim3(1), dim3(1024), 0, s, wk, w, f.d_ord_pend, left, f.d_ord_tail,
+                           count);
         hipError_t e = launch_ordered_c<C>(f, f.d_ord_tail, 0, count, s);
         if (e != hipSuccess)
             return e;
