@@ -259,7 +259,8 @@ constexpr uint32_t kWideMaxWindow = 1u << 18; // the window's scratch is sized f
 constexpr int kWideThreads = 256;
 
 // Window, claim table and steps per filter size. A large filter has few
-// conflicts per window: long windows and three steps amortise the launches.
+// conflicts per window: long windows amortise the launches, and a fourth
+// step usually leaves no key to the tail.
 // A small one has many: shorter windows and more steps leave fewer keys to
 // the one-workgroup tail. (Measured on 2^24 keys into 2^25 blocks and 2^22
 // keys into 2^17 blocks; every choice gives the same bits.)
@@ -272,7 +273,7 @@ struct WidePlan {
 WidePlan wide_plan(uint64_t n_blocks)
 {
     if (n_blocks >= (1ull << 24))
-        return {1u << 18, 1ull << 24, 3};
+        return {1u << 18, 1ull << 24, 4};
     return {1u << 16, 1ull << 22, 8};
 }
 
