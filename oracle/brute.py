@@ -95,8 +95,30 @@ class BruteFilter:
         return any(F <= self.blocks[b] for b in self.candidates(x))
 
     def words(self) -> list[int]:
-        out = []
+        return _words(self.blocks)
+
+    def envelope_words(self, keys) -> list[int]:
+        """Every key's F(x) added to every one of its candidates (as sets),
+        then converted to words: the largest bit set any schedule of racing
+        inserts of these keys could produce (Sections 3.1, 3.2)."""
+        env: list[set[int]] = [set() for _ in range(self.M)]
+        for x in keys:
+            F = self.F(int(x))
+            for b in self.candidates(int(x)):
+                env[b] |= F
+        return _words(env)
+
+    def load_counts(self) -> dict[int, int]:
+        """Number of blocks per count of set bits |F'| (App. C, load histogram figure)."""
+        out: dict[int, int] = {}
         for S in self.blocks:
-            for w in range(8):
-                out.append(sum(1 << (f - 64 * w) for f in S if f // 64 == w))
+            out[len(S)] = out.get(len(S), 0) + 1
         return out
+
+
+def _words(blocks: list[set[int]]) -> list[int]:
+    out = []
+    for S in blocks:
+        for w in range(8):
+            out.append(sum(1 << (f - 64 * w) for f in S if f // 64 == w))
+    return out
