@@ -175,6 +175,20 @@ bbfc_status bbfc_destroy(bbfc_handle h);
  * keys with n > 0), EHIP. */
 bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipStream_t stream);
 
+/* Checking hook: bbfc_insert (same kernels' schedule, shape and keys in
+ * flight) that also records each key's decision in d_decisions[0..n)
+ * (device memory, caller-owned, one byte per key, must not overlap the
+ * keys): the index i in [0, choices) of the candidate h_(i+1)(x) whose block
+ * received F(x), or BBFC_DECISION_PRESENT (0xFF) when the key found F(x)
+ * already held by a candidate and wrote nothing (Sections 3.1, 3.2). With
+ * these, the filter after the call is the OR, over the keys that wrote, of
+ * F(x) placed in the recorded candidate, on top of what the filter held
+ * before. bbfc_insert itself records nothing. Errors as bbfc_insert, and
+ * EINVAL for null or overlapping decisions with n > 0. */
+#define BBFC_DECISION_PRESENT 0xFFu
+bbfc_status bbfc_insert_recorded(bbfc_handle h, const uint64_t *d_keys, uint64_t n, uint8_t *d_decisions,
+                                 hipStream_t stream);
+
 /* Insert d_keys[0..n) with exactly the sequential semantics: the result is
  * the filter obtained by inserting the keys one at a time in index order
  * (Section 3.2 applied key by key), on any layout. Each step decides

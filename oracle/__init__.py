@@ -79,6 +79,8 @@ def _load():
     lib.bbo_derive_multipliers.restype = None
     lib.bbo_envelope.argtypes = [_u64p, _Lp, u32, u32, i32, _u64p, _u64p, _u64p, u64]
     lib.bbo_envelope.restype = None
+    lib.bbo_place.argtypes = [_u64p, _Lp, u32, u32, i32, _u64p, _u64p, _u64p, ctypes.c_void_p, u64, u64, u64]
+    lib.bbo_place.restype = u64
     lib.bbo_block_loads.argtypes = [_u64p, u64, _u64p]
     lib.bbo_block_loads.restype = None
     lib.bbo_conditional_fpr.argtypes = [_u64p, _Lp, u32, u32, i32, _u64p, _u64p, u64]
@@ -223,6 +225,31 @@ class OracleFilter:
         _load().bbo_envelope(_ptr(env), ctypes.byref(self.layout), self.c, self.k, self.distinct, _ptr(self.block_mult),
                              _ptr(self.bit_mult), _ptr(keys), len(keys))
         return env
+
+    def place(self, keys, decisions, words: np.ndarray | None = None, part_mod: int = 1,
+              part_rem: int = 0) -> np.ndarray:
+        """Words after placing F(keys[t]) in candidate decisions[t] (< c) for
+        every key that wrote (decisions[t] >= c: none), on top of `words`
+        (default: an empty filter). Only blocks b with b % part_mod ==
+        part_rem are written."""
+        keys = _u64(keys)
+        dec = np.ascontiguousarray(decisions, dtype=np.uint8)
+        assert len(dec) == len(keys) and part_mod >= 1 and 0 <= part_rem < part_mod
+        out = np.zeros_like(self.words) if words is None else _u64(words).copy()
+        _load().bbo_place(_ptr(out), ctypes.byref(self.layout), self.c, self.k, self.distinct,
+                          _ptr(self.block_mult), _ptr(self.bit_mult), _ptr(keys), dec.ctypes.data, len(keys),
+                          part_mod, part_rem)
+        return out
+
+    def insert_recording(self, keys) -> np.ndarray:
+        """Sequential insert of keys in order, returning each key's decision:
+        the chosen candidate index, or 0xFF when the key was already present."""
+        keys = _u64(keys)
+        dec = np.empty(len(keys), dtype=np.uint8)
+        for t, x in enumerate(keys):
+            r = self.insert_one(int(x))
+            dec[t] = 0xFF if r < 0 else r
+        return dec
 
     def block_loads(self, words: np.ndarray | None = None) -> np.ndarray:
         w = self.words if words is None else _u64(words)

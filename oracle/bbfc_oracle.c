@@ -359,6 +359,34 @@ void bbo_envelope(uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int 
     }
 }
 
+/* A filter from per-key decisions (Sections 3.1, 3.2): insert(x) either
+ * finds F(x) already held by a candidate and writes nothing, or sets F(x) in
+ * exactly one candidate. So a build whose decisions are known is the OR,
+ * over the keys that wrote, of F(x) placed in the candidate they name.
+ * decision[t] = i < c names candidate i (block h_{i+1}(keys[t])); any value
+ * >= c means the key wrote nothing. Only blocks b with b mod part_mod ==
+ * part_rem are written (part_mod 1: every block), so a large build can be
+ * checked one residue class at a time. Returns the number of keys placed. */
+uint64_t bbo_place(uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct,
+                   const uint64_t *block_mult, const uint64_t *bit_mult, const uint64_t *keys,
+                   const uint8_t *decision, uint64_t n, uint64_t part_mod, uint64_t part_rem)
+{
+    uint64_t m[8];
+    uint64_t placed = 0;
+    for (uint64_t t = 0; t < n; t++) {
+        if (decision[t] >= c)
+            continue;
+        uint64_t b = bbo_block(L, block_mult[decision[t]], keys[t]);
+        if (b % part_mod != part_rem)
+            continue;
+        bbo_mask_sel(distinct, bit_mult, k, keys[t], m);
+        for (int w = 0; w < 8; w++)
+            W[8 * b + w] |= m[w];
+        placed++;
+    }
+    return placed;
+}
+
 /* Histogram of set bits per block: hist[P] = number of blocks with P bits
  * set, P in [0, 512]. */
 void bbo_block_loads(const uint64_t *W, uint64_t M, uint64_t *hist)

@@ -108,6 +108,16 @@ class BruteFilter:
                 env[b] |= F
         return _words(env)
 
+    def placed_words(self, keys, decisions) -> list[int]:
+        """Blocks as sets after adding each key's F(x) to the one candidate
+        its decision names (decision >= c: the key added nothing), Sections
+        3.1 and 3.2; converted to words."""
+        blocks: list[set[int]] = [set() for _ in range(self.M)]
+        for x, d in zip(keys, decisions):
+            if int(d) < self.c:
+                blocks[self.candidates(int(x))[int(d)]] |= self.F(int(x))
+        return _words(blocks)
+
     def load_counts(self) -> dict[int, int]:
         """Number of blocks per count of set bits |F'| (App. C, load histogram figure)."""
         out: dict[int, int] = {}

@@ -46,6 +46,7 @@ BITS_RANDOM, BITS_DISTINCT = 0, 1
 _BITS_BY_NAME = {"random": BITS_RANDOM, "distinct": BITS_DISTINCT}
 OP_INSERT, OP_QUERY = 0, 1
 OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT = 1, 2
+DECISION_PRESENT = 0xFF
 _COST_BY_NAME = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -116,6 +117,7 @@ def lib() -> ctypes.CDLL:
         "bbfc_destroy": (_st, [_vp]),
         "bbfc_insert": (_st, [_vp, _vp, _u64, _vp]),
         "bbfc_insert_deterministic": (_st, [_vp, _vp, _u64, _vp]),
+        "bbfc_insert_recorded": (_st, [_vp, _vp, _u64, _vp, _vp]),
         "bbfc_query": (_st, [_vp, _vp, _u64, _vp, _vp]),
         "bbfc_clear": (_st, [_vp, _vp]),
         "bbfc_upload": (_st, [_vp, _vp, _vp]),
@@ -368,6 +370,21 @@ class Filter:
     def insert(self, keys, stream=None) -> None:
         keys = _device_u64(keys, "keys")
         _check(lib().bbfc_insert(self.handle, keys.data_ptr(), keys.numel(), _stream_handle(stream)))
+
+    def insert_recorded(self, keys, out=None, stream=None):
+        """The racing insert, also returning each key's decision as a uint8
+        GPU tensor: the candidate index that received the key's bits, or
+        DECISION_PRESENT when a candidate already held them."""
+        import torch
+
+        keys = _device_u64(keys, "keys")
+        n = keys.numel()
+        if out is None:
+            out = torch.empty(max(n, 1), dtype=torch.uint8, device=keys.device)
+        elif out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
+            raise ValueError("decisions need a contiguous uint8 GPU tensor of n entries")
+        _check(lib().bbfc_insert_recorded(self.handle, keys.data_ptr(), n, out.data_ptr(), _stream_handle(stream)))
+        return out[:n]
 
     def insert_deterministic(self, keys, stream=None) -> None:
         keys = _device_u64(keys, "keys")

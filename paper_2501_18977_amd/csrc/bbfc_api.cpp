@@ -387,6 +387,26 @@ bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipSt
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching insert");
 }
 
+bbfc_status bbfc_insert_recorded(bbfc_handle h, const uint64_t *d_keys, uint64_t n, uint8_t *d_decisions,
+                                 hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (n == 0)
+        return BBFC_OK;
+    if (d_keys == nullptr || d_decisions == nullptr)
+        return fail(BBFC_EINVAL, "null keys or decisions with n = %llu", (unsigned long long)n);
+    if (n > kMaxKeys)
+        return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
+    const uintptr_t k0 = (uintptr_t)d_keys, k1 = k0 + n * 8;
+    const uintptr_t d0 = (uintptr_t)d_decisions, d1 = d0 + n;
+    if (k0 < d1 && d0 < k1)
+        return fail(BBFC_EINVAL, "decisions overlap the keys");
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_insert_recorded(*h, d_keys, n, d_decisions, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching recorded insert");
+}
+
 bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipStream_t stream)
 {
     if (h == nullptr)

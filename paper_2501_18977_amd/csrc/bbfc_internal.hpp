@@ -67,6 +67,9 @@ size_t rank_lds_bytes(uint32_t c, uint32_t k);
 uint64_t insert_inflight(const bbfc_filter &f);
 
 hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
+// The racing insert that also writes each key's decision (bbfc_insert_recorded).
+hipError_t launch_insert_recorded(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint8_t *decisions,
+                                  hipStream_t s);
 hipError_t launch_insert_det(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out,
                         hipStream_t s);

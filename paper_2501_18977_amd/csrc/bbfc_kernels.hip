@@ -57,6 +57,23 @@ __global__ __launch_bounds__(kWGSize) void insert_kernel(KParams p, Src keys, ui
         insert_tiles<C, LPK, T>(p, s_rank, keys, n, u * T * kTile, lane, s_mask[wv], s_blk[wv]);
 }
 
+// insert_kernel that also writes each key's decision to rec[t] (see
+// insert_tiles): a checking aid with the same schedule, never the timed kernel.
+template <int C, int LPK, int T, typename Src>
+__global__ __launch_bounds__(kWGSize) void insert_recorded_kernel(KParams p, Src keys, uint64_t n, uint64_t n_units,
+                                                                  uint8_t *__restrict__ rec)
+{
+    __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
+    __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
+    extern __shared__ uint16_t s_rank[];
+    load_rank_table<C>(p, s_rank);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerWG;
+    for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerWG + wv; u < n_units; u += n_waves)
+        insert_tiles<C, LPK, T, Src, true>(p, s_rank, keys, n, u * T * kTile, lane, s_mask[wv], s_blk[wv], rec);
+}
+
 __global__ void fill_zero_kernel(uint64_t *p, uint64_t n_words)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -152,8 +169,8 @@ uint64_t grid_for(K kernel, size_t dyn_lds, int num_cus, int wgs_per_cu, uint64_
     return wgs < 1 ? 1 : wgs;
 }
 
-template <int C, int LPK, int T, typename Src>
-hipError_t insert_launch(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s)
+template <int C, int LPK, int T, typename Src, bool REC = false>
+hipError_t insert_launch(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr)
 {
     const uint64_t n_units = (n + (uint64_t)T * kTile - 1) / ((uint64_t)T * kTile);
     const size_t lds = rank_lds_bytes(f.c, f.k);
@@ -163,10 +180,17 @@ hipError_t insert_launch(const bbfc_filter &f, const Src &keys, uint64_t n, hipS
     uint64_t need = (n_units + kWavesPerWG - 1) / kWavesPerWG;
     if (cap_wgs < need)
         need = cap_wgs;
-    const uint64_t wgs =
-        grid_for(insert_kernel<C, LPK, T, Src>, lds, f.num_cus, f.shape[BBFC_OP_INSERT].wgs_per_cu, need);
-    hipLaunchKernelGGL((insert_kernel<C, LPK, T, Src>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s, make_kparams(f),
-                       keys, n, n_units);
+    if constexpr (REC) {
+        const uint64_t wgs = grid_for(insert_recorded_kernel<C, LPK, T, Src>, lds, f.num_cus,
+                                      f.shape[BBFC_OP_INSERT].wgs_per_cu, need);
+        hipLaunchKernelGGL((insert_recorded_kernel<C, LPK, T, Src>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s,
+                           make_kparams(f), keys, n, n_units, rec);
+    } else {
+        const uint64_t wgs =
+            grid_for(insert_kernel<C, LPK, T, Src>, lds, f.num_cus, f.shape[BBFC_OP_INSERT].wgs_per_cu, need);
+        hipLaunchKernelGGL((insert_kernel<C, LPK, T, Src>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s,
+                           make_kparams(f), keys, n, n_units);
+    }
     return hipGetLastError();
 }
 
@@ -188,15 +212,15 @@ constexpr size_t insert_static_lds(int C, int T)
     return (size_t)kWavesPerWG * T * kTile * (kSlotDw * sizeof(uint32_t) + C * sizeof(uint64_t));
 }
 
-template <int C, typename Src>
-hipError_t insert_c(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s)
+template <int C, typename Src, bool REC = false>
+hipError_t insert_c(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr)
 {
     // two tiles per wave only where their LDS and the rank table fit a workgroup
     int tpw = f.shape[BBFC_OP_INSERT].tiles_per_wave;
     if (tpw == 2 && insert_static_lds(C, 2) + rank_lds_bytes(f.c, f.k) > f.max_lds)
         tpw = 1;
     return with_shape(f.shape[BBFC_OP_INSERT].lanes_per_key, tpw, [&](auto L, auto T) {
-        return insert_launch<C, decltype(L)::value, decltype(T)::value, Src>(f, keys, n, s);
+        return insert_launch<C, decltype(L)::value, decltype(T)::value, Src, REC>(f, keys, n, s, rec);
     });
 }
 
@@ -213,18 +237,18 @@ hipError_t query_c(const bbfc_filter &f, const Src &keys, uint64_t n, uint64_t *
     });
 }
 
-template <typename Src>
-hipError_t insert_any(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s)
+template <typename Src, bool REC = false>
+hipError_t insert_any(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr)
 {
     switch (f.c) {
     case 1:
-        return insert_c<1>(f, keys, n, s);
+        return insert_c<1, Src, REC>(f, keys, n, s, rec);
     case 2:
-        return insert_c<2>(f, keys, n, s);
+        return insert_c<2, Src, REC>(f, keys, n, s, rec);
     case 3:
-        return insert_c<3>(f, keys, n, s);
+        return insert_c<3, Src, REC>(f, keys, n, s, rec);
     case 4:
-        return insert_c<4>(f, keys, n, s);
+        return insert_c<4, Src, REC>(f, keys, n, s, rec);
     default:
         return hipErrorInvalidValue;
     }
@@ -274,6 +298,12 @@ KmerKeys make_kmer_src(const uint64_t *seq, uint64_t seg_len, uint32_t q)
 hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
     return insert_any(f, ArrayKeys{keys}, n, s);
+}
+
+hipError_t launch_insert_recorded(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint8_t *decisions,
+                                  hipStream_t s)
+{
+    return insert_any<ArrayKeys, true>(f, ArrayKeys{keys}, n, s, decisions);
 }
 
 hipError_t launch_insert_kmers(const bbfc_filter &f, const uint64_t *seq, uint64_t n_segments, uint64_t seg_len, uint32_t q, hipStream_t s)

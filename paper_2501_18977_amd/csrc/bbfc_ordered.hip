@@ -222,21 +222,35 @@ __global__ __launch_bounds__(kOrdThreads) void insert_ordered_kernel(KParams p, 
     }
 }
 
+// Checks that the one-workgroup kernel's LDS fits and allows it; done before
+// anything is enqueued, so a failure leaves the filter untouched.
+template <int C>
+hipError_t prepare_ordered_c(const bbfc_filter &f)
+{
+    const size_t lds = ordered_lds_bytes(rank_lds_bytes(f.c, f.k));
+    if (f.max_lds < lds)
+        return hipErrorInvalidValue;
+    return hipFuncSetAttribute((const void *)insert_ordered_kernel<C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+// Enqueues the one-workgroup kernel (after prepare_ordered_c).
+template <int C>
+hipError_t enqueue_ordered_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, const uint64_t *n_dev,
+                             hipStream_t s)
+{
+    const size_t rank = rank_lds_bytes(f.c, f.k);
+    hipLaunchKernelGGL((insert_ordered_kernel<C>), dim3(1), dim3(kOrdThreads), ordered_lds_bytes(rank), s,
+                       make_kparams(f), keys, n, n_dev, (uint32_t)rank);
+    return hipGetLastError();
+}
+
 template <int C>
 hipError_t launch_ordered_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, const uint64_t *n_dev,
                             hipStream_t s)
 {
-    const size_t rank = rank_lds_bytes(f.c, f.k);
-    const size_t lds = ordered_lds_bytes(rank);
-    if (f.max_lds < lds)
-        return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void *)insert_ordered_kernel<C>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL((insert_ordered_kernel<C>), dim3(1), dim3(kOrdThreads), lds, s, make_kparams(f), keys, n,
-                       n_dev, (uint32_t)rank);
-    return hipGetLastError();
+    const hipError_t e = prepare_ordered_c<C>(f);
+    return e != hipSuccess ? e : enqueue_ordered_c<C>(f, keys, n, n_dev, s);
 }
 
 // ------------------------------------------------------------ wide steps
@@ -479,6 +493,10 @@ template <int C>
 hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
     const WidePlan plan = wide_plan(f.M);
+    // the tail kernel of every window must fit before the first window runs
+    hipError_t e0 = prepare_ordered_c<C>(f);
+    if (e0 != hipSuccess)
+        return e0;
     if (f.d_ord_claims == nullptr) {
         // scratch of the filter, kept until it is destroyed
         hipError_t e = hipMalloc((void **)&f.d_ord_claims, plan.claims * 8);
@@ -520,7 +538,7 @@ hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipSt
         }
         hipLaunchKernelGGL(wide_tail_kernel, dim3(1), dim3(1024), 0, s, wk, w, f.d_ord_pend, left, f.d_ord_tail,
                            count);
-        hipError_t e = launch_ordered_c<C>(f, f.d_ord_tail, 0, count, s);
+        hipError_t e = enqueue_ordered_c<C>(f, f.d_ord_tail, 0, count, s);
         if (e != hipSuccess)
             return e;
     }

@@ -368,9 +368,15 @@ __device__ __forceinline__ uint64_t pick(const uint64_t (&B)[C][KW], int i, int 
 }
 
 // Racing insert of T consecutive tiles whose first key is keys[base].
-template <int C, int LPK, int T, typename Src>
+// REC: rec[t] also receives key t's decision, the index of the candidate
+// that received F(x) or kPresent when a candidate already held it (a
+// checking aid; the kernels that are timed do not record).
+constexpr uint8_t kPresent = 0xFF;
+
+template <int C, int LPK, int T, typename Src, bool REC = false>
 __device__ __forceinline__ void insert_tiles(const KParams &p, const uint16_t *rank, const Src &keys, uint64_t n,
-                                    uint64_t base, uint32_t lane, uint32_t *smask, uint64_t *sblk)
+                                    uint64_t base, uint32_t lane, uint32_t *smask, uint64_t *sblk,
+                                    uint8_t *__restrict__ rec = nullptr)
 {
     using L = Lanes<LPK>;
     constexpr int R = L::kRounds;
@@ -399,6 +405,10 @@ __device__ __forceinline__ void insert_tiles(const KParams &p, const uint16_t *r
             mask_words<KW>(smask + tt * kTile * kSlotDw, t, w0, m);
             const JA<C> ja = reduce_ja<C, LPK, KW>(B[tt][r], m);
             const int best = decide<C>(ja, rank);
+            if constexpr (REC) {
+                if (w0 == 0 && base + (uint64_t)tt * kTile + t < n)
+                    rec[base + (uint64_t)tt * kTile + t] = best < 0 ? kPresent : (uint8_t)best;
+            }
             if (best >= 0 && base + (uint64_t)tt * kTile + t < n) {
                 const uint64_t blk = sblk[tt * kTile * C + t * C + best];
 #pragma unroll

@@ -109,6 +109,72 @@ def test_plain_filter_2_pow_30_keys(dev):
         del keys
 
 
+def test_plain_filter_2_pow_30_racing_against_sequential(dev):
+    """The headline filter built three ways from the same 2^30 keys:
+
+    * the racing insert (the timed kernel);
+    * the racing insert that records each key's decision: every decision
+      names a candidate or 'present', and on the blocks of one residue class
+      (block index = 17 mod 64, 2^19 blocks) the filter equals the oracle's
+      placement of the decided keys' masks, word for word;
+    * the sequential insert (one key at a time in index order).
+
+    The racing filter's false-positive rate must stay within 2% of the
+    sequential build's (Section 4.1): the conditional estimate over 2^24
+    never-inserted keys within 2% relative, and the raw false-positive counts
+    over the 2^30 never-inserted keys within 4 binomial sigma."""
+    N, M, C, K = 1 << 30, 1 << 25, 2, 11
+    keys = torch.empty(2 * N, dtype=torch.int64, device=dev)
+    workload.device_keys(0, 0, N, out=keys[:N])
+    workload.device_keys(0, N, N, out=keys[N:])
+    f = bbfc.Filter(M, C, K, "la", seed=0)
+    try:
+        f.set_shape(bbfc.OP_INSERT, 8, 1)
+        f.set_shape(bbfc.OP_QUERY, 8, 2)
+        ref = oracle.OracleFilter(M, C, K, oracle.COST_LA, None, seed=0)
+        assert list(f.params.block_mult) == [int(v) for v in ref.block_mult]
+
+        print("racing vs sequential: racing build", flush=True)
+        f.insert(keys[:N])
+        fp_race = int(np.bitwise_count(f.query(keys[N:]).cpu().numpy().view(np.uint64)).sum())
+        words_race = f.download()
+
+        print("racing vs sequential: recorded racing build", flush=True)
+        f.clear()
+        dec_d = f.insert_recorded(keys[:N])
+        words_rec = f.download()
+        dec = dec_d.cpu().numpy()
+        del dec_d
+        bad = (dec >= C) & (dec != 0xFF)
+        assert not bad.any(), f"{int(bad.sum())} decisions name no candidate"
+        host_keys = keys[:N].cpu().numpy().view(np.uint64)
+        placed = ref.place(host_keys, dec, part_mod=64, part_rem=17).reshape(M, 8)
+        sel = np.arange(17, M, 64)
+        assert np.array_equal(placed[sel], words_rec.reshape(M, 8)[sel]), "recorded decisions do not rebuild the blocks"
+        print(f"racing vs sequential: {int((dec == 0xFF).sum())} keys decided present, "
+              f"{len(sel)} blocks rebuilt from the decisions", flush=True)
+        del placed, host_keys, dec, words_rec
+
+        print("racing vs sequential: sequential build", flush=True)
+        f.clear()
+        f.insert_deterministic(keys[:N])
+        fp_seq = int(np.bitwise_count(f.query(keys[N:]).cpu().numpy().view(np.uint64)).sum())
+        words_seq = f.download()
+
+        neg = workload.splitmix64_keys(0, N + 777, 1 << 24)
+        est_race = ref.conditional_fpr(neg, words=words_race)
+        est_seq = ref.conditional_fpr(neg, words=words_seq)
+        rel = abs(est_race - est_seq) / est_seq
+        sd = math.sqrt(fp_race + fp_seq)
+        print(f"racing vs sequential: conditional FPR {est_race:.5e} vs {est_seq:.5e} ({rel:.3%}); raw FP over 2^30 "
+              f"negatives {fp_race} vs {fp_seq} ({(fp_race - fp_seq) / sd:+.2f} sigma)", flush=True)
+        assert rel < 0.02
+        assert abs(fp_race - fp_seq) < 4 * sd
+    finally:
+        f.close()
+        del keys
+
+
 def read_bases(packed: np.ndarray, reads: np.ndarray, length: int) -> np.ndarray:
     """Bases (one per byte) of the given reads of a packed read set."""
     start = reads.astype(np.int64) * length

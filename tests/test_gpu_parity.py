@@ -6,9 +6,13 @@ on the same seeded inputs:
 * query: bit-exact on filters the oracle built (uploaded to the device);
 * deterministic insert: filter words bit-exact with the oracle's;
 * racing insert with one choice: bit-exact (the result is order-free);
-* racing insert with choices: zero false negatives, every set bit lies in
-  the oracle's envelope (each key's mask in all of its candidates), and the
-  false-positive rate within 2% relative of the oracle's sequential build.
+* racing insert with choices: every key's recorded decision names one of
+  its candidates (or "present"), and the filter equals, word for word, the
+  oracle's placement of each key's mask into the candidate it names; every
+  "present" key is held by a candidate; zero false negatives; every set bit
+  lies in the oracle's envelope (each key's mask in all of its candidates);
+  and the false-positive rate is within 2% relative of the oracle's
+  sequential build.
 """
 
 import math
@@ -154,6 +158,8 @@ def test_deterministic_insert_is_bit_exact(dev, M, c, k, cost, n):
         (8, 2, 6, "la", 150_000),  # windows of 2^16 keys whose steps leave most keys to the tail
         (1 << 16, 2, 11, "la", 3 * (1 << 16) + 4321),  # several windows and a ragged one
         (1 << 24, 2, 11, "la", 2 * (1 << 18) + 777),  # a large filter's plan: windows of 2^18 keys
+        (1 << 14, 4, 20, "la", (1 << 17) + 777),  # four choices through the device-wide steps
+        (777, 3, 8, "mix", (1 << 16) + 1),  # odd M, c = 3, one key past a whole window
     ],
 )
 def test_deterministic_insert_over_many_steps(dev, M, c, k, cost, n):
@@ -217,17 +223,80 @@ def _fpr_gate(ref, gpu_words, n_keys, seed, dev, gpu):
     return est_gpu, est_ref
 
 
-@pytest.mark.parametrize("M,c,k,cost,n", [
+def check_decisions(ref, keys: np.ndarray, dec: np.ndarray, words: np.ndarray) -> None:
+    """Validity of a racing build (Sections 3.1, 3.2): each key either found
+    F(x) in a candidate (0xFF) or set it in exactly one candidate, the one
+    its decision names. So every decision is a candidate index or 0xFF, the
+    filter is exactly the oracle's placement of the decided keys' masks, and
+    every "present" key is held by some candidate of the final filter."""
+    assert len(dec) == len(keys)
+    bad = (dec >= ref.c) & (dec != 0xFF)
+    assert not bad.any(), f"{int(bad.sum())} decisions name no candidate"
+    placed = ref.place(keys, dec)
+    diff = np.flatnonzero(placed != words)
+    assert len(diff) == 0, f"{len(diff)} words differ from the placement, first at block {diff[0] // 8}"
+    chk = oracle.OracleFilter(ref.M, ref.c, ref.k, ref.kind, ref.param, ref.block_mult, ref.bit_mult,
+                              distinct=bool(ref.distinct))
+    chk.words[:] = words
+    present = keys[dec == 0xFF]
+    assert chk.query(present).all(), "a key decided 'present' is not held"
+
+
+RACING_CONFIGS = [
     (1 << 15, 2, 14, "la", 1 << 20),     # 2^20 keys, 16 bits/key, LA
     (1 << 14, 3, 8, "mix", 3 << 18),    # three choices, MIX, ~10.7 bits/key
     (3000, 2, 11, "exp", 3000 * 32),    # even non-power-of-two M, EXP
+]
+
+
+@pytest.mark.parametrize("M,c,k,cost,n", RACING_CONFIGS + [
+    (777, 4, 20, "la", 777 * 512 // 24),  # four choices, odd M
+    (1, 2, 5, "exp", 40),                 # one block: all candidates coincide
+    (6, 2, 7, "la", 500),                 # overloaded: many keys find themselves present
+    (1 << 12, 2, 32, "exp", 1 << 12 + 7), # k = 32
 ])
+@pytest.mark.parametrize("lpk,tpw", [(8, 1), (8, 2), (4, 1), (4, 2)])
+def test_racing_insert_decisions_rebuild_the_filter(dev, M, c, k, cost, n, lpk, tpw):
+    ref, gpu = make_pair(M, c, k, cost, seed=c * k + M + lpk + tpw)
+    try:
+        gpu.set_shape(bbfc.OP_INSERT, lpk, tpw)
+        keys_d = workload.device_keys(M + 2, 0, n, device=dev)
+        keys = from_dev(keys_d)
+        keys = np.concatenate([keys, keys[: n // 8]])  # repeats: decided present or placed again
+        dec = gpu.insert_recorded(to_dev(keys, dev)).cpu().numpy()
+        check_decisions(ref, keys, dec, gpu.download())
+        assert (dec[n:] == 0xFF).mean() > 0.5 or M < 8, "repeated keys should mostly find themselves present"
+    finally:
+        gpu.close()
+
+
+def test_racing_insert_decisions_on_top_of_a_filter(dev):
+    """A second racing call decides on the first call's blocks: the filter is
+    the first build plus the second call's placement."""
+    M, c, k = 1 << 12, 3, 9
+    ref, gpu = make_pair(M, c, k, "mix", seed=41)
+    try:
+        a = workload.positive_keys(41, 30000)
+        b = workload.negative_keys(41, 30000, 30000)
+        gpu.insert(to_dev(a, dev))
+        first = gpu.download()
+        dec = gpu.insert_recorded(to_dev(b, dev)).cpu().numpy()
+        assert np.array_equal(gpu.download(), ref.place(b, dec, words=first))
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("M,c,k,cost,n", RACING_CONFIGS)
 def test_racing_insert_invariants_and_fpr(dev, M, c, k, cost, n):
     ref, gpu = make_pair(M, c, k, cost, seed=c * k + M)
     try:
         keys_d = workload.device_keys(M, 0, n, device=dev)
         keys = from_dev(keys_d)
         ref.insert(keys)
+        # the recorded kernel has the timed kernel's schedule: its build is
+        # checked exactly, then the timed kernel's own build as below
+        check_decisions(ref, keys, gpu.insert_recorded(keys_d).cpu().numpy(), gpu.download())
+        gpu.clear()
         gpu.insert(keys_d)
         hits = bbfc.unpack_bits(from_dev(gpu.query(keys_d)), n)
         assert hits.all(), f"{(~hits).sum()} false negatives"

@@ -85,7 +85,8 @@ def test_query_matches_oracle(dev, M, T, c, k, cost, n):
 def test_per_key_inserts(dev, M, T, c, k, cost, n):
     ref, gpu = make_pair(M, T, c, k, cost, seed=2 * M + T)
     try:
-        keys = workload.positive_keys(M + 2, min(n, 60000))
+        # above 2^16 keys the sequential insert runs its device-wide window steps
+        keys = workload.positive_keys(M + 2, min(n, (1 << 16) + 4321))
         gpu.insert_deterministic(to_dev(keys, dev))
         ref.insert(keys)
         assert np.array_equal(gpu.download(), ref.words)
@@ -97,6 +98,24 @@ def test_per_key_inserts(dev, M, T, c, k, cost, n):
         else:
             assert not np.any(words & ~ref.envelope(keys))
         assert bbfc.unpack_bits(from_dev(gpu.query(to_dev(keys, dev))), len(keys)).all()
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("M,T,c,k,cost,n", [
+    (1 << 17, 1 << 9, 2, 11, "la", 3 * (1 << 16) + 4321),  # several windows and a ragged one
+    (777 * 4 * 15, 4, 4, 20, "la", (1 << 17) + 777),      # four choices, odd S = 11655
+])
+def test_sequential_insert_device_wide_windows(dev, M, T, c, k, cost, n):
+    """The sequential insert's device-wide steps (inputs of 2^16 keys and
+    more) on sub-array filters: bit-exact with the oracle."""
+    ref, gpu = make_pair(M, T, c, k, cost, seed=3 * M + T)
+    try:
+        keys = workload.positive_keys(M + 5, n)
+        print(f"sub-array sequential insert M={M} T={T} c={c} k={k} n={n}", flush=True)
+        gpu.insert_deterministic(to_dev(keys, dev))
+        ref.insert(keys)
+        assert np.array_equal(gpu.download(), ref.words)
     finally:
         gpu.close()
 

@@ -244,3 +244,78 @@ def test_conditional_fpr_equals_pair_enumeration(c, M):
             assert got == pytest.approx(float(np.mean(want)), rel=1e-12)
             for x, w in zip(keys[:6], want):
                 assert f.conditional_fpr([x], words) == pytest.approx(w, rel=1e-12)
+
+
+# ------------------------------------------------------------ placement
+# Sections 3.1 and 3.2: each insert either finds F(x) in a candidate and
+# writes nothing, or sets F(x) in exactly one candidate. A build is then fixed
+# by its per-key decisions; the placement comparator rebuilds it from them.
+
+@pytest.mark.parametrize("M,c,k,kind,distinct", [(97, 2, 11, oracle.COST_LA, False),
+                                                  (1 << 10, 3, 8, oracle.COST_MIX, False),
+                                                  (6, 2, 14, oracle.COST_EXP, True),
+                                                  (1, 4, 5, oracle.COST_EXP, False),
+                                                  (3000, 1, 9, oracle.COST_NONE, False)])
+def test_placement_of_the_sequential_decisions_is_the_sequential_filter(M, c, k, kind, distinct):
+    """The sequential oracle's own decisions, placed, give its filter word
+    for word, also when the keys are placed in another order (the OR does not
+    depend on it)."""
+    keys = workload.positive_keys(M + c, 4000)
+    f = oracle.OracleFilter(M, c, k, kind, None, seed=7, distinct=distinct)
+    dec = f.insert_recording(keys)
+    assert set(np.unique(dec)) <= set(range(c)) | {0xFF}
+    assert np.array_equal(f.place(keys, dec), f.words)
+    perm = np.random.default_rng(M).permutation(len(keys))
+    assert np.array_equal(f.place(keys[perm], dec[perm]), f.words)
+
+
+@pytest.mark.parametrize("M,c", [(5, 2), (8, 3), (12, 4), (64, 2)])
+def test_placement_equals_set_restatement(M, c):
+    """Arbitrary decisions (every candidate index, and 'present'), placed by
+    the oracle and by the set-based restatement, word for word."""
+    k = 6
+    bm = workload.draw_multipliers(40 + M, c, coprime_to=M)
+    am = workload.draw_multipliers(41 + M, k)
+    keys = workload.positive_keys(M, 300)
+    rng = np.random.default_rng(M * c)
+    dec = rng.integers(0, c + 1, size=len(keys)).astype(np.uint8)
+    dec[dec == c] = 0xFF
+    f = oracle.OracleFilter(M, c, k, oracle.COST_MIX, None, bm, am)
+    b = brute.BruteFilter(M, c, k, "mix", 2.5, bm, am)
+    assert [int(v) for v in f.place(keys, dec)] == b.placed_words(keys, dec)
+
+
+def test_placement_by_residue_classes_partitions_the_filter():
+    """Placing one residue class of blocks at a time writes only that class,
+    and the classes together give the whole placement."""
+    M, c, k, mod = 1 << 12, 2, 11, 7
+    keys = workload.positive_keys(9, 20000)
+    f = oracle.OracleFilter(M, c, k, oracle.COST_LA, None, seed=9)
+    dec = f.insert_recording(keys)
+    whole = f.place(keys, dec)
+    acc = np.zeros_like(whole)
+    blk = np.arange(M)
+    for rem in range(mod):
+        part = f.place(keys, dec, part_mod=mod, part_rem=rem).reshape(M, 8)
+        assert not part[blk % mod != rem].any()
+        assert np.array_equal(part[blk % mod == rem], whole.reshape(M, 8)[blk % mod == rem])
+        acc |= part.reshape(-1)
+    assert np.array_equal(acc, whole)
+
+
+def test_placement_detects_a_wrong_or_doubled_candidate():
+    """A decision naming the other candidate, or a key whose bits also appear
+    in its second candidate, changes the placement: the comparator sees the
+    faults a racing insert must not make."""
+    M, c, k = 1 << 10, 2, 11
+    keys = workload.positive_keys(11, 3000)
+    f = oracle.OracleFilter(M, c, k, oracle.COST_LA, None, seed=11)
+    dec = f.insert_recording(keys)
+    t = int(np.flatnonzero(dec == 0)[0])
+    wrong = dec.copy()
+    wrong[t] = 1
+    assert not np.array_equal(f.place(keys, wrong), f.words)
+    doubled = f.words.copy()
+    b2 = oracle.block_index(M, 1, 0, int(f.block_mult[1]), int(keys[t]))
+    doubled[8 * b2:8 * b2 + 8] |= oracle.mask(f.bit_mult, int(keys[t]))
+    assert not np.array_equal(f.place(keys, dec), doubled)
