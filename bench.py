@@ -44,8 +44,9 @@ def parse_args():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["plain", "batch", "serve", "kmer"], default="plain",
-                    help="plain: one 2^30-key filter (the headline); batch: 256 filters of uneven sizes; "
+    ap.add_argument("--workload", choices=["plain", "small", "batch", "serve", "kmer"], default="plain",
+                    help="plain: one 2^30-key filter (the headline); small: 2^20 keys into 2^15 blocks, k = 14; "
+                         "batch: 256 filters of uneven sizes; "
                          "serve: query requests of mixed sizes against the resident 2^30-key filter; "
                          "kmer: canonical 31-mers of a synthetic genome and of sequenced reads")
     ap.add_argument("--genome-bases", type=float, default=128e6, help="kmer workload: genome length")
@@ -363,6 +364,191 @@ PAPER_CPU_REFERENCE = {
     "hardware": "AMD Ryzen 9 7950X3D, 16 cores, 9 inserter threads, numba",
     "note": "context only: includes FASTA reading and q-gram extraction; not this metric or workload",
 }
+
+
+def cpu_baseline_small(n, n_blocks, c, k):
+    """The sequential oracle on the whole small workload: every insert, then
+    every query (the inserted keys and as many never inserted), one thread."""
+    import oracle
+    import workload
+
+    f = oracle.OracleFilter(n_blocks, c, k, oracle.COST_LA, None, seed=0)
+    keys = workload.positive_keys(0, n)
+    probe = workload.splitmix64_keys(0, 0, 2 * n)
+    t = time.perf_counter()
+    f.insert(keys)
+    t_ins = time.perf_counter() - t
+    t = time.perf_counter()
+    f.count_hits(probe)
+    t_q = time.perf_counter() - t
+    return {
+        "value": round(3 * n / (t_ins + t_q) / 1e6, 3),
+        "unit": "Mkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"the whole workload: {n} sequential inserts, then {2 * n} queries, one thread "
+                  f"({t_ins + t_q:.2f} s)",
+        "insert_mkeys_s": round(n / t_ins / 1e6, 3),
+        "query_mkeys_s": round(2 * n / t_q / 1e6, 3),
+    }
+
+
+def small_workload(steps: int, warmup: int, with_cpu: bool) -> dict:
+    """The small plain filter: 2^20 random keys (SplitMix64 counters [0, 2^20)
+    of seed 0) into 2^15 blocks (2 MiB, resident in the L2 and the Infinity
+    Cache), 2 choices, k = 14, lookahead cost; then the 2^20 inserted keys and
+    2^20 never-inserted keys are queried. One step = clear + insert + query.
+
+    Three inserts are timed: the library's default racing insert (keys in
+    flight capped at n_blocks/32 = 1024), the racing insert with every key
+    allowed in flight at once, and the sequential insert (exact). Each build's
+    false-positive count over 2^24 further never-inserted keys is compared
+    with the sequential build's (outside the timed steps). The roofline is the
+    insert's algorithmic bytes against the HBM peak, beside random-line read
+    and insert-pattern probes over a buffer of the filter's size."""
+    import numpy as np
+    import torch
+
+    import paper_2501_18977_amd as bbfc
+    import workload
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n, M, c, k = 1 << 20, 1 << 15, 2, 14
+    keys = torch.empty(2 * n, dtype=torch.int64, device=dev)
+    workload.device_keys(0, 0, n, out=keys[:n])
+    workload.device_keys(0, n, n, out=keys[n:])
+    n_neg = 1 << 24
+    neg = workload.device_keys(0, 2 * n, n_neg, device=dev)
+    out = torch.empty(2 * n // 64, dtype=torch.int64, device=dev)
+    out_neg = torch.empty(n_neg // 64, dtype=torch.int64, device=dev)
+    f = bbfc.Filter(M, c, k, "la", seed=0)
+    torch.cuda.synchronize()
+
+    def run(insert_fn):
+        for _ in range(warmup):
+            f.clear(stream)
+            insert_fn()
+            f.query(keys, out=out, stream=stream)
+        torch.cuda.synchronize()
+        ev = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(stream)
+            f.clear(stream)
+            e[1].record(stream)
+            insert_fn()
+            e[2].record(stream)
+            f.query(keys, out=out, stream=stream)
+            e[3].record(stream)
+            ev.append(e)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        ins = sum(e[1].elapsed_time(e[2]) for e in ev) / steps
+        qry = sum(e[2].elapsed_time(e[3]) for e in ev) / steps
+        fn_free = bool(torch.all(out[: n // 64] == -1).item())
+        f.query(neg, out=out_neg, stream=stream)
+        fp = int(np.bitwise_count(out_neg.cpu().numpy().view(np.uint64)).sum())
+        return {"ms_per_step": round(wall, 4), "insert_ms": round(ins, 4), "query_ms": round(qry, 4),
+                "insert_mkeys_s": round(n / ins / 1e3, 1), "query_mkeys_s": round(2 * n / qry / 1e3, 1),
+                "mkeys_s": round(3 * n / wall / 1e3, 1), "zero_false_negatives": fn_free,
+                "false_positives": fp, "fpr_negatives": fp / n_neg}
+
+    variants = {}
+    cap = f.get_option(bbfc.OPT_INSERT_INFLIGHT)
+    variants["racing_default_cap"] = run(lambda: f.insert(keys[:n], stream))
+    variants["racing_default_cap"]["keys_in_flight"] = M // 32 if cap == 0 else cap
+    f.set_option(bbfc.OPT_INSERT_INFLIGHT, n)
+    variants["racing_uncapped"] = run(lambda: f.insert(keys[:n], stream))
+    variants["racing_uncapped"]["keys_in_flight"] = n
+    f.set_option(bbfc.OPT_INSERT_INFLIGHT, cap)
+    variants["exact"] = run(lambda: f.insert_deterministic(keys[:n], stream))
+    fp_exact = variants["exact"]["false_positives"]
+    for v in variants.values():
+        v["fp_vs_exact_rel"] = round(v["false_positives"] / max(fp_exact, 1) - 1, 5)
+        v["fp_vs_exact_sigma"] = round((v["false_positives"] - fp_exact) /
+                                       math.sqrt(max(v["false_positives"] + fp_exact, 1)), 2)
+    default = variants["racing_default_cap"]
+
+    # probes over a buffer of the filter's size (2^15 lines of 64 bytes)
+    buf = torch.zeros(M * 8, dtype=torch.int64, device=dev)
+    sink = torch.zeros(1 << 16, dtype=torch.int64, device=dev)
+    probe = {}
+    for name, fn, acc in (
+        ("rand64_read", lambda a: bbfc.probe_gather(buf, a, 7, sink, 64, stream), 1 << 26),
+        ("insert_pattern_2reads_atomic", lambda a: bbfc.probe_insert_pattern(buf, a, k, 13, sink, stream), n),
+    ):
+        buf.zero_()
+        fn(acc)
+        buf.zero_()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn(acc)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        key = "_Gkeys_s" if name.startswith("insert") else "_Glines_s"
+        probe[name + key] = round(acc / (ms / 1e3) / 1e9, 2)
+    probe["buffer_bytes"] = M * 64
+    probe["query_ceiling_mkeys_s"] = round(probe["rand64_read_Glines_s"] * 1e3 / c, 1)
+    probe["query_frac_of_ceiling"] = round(default["query_mkeys_s"] / probe["query_ceiling_mkeys_s"], 4)
+    probe["insert_frac_of_pattern"] = round(
+        default["insert_mkeys_s"] / (probe["insert_pattern_2reads_atomic_Gkeys_s"] * 1e3), 4)
+    del buf
+
+    ins_bytes = INSERT_BYTES_PER_KEY * n
+    achieved = ins_bytes / (default["insert_ms"] / 1e3) / 1e9
+    rec = {
+        "value": default["mkeys_s"],
+        "unit": "Mkeys/s",
+        "ms_per_step": default["ms_per_step"],
+        "config": {"workload": ("plain filter, small: 2^20 random 64-bit keys inserted into 2^15 blocks of 512 bits "
+                                "(2 MiB, 16 bits per key), 2 choices, k=14, lookahead cost mu=3.5, racing insert "
+                                "(the library default); queries: the 2^20 inserted + 2^20 never inserted"),
+                   "n_keys": n, "n_queries": 2 * n, "n_blocks": M, "filter_bytes": M * 64, "choices": c,
+                   "bits_per_key": k, "cost": "la"},
+        "insert_mkeys_s": default["insert_mkeys_s"],
+        "query_mkeys_s": default["query_mkeys_s"],
+        "variants": variants,
+        "roofline": {"bound": "hbm", "kernel": f"insert_kernel<{c}, 8, 1, ArrayKeys>",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_launch_algorithmic": int(ins_bytes),
+                     "launch_ms": default["insert_ms"], "traffic": None,
+                     "note": "the filter is cache resident and the default insert keeps 1024 keys in flight: "
+                             "bound by the latency of its memory round trips, not by bandwidth"},
+        "probe": probe,
+        "cpu_baseline": cpu_baseline_small(n, M, c, k) if with_cpu else None,
+    }
+    f.close()
+    return rec
+
+
+def bench_small(args):
+    import torch
+
+    torch.cuda.set_device(torch.device("cuda:0"))
+    leg = small_workload(args.steps, args.warmup, not args.no_cpu_baseline)
+    rec = {
+        "metric": "Mkeys/s insert & query, 2-choice 512b blocks; % of random-access HBM peak",
+        "value": leg.pop("value"),
+        "unit": leg.pop("unit"),
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": leg.pop("ms_per_step"),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        **leg,
+        "host": host_info(),
+        "kernel_source_sha": kernel_source_sha(),
+    }
+    print(json.dumps(rec), flush=True)
+    if not all(v["zero_false_negatives"] for v in rec["variants"].values()):
+        sys.exit(1)
 
 
 def bench_batch(args):
@@ -855,6 +1041,9 @@ def main():
         return
     if args.probe_only:
         print(json.dumps(run_probes()), flush=True)
+        return
+    if args.workload == "small":
+        bench_small(args)
         return
     if args.workload == "batch":
         bench_batch(args)
