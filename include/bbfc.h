@@ -203,6 +203,23 @@ bbfc_status bbfc_insert_recorded(bbfc_handle h, const uint64_t *d_keys, uint64_t
 bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uint64_t n,
                                       hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * bbfc_insert_deterministic with the same result, bit for bit, that never
+ * allocates. Its scratch is a static device array of 34,144,512 bytes per
+ * device (a 2^22-entry claim table and one window of 2^16 keys), held on
+ * every device the library runs on until the process ends; the claim table
+ * is cleared by a fill kernel on the caller's stream at the first call on a
+ * device. Every n fits: the call walks the keys in windows of 2^16 (inputs
+ * below 2^16 keys use no scratch), so no key count exceeds the scratch.
+ * All calls on one device share the array, so calls that overlap on a
+ * device race and corrupt each other's results: order them (one stream, or
+ * synchronise between calls), across filters too. Errors as
+ * bbfc_insert_deterministic except ENOMEM; EUNSUPPORTED on a device index
+ * of 64 or more. */
+bbfc_status bbfc_insert_deterministic_noalloc(bbfc_handle h, const uint64_t *d_keys, uint64_t n,
+                                              hipStream_t stream);
+
 /* Query d_keys[0..n) (Section 3.1). Writes ceil(n/64) words to d_out_bits
  * (device memory): bit t mod 64 of word t/64, least significant first, is
  * the answer for d_keys[t]; bits past n in the last word are zero. The

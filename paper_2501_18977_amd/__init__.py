@@ -118,6 +118,7 @@ def lib() -> ctypes.CDLL:
         "bbfc_insert": (_st, [_vp, _vp, _u64, _vp]),
         "bbfc_insert_deterministic": (_st, [_vp, _vp, _u64, _vp]),
         "bbfc_insert_recorded": (_st, [_vp, _vp, _u64, _vp, _vp]),
+        "bbfc_insert_deterministic_noalloc": (_st, [_vp, _vp, _u64, _vp]),
         "bbfc_query": (_st, [_vp, _vp, _u64, _vp, _vp]),
         "bbfc_clear": (_st, [_vp, _vp]),
         "bbfc_upload": (_st, [_vp, _vp, _vp]),
@@ -389,6 +390,13 @@ class Filter:
     def insert_deterministic(self, keys, stream=None) -> None:
         keys = _device_u64(keys, "keys")
         _check(lib().bbfc_insert_deterministic(self.handle, keys.data_ptr(), keys.numel(), _stream_handle(stream)))
+
+    def insert_deterministic_noalloc(self, keys, stream=None) -> None:
+        """insert_deterministic without any device allocation (its scratch is a
+        static device array shared by every call on the device)."""
+        keys = _device_u64(keys, "keys")
+        _check(lib().bbfc_insert_deterministic_noalloc(self.handle, keys.data_ptr(), keys.numel(),
+                                                       _stream_handle(stream)))
 
     def query(self, keys, out=None, stream=None):
         """Packed answers: an int64 tensor of ceil(n/64) words (bit t%64 of

@@ -424,6 +424,24 @@ bbfc_status bbfc_insert_deterministic(bbfc_handle h, const uint64_t *d_keys, uin
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching deterministic insert");
 }
 
+bbfc_status bbfc_insert_deterministic_noalloc(bbfc_handle h, const uint64_t *d_keys, uint64_t n,
+                                              hipStream_t stream)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (n == 0)
+        return BBFC_OK;
+    if (d_keys == nullptr)
+        return fail(BBFC_EINVAL, "null keys with n = %llu", (unsigned long long)n);
+    if (n > kMaxKeys)
+        return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
+    DeviceGuard guard(h->device);
+    hipError_t e = bbfc::launch_insert_det_noalloc(*h, d_keys, n, stream);
+    if (e == hipErrorInvalidDevice)
+        return fail(BBFC_EUNSUPPORTED, "device %d is beyond the 64 devices the static scratch serves", h->device);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching deterministic insert without allocation");
+}
+
 bbfc_status bbfc_query(bbfc_handle h, const uint64_t *d_keys, uint64_t n, uint64_t *d_out_bits, hipStream_t stream)
 {
     if (h == nullptr)

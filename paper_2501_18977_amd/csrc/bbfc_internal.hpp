@@ -71,6 +71,8 @@ hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n,
 hipError_t launch_insert_recorded(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint8_t *decisions,
                                   hipStream_t s);
 hipError_t launch_insert_det(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
+// The same insert with its scratch in a static device array (no allocation).
+hipError_t launch_insert_det_noalloc(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out,
                         hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s);

@@ -25,6 +25,8 @@
 // (workgroup scope; the step also waits for its stores before the barrier).
 #include <stdint.h>
 
+#include <mutex>
+
 #include <hip/hip_runtime.h>
 
 #include "bbfc_common.hpp"
@@ -489,6 +491,46 @@ __global__ __launch_bounds__(1024) void wide_tail_kernel(const uint64_t *__restr
         *count = at;
 }
 
+// Device memory of the device-wide steps: the claim table, a window's
+// pending flags, and its remaining keys followed by their count and the count
+// the last step saw. tag holds the last step tag used with this claim table.
+struct WideScratch {
+    uint64_t *claims;
+    uint8_t *pend;
+    uint64_t *tail;
+    uint64_t *tag;
+};
+
+template <int C>
+hipError_t run_wide_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, const WidePlan &plan,
+                      const WideScratch &ws, hipStream_t s)
+{
+    const KParams kp = make_kparams(f);
+    const uint64_t hmask = plan.claims - 1;
+    const size_t lds = align16(rank_lds_bytes(f.c, f.k)) + (size_t)kWideThreads * kOrdSlotDw * 4;
+    uint64_t *count = ws.tail + plan.window;
+    unsigned long long *left = reinterpret_cast<unsigned long long *>(ws.tail + plan.window + 1);
+    for (uint64_t base = 0; base < n; base += plan.window) {
+        const uint32_t w = (uint32_t)(n - base < plan.window ? n - base : plan.window);
+        const uint32_t grid = (w + kWideThreads - 1) / kWideThreads;
+        const uint64_t *wk = keys + base;
+        uint64_t tag = ++*ws.tag;
+        hipLaunchKernelGGL((wide_claim_kernel<C>), dim3(grid), dim3(kWideThreads), 0, s, kp, wk, w, ws.claims, hmask,
+                           tag, left);
+        for (int step = 0; step < plan.steps; ++step) {
+            const uint64_t next = step + 1 < plan.steps ? ++*ws.tag : 0;
+            hipLaunchKernelGGL((wide_step_kernel<C>), dim3(grid), dim3(kWideThreads), lds, s, kp, wk, w, ws.claims,
+                               hmask, ws.pend, tag, next, step == 0 ? 1 : 0, left);
+            tag = next;
+        }
+        hipLaunchKernelGGL(wide_tail_kernel, dim3(1), dim3(1024), 0, s, wk, w, ws.pend, left, ws.tail, count);
+        hipError_t e = enqueue_ordered_c<C>(f, ws.tail, 0, count, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipGetLastError();
+}
+
 template <int C>
 hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
@@ -518,31 +560,9 @@ hipError_t launch_wide_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipSt
         if (e != hipSuccess)
             return e;
     }
-    const KParams kp = make_kparams(f);
-    const uint64_t hmask = plan.claims - 1;
-    const size_t lds = align16(rank_lds_bytes(f.c, f.k)) + (size_t)kWideThreads * kOrdSlotDw * 4;
-    uint64_t *count = f.d_ord_tail + kWideMaxWindow;
-    unsigned long long *left = reinterpret_cast<unsigned long long *>(f.d_ord_tail + kWideMaxWindow + 1);
-    for (uint64_t base = 0; base < n; base += plan.window) {
-        const uint32_t w = (uint32_t)(n - base < plan.window ? n - base : plan.window);
-        const uint32_t grid = (w + kWideThreads - 1) / kWideThreads;
-        const uint64_t *wk = keys + base;
-        uint64_t tag = ++f.ord_tag;
-        hipLaunchKernelGGL((wide_claim_kernel<C>), dim3(grid), dim3(kWideThreads), 0, s, kp, wk, w, f.d_ord_claims,
-                           hmask, tag, left);
-        for (int step = 0; step < plan.steps; ++step) {
-            const uint64_t next = step + 1 < plan.steps ? ++f.ord_tag : 0;
-            hipLaunchKernelGGL((wide_step_kernel<C>), dim3(grid), dim3(kWideThreads), lds, s, kp, wk, w,
-                               f.d_ord_claims, hmask, f.d_ord_pend, tag, next, step == 0 ? 1 : 0, left);
-            tag = next;
-        }
-        hipLaunchKernelGGL(wide_tail_kernel, dim3(1), dim3(1024), 0, s, wk, w, f.d_ord_pend, left, f.d_ord_tail,
-                           count);
-        hipError_t e = enqueue_ordered_c<C>(f, f.d_ord_tail, 0, count, s);
-        if (e != hipSuccess)
-            return e;
-    }
-    return hipGetLastError();
+    // the tail buffer holds the largest window's keys plus two counters
+    const WideScratch ws{f.d_ord_claims, f.d_ord_pend, f.d_ord_tail, &f.ord_tag};
+    return run_wide_c<C>(f, keys, n, plan, ws, s);
 }
 
 template <int C>
@@ -553,7 +573,85 @@ hipError_t launch_det_c(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStr
     return launch_wide_c<C>(f, keys, n, s);
 }
 
+// ------------------------------------------------- without allocation
+//
+// The device-wide steps with their scratch in a static device array instead
+// of memory the filter allocates: for callers that cannot allocate. Its plan
+// is the small-filter one (windows of 2^16 keys, a 2^22-entry claim table) on
+// every filter; the result does not depend on the plan.
+
+constexpr uint32_t kNaWindow = 1u << 16;
+constexpr uint64_t kNaClaims = 1ull << 22;
+constexpr uint64_t kNaTailWords = kNaWindow + 32; // keys, count, left; padded to 256 bytes
+constexpr uint64_t kNaPendWords = kNaWindow / 8;  // one flag byte per window key
+constexpr uint64_t kNaScratchWords = kNaClaims + kNaTailWords + kNaPendWords;
+static_assert(kNaWindow <= (1u << 24) - 1, "ages must fit below the step tag");
+
 } // namespace
+
+// 34,144,512 bytes per device, held from the library's first use of the
+// device until the process ends: claim table | window tail keys, count, left
+// | pending flags.
+static __device__ __align__(256) uint64_t scratch[kNaScratchWords];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+
+struct NoAllocDevice {
+    uint64_t *ptr = nullptr; // scratch's device address on this device
+    uint64_t tag = 0;        // last step tag written into its claim table
+};
+
+std::mutex g_na_mutex;
+NoAllocDevice g_na[kNaMaxDevices];
+
+template <int C>
+hipError_t launch_det_noalloc_c(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+{
+    hipError_t e = prepare_ordered_c<C>(f);
+    if (e != hipSuccess || n < kWideMinKeys)
+        return e != hipSuccess ? e : enqueue_ordered_c<C>(f, keys, n, nullptr, s);
+    if (f.device < 0 || f.device >= kNaMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_na_mutex);
+    NoAllocDevice &d = g_na[f.device];
+    if (d.ptr == nullptr) {
+        // once per device, with the device current (the caller's guard made it
+        // so): the array's address on this device, and a claim table cleared
+        // below every tag, by a fill kernel on the caller's stream
+        uint64_t *ptr = nullptr;
+        e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        e = launch_fill_zero(ptr, kNaClaims, s);
+        if (e != hipSuccess)
+            return e;
+        d.ptr = ptr;
+    }
+    const WidePlan plan{kNaWindow, kNaClaims, f.M >= (1ull << 24) ? 4 : 8};
+    const WideScratch ws{d.ptr, reinterpret_cast<uint8_t *>(d.ptr + kNaClaims + kNaTailWords), d.ptr + kNaClaims,
+                         &d.tag};
+    return run_wide_c<C>(f, keys, n, plan, ws, s);
+}
+
+} // namespace
+
+hipError_t launch_insert_det_noalloc(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
+{
+    switch (f.c) {
+    case 1:
+        return launch_det_noalloc_c<1>(f, keys, n, s);
+    case 2:
+        return launch_det_noalloc_c<2>(f, keys, n, s);
+    case 3:
+        return launch_det_noalloc_c<3>(f, keys, n, s);
+    case 4:
+        return launch_det_noalloc_c<4>(f, keys, n, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_insert_det(bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
