@@ -26,15 +26,24 @@ COST_NONE, COST_MIX, COST_LA, COST_EXP = 0, 1, 2, 3
 COST_NAMES = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
 
 
-def build() -> str:
-    """Compile the oracle with gcc (plain C, no contraction of a*b+c)."""
+# A sanitizer build (build(sanitize=True)) is loaded instead of liboracle.so
+# when this variable names it; the process must then preload gcc's libasan.
+LIB_ENV = "BBFC_ORACLE_LIB"
+
+
+def build(sanitize: bool = False, out: str | None = None) -> str:
+    """Compile the oracle with gcc (plain C, no contraction of a*b+c). With
+    sanitize=True: AddressSanitizer and UndefinedBehaviorSanitizer, every
+    finding fatal, into `out` (default liboracle_san.so beside the source)."""
+    out = out or (os.path.join(HERE, "liboracle_san.so") if sanitize else LIB)
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
     cmd = [
         "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-        "-Wall", "-Wextra", "-o", LIB + ".tmp", SRC, "-lm",
+        "-Wall", "-Wextra", *(san if sanitize else []), "-o", out + ".tmp", SRC, "-lm",
     ]
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 _lib = None
@@ -53,9 +62,12 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        build()
-    lib = ctypes.CDLL(LIB)
+    path = os.environ.get(LIB_ENV)
+    if not path:
+        path = LIB
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+    lib = ctypes.CDLL(path)
     u64, u32, i32, dbl = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_double
     lib.bbo_hash.argtypes = [u64, u64, u64]
     lib.bbo_hash.restype = u64
