@@ -511,6 +511,20 @@ bbfc_status bbfc_server_destroy(bbfc_server_handle s);
 bbfc_status bbfc_server_submit(bbfc_server_handle s, const uint64_t *h_keys, uint64_t n, uint64_t *h_out_bits,
                                uint64_t *ticket);
 
+/* As bbfc_server_submit, with the keys d_keys[0..n) and the answers
+ * d_out_bits[0..ceil(n/64)) in device memory on the filter's device
+ * (caller-owned; they must not overlap). Nothing is staged: the request
+ * joins the same queue, and a batch of such requests is one query launch
+ * that reads each request's keys in place and writes its answers straight
+ * into its buffer (bbfc_query's layout). A batch holds requests of one
+ * kind (host or device) and at most 1024 request pieces. The buffers must
+ * stay valid, and the keys unchanged, until the request is waited for;
+ * after bbfc_server_wait returns, the answers are in device memory and
+ * need no further synchronisation. Errors as bbfc_server_submit, and
+ * EINVAL when the output overlaps the keys. */
+bbfc_status bbfc_server_submit_device(bbfc_server_handle s, const uint64_t *d_keys, uint64_t n,
+                                      uint64_t *d_out_bits, uint64_t *ticket);
+
 /* Waits for a request (timeout_s < 0: no limit) and forgets its ticket
  * (wait once per ticket). *latency_us (may be null) receives the time from
  * submission to answers in the caller's buffer. Errors: EINVAL (unknown
@@ -529,6 +543,15 @@ bbfc_status bbfc_server_stats(bbfc_server_handle s, uint64_t *batches, uint64_t 
 bbfc_status bbfc_server_replay(bbfc_server_handle s, const uint64_t *h_keys, const uint64_t *req_offsets,
                                uint32_t n_requests, const double *arrival_s, uint64_t *h_out_bits,
                                const uint64_t *out_offsets, double *latency_us, double *wall_s);
+
+/* bbfc_server_replay for device-resident requests: request i reads
+ * d_keys[req_offsets[i] .. req_offsets[i+1]) in place and its answers go to
+ * d_out_bits + out_offsets[i] (both device memory; the offset arrays,
+ * arrival times and latencies are host memory), each submitted as by
+ * bbfc_server_submit_device at its arrival time. */
+bbfc_status bbfc_server_replay_device(bbfc_server_handle s, const uint64_t *d_keys, const uint64_t *req_offsets,
+                                      uint32_t n_requests, const double *arrival_s, uint64_t *d_out_bits,
+                                      const uint64_t *out_offsets, double *latency_us, double *wall_s);
 
 /* ------------------------------------------------------------------ */
 /* Measurement hooks: the kernels that calibrate the roofline. They do   */

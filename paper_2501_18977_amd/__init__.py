@@ -155,6 +155,8 @@ def lib() -> ctypes.CDLL:
         "bbfc_server_wait": (_st, [_vp, _u64, ctypes.c_double, _vp]),
         "bbfc_server_stats": (_st, [_vp, _vp, _vp, _vp]),
         "bbfc_server_replay": (_st, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
+        "bbfc_server_submit_device": (_st, [_vp, _vp, _u64, _vp, _vp]),
+        "bbfc_server_replay_device": (_st, [_vp, _vp, _vp, _u32, _vp, _vp, _vp, _vp, _vp]),
         "bbfc_kmer_count": (_u64, [_u64, _u64, _u32]),
         "bbfc_kmer_keys": (_st, [_vp, _u64, _u64, _u32, _vp, _vp]),
         "bbfc_insert_kmers": (_st, [_vp, _vp, _u64, _u64, _u32, _vp]),
@@ -619,7 +621,8 @@ class Graph:
 
 class Server:
     """Continuous-batching query server over one resident filter; requests
-    are numpy uint64 key arrays in host memory."""
+    are numpy uint64 key arrays in host memory (submit, replay) or 64-bit
+    GPU tensors (submit_device, replay_device)."""
 
     def __init__(self, filt: Filter, n_slots: int = 4, max_batch_keys: int = 1 << 20,
                  max_pending_keys: int = 1 << 28, poll_us: int = 20):
@@ -640,12 +643,58 @@ class Server:
         self._live[t.value] = (keys, out)
         return t.value
 
+    def submit_device(self, keys, out=None) -> int:
+        """Submit a request whose keys are a GPU tensor; its packed answers
+        are written to `out` (an int64 GPU tensor of ceil(n/64) words,
+        allocated if not given) by the server's query launch."""
+        import torch
+
+        keys = _device_u64(keys, "keys")
+        n = keys.numel()
+        if out is None:
+            out = torch.zeros(max(1, (n + 63) // 64), dtype=torch.int64, device=keys.device)
+        out = _device_u64(out, "out")
+        if out.numel() < (n + 63) // 64:
+            raise ValueError("output too small")
+        t = ctypes.c_uint64()
+        _check(lib().bbfc_server_submit_device(self._h, keys.data_ptr(), n, out.data_ptr(), ctypes.byref(t)))
+        self._live[t.value] = (keys, out)
+        return t.value
+
     def wait(self, ticket: int, timeout_s: float = -1.0):
-        """(packed answer words, latency in microseconds)."""
+        """(packed answer words, latency in microseconds); the words are a
+        numpy array for host requests and a GPU tensor for device ones."""
         lat = ctypes.c_double()
         _check(lib().bbfc_server_wait(self._h, ticket, timeout_s, ctypes.byref(lat)))
         keys, out = self._live.pop(ticket)
-        return out[: (len(keys) + 63) // 64], lat.value
+        n = keys.numel() if hasattr(keys, "numel") else len(keys)
+        return out[: (n + 63) // 64], lat.value
+
+    def replay_device(self, keys, req_offsets, arrival_s, out=None):
+        """replay with the keys in a GPU tensor: request i reads
+        keys[req_offsets[i]:req_offsets[i+1]] in place and its answers go to
+        a GPU tensor (word offsets as in replay). Returns (answer tensor,
+        word offsets, latencies in us, wall s)."""
+        import numpy as np
+        import torch
+
+        keys = _device_u64(keys, "keys")
+        ro = np.ascontiguousarray(req_offsets, dtype=np.uint64)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        nreq = len(ro) - 1
+        words = (np.diff(ro) + 63) // 64
+        oo = np.zeros(nreq + 1, dtype=np.uint64)
+        oo[1:] = np.cumsum(words)
+        if out is None:
+            out = torch.zeros(max(1, int(oo[-1])), dtype=torch.int64, device=keys.device)
+        out = _device_u64(out, "out")
+        if out.numel() < int(oo[-1]):
+            raise ValueError("output too small")
+        lat = np.zeros(nreq, dtype=np.float64)
+        wall = ctypes.c_double()
+        _check(lib().bbfc_server_replay_device(self._h, keys.data_ptr(), ro.ctypes.data, nreq, arr.ctypes.data,
+                                               out.data_ptr(), oo.ctypes.data, lat.ctypes.data, ctypes.byref(wall)))
+        return out, oo, lat, wall.value
 
     def stats(self) -> dict:
         b, k, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()

@@ -76,6 +76,23 @@ hipError_t launch_insert_det_noalloc(const bbfc_filter &f, const uint64_t *keys,
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out,
                         hipStream_t s);
 hipError_t launch_fill_zero(uint64_t *p, uint64_t n_words, hipStream_t s);
+
+// One piece of a query over several key arrays of one filter: keys[0..n)
+// answered into out (bbfc_query's layout). unit_off is filled by the
+// launcher: the piece's first unit of T 64-key tiles in the launch.
+struct QueryPiece {
+    const uint64_t *keys;
+    uint64_t *out;
+    uint64_t n;
+    uint64_t unit_off;
+};
+
+// Enqueues one query launch over h_pieces[0..n_pieces) (pinned host memory,
+// keys/out/n filled by the caller; unit offsets are written here), whose
+// table is copied to d_pieces on the stream first. The host table must stay
+// untouched until the stream has passed the copy.
+hipError_t launch_query_pieces(const bbfc_filter &f, QueryPiece *h_pieces, QueryPiece *d_pieces, uint32_t n_pieces,
+                               hipStream_t s);
 hipError_t launch_load_histogram(const bbfc_filter &f, uint64_t *hist, hipStream_t s);
 
 // Bulk insert through a stable partition by sub-array (bbfc_bulk.hip).

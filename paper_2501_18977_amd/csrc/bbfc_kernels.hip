@@ -43,6 +43,30 @@ __global__ __launch_bounds__(kWGSize) void query_kernel(KParams p, Src keys, uin
         query_tiles<C, LPK, T, EARLY>(p, keys, n, u * T * kTile, out + u * T, lane, s_mask[wv], s_blk[wv]);
 }
 
+// A query over several key arrays of one filter (a batch of requests that
+// live in device memory): units are numbered piece after piece and strided
+// over the wavefronts; a wavefront's units only increase, so its piece
+// cursor only moves forward.
+template <int C, int LPK, int T, bool EARLY>
+__global__ __launch_bounds__(kWGSize) void query_pieces_kernel(KParams p, const QueryPiece *__restrict__ pieces,
+                                                               uint32_t n_pieces, uint64_t n_units)
+{
+    __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
+    __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerWG;
+    uint32_t f = 0;
+    for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerWG + wv; u < n_units; u += n_waves) {
+        while (f + 1 < n_pieces && pieces[f + 1].unit_off <= u)
+            ++f;
+        const QueryPiece pc = pieces[f];
+        const uint64_t lu = u - pc.unit_off;
+        query_tiles<C, LPK, T, EARLY>(p, ArrayKeys{pc.keys}, pc.n, lu * T * kTile, pc.out + lu * T, lane, s_mask[wv],
+                                      s_blk[wv]);
+    }
+}
+
 template <int C, int LPK, int T, typename Src>
 __global__ __launch_bounds__(kWGSize) void insert_kernel(KParams p, Src keys, uint64_t n, uint64_t n_units)
 {
@@ -206,6 +230,40 @@ hipError_t query_launch(const bbfc_filter &f, const Src &keys, uint64_t n, uint6
     return hipGetLastError();
 }
 
+template <int C, int LPK, int T, bool EARLY>
+hipError_t query_pieces_launch(const bbfc_filter &f, QueryPiece *h, QueryPiece *d, uint32_t n_pieces, hipStream_t s)
+{
+    uint64_t units = 0;
+    for (uint32_t i = 0; i < n_pieces; ++i) {
+        h[i].unit_off = units;
+        units += (h[i].n + (uint64_t)T * kTile - 1) / ((uint64_t)T * kTile);
+    }
+    if (units == 0)
+        return hipSuccess;
+    hipError_t e = hipMemcpyAsync(d, h, n_pieces * sizeof(QueryPiece), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess)
+        return e;
+    const uint64_t need = (units + kWavesPerWG - 1) / kWavesPerWG;
+    const uint64_t wgs =
+        grid_for(query_pieces_kernel<C, LPK, T, EARLY>, 0, f.num_cus, f.shape[BBFC_OP_QUERY].wgs_per_cu, need);
+    hipLaunchKernelGGL((query_pieces_kernel<C, LPK, T, EARLY>), dim3((uint32_t)wgs), dim3(kWGSize), 0, s,
+                       make_kparams(f), d, n_pieces, units);
+    return hipGetLastError();
+}
+
+template <int C>
+hipError_t query_pieces_c(const bbfc_filter &f, QueryPiece *h, QueryPiece *d, uint32_t n_pieces, hipStream_t s)
+{
+    const bbfc_launch_shape &sh = f.shape[BBFC_OP_QUERY];
+    return with_shape(sh.lanes_per_key, sh.tiles_per_wave, [&](auto L, auto T) {
+        if constexpr (C > 1) {
+            if (f.query_early_exit)
+                return query_pieces_launch<C, decltype(L)::value, decltype(T)::value, true>(f, h, d, n_pieces, s);
+        }
+        return query_pieces_launch<C, decltype(L)::value, decltype(T)::value, false>(f, h, d, n_pieces, s);
+    });
+}
+
 // Static LDS of insert_kernel<C, LPK, T>: masks and block indices per wave.
 constexpr size_t insert_static_lds(int C, int T)
 {
@@ -335,6 +393,23 @@ hipError_t launch_kmer_keys(const uint64_t *seq, uint64_t n_segments, uint64_t s
 hipError_t launch_query(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint64_t *out, hipStream_t s)
 {
     return query_any(f, ArrayKeys{keys}, n, out, s);
+}
+
+hipError_t launch_query_pieces(const bbfc_filter &f, QueryPiece *h_pieces, QueryPiece *d_pieces, uint32_t n_pieces,
+                               hipStream_t s)
+{
+    switch (f.c) {
+    case 1:
+        return query_pieces_c<1>(f, h_pieces, d_pieces, n_pieces, s);
+    case 2:
+        return query_pieces_c<2>(f, h_pieces, d_pieces, n_pieces, s);
+    case 3:
+        return query_pieces_c<3>(f, h_pieces, d_pieces, n_pieces, s);
+    case 4:
+        return query_pieces_c<4>(f, h_pieces, d_pieces, n_pieces, s);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_load_histogram(const bbfc_filter &f, uint64_t *hist, hipStream_t s)

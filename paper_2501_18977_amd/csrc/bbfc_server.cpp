@@ -15,6 +15,12 @@
 // Admission is by memory: at most max_pending_keys keys are queued (submit
 // answers BBFC_EBUSY beyond that), and a batch never holds more than a
 // slot's staging.
+//
+// Requests whose keys and answers are in device memory join the same queue.
+// A batch holds requests of one kind: a device batch stages nothing; its
+// pieces (at most kMaxDevicePieces) become a small descriptor table, copied
+// to the device, and one query launch reads every piece's keys where they
+// are and writes its answers straight into the request's buffer.
 #include <stdint.h>
 #include <string.h>
 
@@ -38,11 +44,14 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+constexpr uint32_t kMaxDevicePieces = 1024;
+
 struct Request {
     uint64_t ticket = 0;
     const uint64_t *keys = nullptr;
     uint64_t n = 0;
     uint64_t *out = nullptr;
+    bool device = false;      // keys and answers in device memory
     uint64_t next = 0;        // first key not yet placed in a batch
     uint64_t answered = 0;    // keys whose answers are back
     Clock::time_point t_submit;
@@ -64,6 +73,9 @@ struct Slot {
     uint64_t *d_keys = nullptr;
     uint64_t *d_out = nullptr;
     hipEvent_t done = nullptr;
+    bbfc::QueryPiece *h_table = nullptr; // pinned: a device batch's pieces
+    bbfc::QueryPiece *d_table = nullptr;
+    bool device = false; // the planned batch is of device requests
     std::vector<Piece> pieces;
     std::thread worker;
 };
@@ -98,8 +110,11 @@ uint64_t plan_slot(bbfc_server &s, Slot &slot)
     uint64_t used = 0;
     const uint64_t cap = s.cfg.max_batch_keys;
     slot.pieces.clear();
+    slot.device = !s.pending.empty() && s.pending.front()->device;
     while (!s.pending.empty() && used < cap) {
         std::shared_ptr<Request> r = s.pending.front();
+        if (r->device != slot.device || (slot.device && slot.pieces.size() >= kMaxDevicePieces))
+            break; // one kind per batch; a device batch's table is bounded
         const uint64_t room = cap - used;
         const uint64_t left = r->n - r->next;
         uint64_t take = std::min(left, room);
@@ -123,6 +138,13 @@ uint64_t plan_slot(bbfc_server &s, Slot &slot)
 // clients keep their key buffers valid until their requests are done.
 hipError_t launch_slot(bbfc_server &s, Slot &slot, uint64_t used)
 {
+    if (slot.device) {
+        uint32_t i = 0;
+        for (const Piece &p : slot.pieces)
+            slot.h_table[i++] = bbfc::QueryPiece{p.req->keys + p.key_off, p.req->out + p.key_off / 64, p.n, 0};
+        hipError_t e = bbfc::launch_query_pieces(*s.filter, slot.h_table, slot.d_table, i, slot.stream);
+        return e == hipSuccess ? hipEventRecord(slot.done, slot.stream) : e;
+    }
     for (const Piece &p : slot.pieces) {
         memcpy(slot.h_keys + p.word_off * 64, p.req->keys + p.key_off, p.n * sizeof(uint64_t));
         const uint64_t padded = (p.n + 63) / 64 * 64;
@@ -140,9 +162,12 @@ hipError_t launch_slot(bbfc_server &s, Slot &slot, uint64_t used)
     return e;
 }
 
-// Copies a finished slot's answers into its requests' buffers (no lock).
+// Copies a finished slot's answers into its requests' buffers (no lock); a
+// device batch wrote them in place.
 void copy_answers(Slot &slot)
 {
+    if (slot.device)
+        return;
     for (const Piece &p : slot.pieces) {
         const uint64_t words = (p.n + 63) / 64;
         memcpy(p.req->out + p.key_off / 64, slot.h_out + p.word_off, words * sizeof(uint64_t));
@@ -220,14 +245,21 @@ void slot_worker(bbfc_server *sp, Slot *slot_p)
 }
 
 bbfc_status submit_at(bbfc_server_handle s, const uint64_t *h_keys, uint64_t n, uint64_t *h_out_bits,
-                      uint64_t *ticket, Clock::time_point t_arrival)
+                      uint64_t *ticket, Clock::time_point t_arrival, bool device)
 {
     if (s == nullptr || ticket == nullptr || (n > 0 && (h_keys == nullptr || h_out_bits == nullptr)))
         return bbfc::fail(BBFC_EINVAL, "null server, ticket, keys or output");
+    if (device && n > 0) {
+        const uintptr_t k0 = (uintptr_t)h_keys, k1 = k0 + n * 8;
+        const uintptr_t o0 = (uintptr_t)h_out_bits, o1 = o0 + ((n + 63) / 64) * 8;
+        if (k0 < o1 && o0 < k1)
+            return bbfc::fail(BBFC_EINVAL, "output overlaps the keys");
+    }
     auto r = std::make_shared<Request>();
     r->keys = h_keys;
     r->n = n;
     r->out = h_out_bits;
+    r->device = device;
     r->t_submit = t_arrival;
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -297,6 +329,11 @@ bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *con
             e = hipMalloc(&slot.d_out, ob);
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipHostMalloc((void **)&slot.h_table, kMaxDevicePieces * sizeof(bbfc::QueryPiece),
+                              hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipMalloc((void **)&slot.d_table, kMaxDevicePieces * sizeof(bbfc::QueryPiece));
     }
     if (e != hipSuccess) {
         bbfc_server_destroy(s);
@@ -334,6 +371,10 @@ bbfc_status bbfc_server_destroy(bbfc_server_handle s)
             (void)hipHostFree(slot.h_keys);
         if (slot.h_out)
             (void)hipHostFree(slot.h_out);
+        if (slot.d_table)
+            (void)hipFree(slot.d_table);
+        if (slot.h_table)
+            (void)hipHostFree(slot.h_table);
         if (slot.stream)
             (void)hipStreamDestroy(slot.stream);
     }
@@ -344,7 +385,13 @@ bbfc_status bbfc_server_destroy(bbfc_server_handle s)
 bbfc_status bbfc_server_submit(bbfc_server_handle s, const uint64_t *h_keys, uint64_t n, uint64_t *h_out_bits,
                                uint64_t *ticket)
 {
-    return submit_at(s, h_keys, n, h_out_bits, ticket, Clock::now());
+    return submit_at(s, h_keys, n, h_out_bits, ticket, Clock::now(), false);
+}
+
+bbfc_status bbfc_server_submit_device(bbfc_server_handle s, const uint64_t *d_keys, uint64_t n,
+                                      uint64_t *d_out_bits, uint64_t *ticket)
+{
+    return submit_at(s, d_keys, n, d_out_bits, ticket, Clock::now(), true);
 }
 
 bbfc_status bbfc_server_wait(bbfc_server_handle s, uint64_t ticket, double timeout_s, double *latency_us)
@@ -384,9 +431,13 @@ bbfc_status bbfc_server_stats(bbfc_server_handle s, uint64_t *batches, uint64_t 
     return BBFC_OK;
 }
 
-bbfc_status bbfc_server_replay(bbfc_server_handle s, const uint64_t *h_keys, const uint64_t *req_offsets,
-                               uint32_t n_requests, const double *arrival_s, uint64_t *h_out_bits,
-                               const uint64_t *out_offsets, double *latency_us, double *wall_s)
+} // extern "C"
+
+namespace {
+
+bbfc_status replay(bbfc_server_handle s, const uint64_t *h_keys, const uint64_t *req_offsets, uint32_t n_requests,
+                   const double *arrival_s, uint64_t *h_out_bits, const uint64_t *out_offsets, double *latency_us,
+                   double *wall_s, bool device)
 {
     if (s == nullptr || h_keys == nullptr || req_offsets == nullptr || arrival_s == nullptr ||
         h_out_bits == nullptr || out_offsets == nullptr || latency_us == nullptr)
@@ -404,7 +455,7 @@ bbfc_status bbfc_server_replay(bbfc_server_handle s, const uint64_t *h_keys, con
         for (;;) {
             // latency counts from the scheduled arrival, also while admission waits
             const bbfc_status st = submit_at(s, h_keys + req_offsets[i], req_offsets[i + 1] - req_offsets[i],
-                                             h_out_bits + out_offsets[i], &tickets[i], due);
+                                             h_out_bits + out_offsets[i], &tickets[i], due, device);
             if (st == BBFC_OK)
                 break;
             if (st != BBFC_EBUSY)
@@ -420,6 +471,24 @@ bbfc_status bbfc_server_replay(bbfc_server_handle s, const uint64_t *h_keys, con
     if (wall_s)
         *wall_s = std::chrono::duration<double>(Clock::now() - t0).count();
     return BBFC_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+bbfc_status bbfc_server_replay(bbfc_server_handle s, const uint64_t *h_keys, const uint64_t *req_offsets,
+                               uint32_t n_requests, const double *arrival_s, uint64_t *h_out_bits,
+                               const uint64_t *out_offsets, double *latency_us, double *wall_s)
+{
+    return replay(s, h_keys, req_offsets, n_requests, arrival_s, h_out_bits, out_offsets, latency_us, wall_s, false);
+}
+
+bbfc_status bbfc_server_replay_device(bbfc_server_handle s, const uint64_t *d_keys, const uint64_t *req_offsets,
+                                      uint32_t n_requests, const double *arrival_s, uint64_t *d_out_bits,
+                                      const uint64_t *out_offsets, double *latency_us, double *wall_s)
+{
+    return replay(s, d_keys, req_offsets, n_requests, arrival_s, d_out_bits, out_offsets, latency_us, wall_s, true);
 }
 
 } // extern "C"

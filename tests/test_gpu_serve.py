@@ -3,7 +3,8 @@
 Every request's answers must be the same when it is served alone, when it
 is served in a mix with many other requests (packed into shared batches,
 split across batches, overlapping on several streams), and when the
-oracle answers the same keys.
+oracle answers the same keys; for requests from host memory and for
+requests whose keys and answers stay in device memory.
 """
 
 import numpy as np
@@ -80,6 +81,100 @@ def test_results_same_alone_in_mix_and_oracle(served):
         assert np.array_equal(m, want)
     # in the mix, requests shared batches
     assert b_mixed < b_alone
+
+
+def _dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.uint64).view(np.int64)).to(dev)
+
+
+def _host_words(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64) if hasattr(t, "cpu") else t
+
+
+def test_device_requests_same_alone_in_mix_and_oracle(served, dev):
+    """Requests whose keys and answers live in device memory: alone, all in
+    flight together, and interleaved with host requests (batches hold one
+    kind), every answer equals the oracle's and the host path's."""
+    ref, f, keys = served
+    reqs = make_requests(keys, SIZES, 11)
+    d_reqs = [_dev(r, dev) for r in reqs]
+    torch.cuda.synchronize()
+    srv = bbfc.Server(f, n_slots=3, max_batch_keys=1 << 16)
+    try:
+        alone = []
+        for r in d_reqs:
+            ans, lat = srv.wait(srv.submit_device(r))
+            assert lat > 0
+            alone.append(_host_words(ans).copy())
+        b_alone = srv.stats()["batches"]
+        tickets = [srv.submit_device(r) for r in d_reqs]
+        mixed = [_host_words(srv.wait(t)[0]).copy() for t in tickets]
+        b_mixed = srv.stats()["batches"] - b_alone
+        tickets = [(srv.submit_device(d) if i % 2 else srv.submit(h)) for i, (h, d) in enumerate(zip(reqs, d_reqs))]
+        both = [_host_words(srv.wait(t)[0]).copy() for t in tickets]
+    finally:
+        srv.close()
+    for r, a, m, b in zip(reqs, alone, mixed, both):
+        want = ref.query_bits(r)
+        assert np.array_equal(a, want)
+        assert np.array_equal(m, want)
+        assert np.array_equal(b, want)
+    assert b_mixed < b_alone
+
+
+def test_device_requests_many_pieces(served, dev):
+    """3000 tiny device requests in flight at once: batches close at 1024
+    pieces, and every request's answer word is exact (bits past n zero)."""
+    ref, f, keys = served
+    sizes = [1 + (i * 37) % 64 for i in range(3000)]
+    reqs = make_requests(keys, sizes, 12)
+    flat = np.concatenate(reqs)
+    d_flat = _dev(flat, dev)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    outs = torch.full((len(reqs),), -1, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    srv = bbfc.Server(f, n_slots=2, max_batch_keys=1 << 20)
+    try:
+        tickets = [srv.submit_device(d_flat[int(offs[i]):int(offs[i + 1])], out=outs[i:i + 1])
+                   for i in range(len(reqs))]
+        for t in tickets:
+            srv.wait(t)
+        assert srv.stats()["batches"] >= len(reqs) // 1024
+    finally:
+        srv.close()
+    got = outs.cpu().numpy().view(np.uint64)
+    for i, r in enumerate(reqs):
+        assert got[i] == ref.query_bits(r)[0], i
+
+
+def test_device_replay_under_tight_admission(served, dev):
+    ref, f, keys = served
+    sizes = [int(round(2 ** u)) for u in np.random.default_rng(13).uniform(0, 13, size=300)]
+    reqs = make_requests(keys, sizes, 13)
+    flat = np.concatenate(reqs)
+    offs = np.zeros(len(reqs) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(r) for r in reqs])
+    arrivals = np.cumsum(np.random.default_rng(14).exponential(20e-6, size=len(reqs)))
+    srv = bbfc.Server(f, n_slots=4, max_batch_keys=1 << 14, max_pending_keys=5000)
+    try:
+        out, oo, lat, wall = srv.replay_device(_dev(flat, dev), offs, arrivals)
+    finally:
+        srv.close()
+    words = out.cpu().numpy().view(np.uint64)
+    assert wall > 0 and np.all(lat > 0)
+    for i, r in enumerate(reqs):
+        assert np.array_equal(words[int(oo[i]):int(oo[i + 1])], ref.query_bits(r)), i
+
+
+def test_device_request_overlapping_output_rejected(served, dev):
+    _, f, _ = served
+    buf = torch.zeros(4096, dtype=torch.int64, device=dev)
+    srv = bbfc.Server(f)
+    try:
+        with pytest.raises(bbfc.BBFCError, match="overlaps"):
+            srv.submit_device(buf[:1000], out=buf[900:1000])
+    finally:
+        srv.close()
 
 
 def test_large_requests_split_across_small_batches(served):
