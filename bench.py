@@ -69,6 +69,8 @@ def parse_args():
                          "or the sequential insert on any layout (bbfc_insert_deterministic)")
     ap.add_argument("--filters", type=int, default=256, help="batch workload: number of filters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="plain workload: skip the small-filter, batch and kmer legs of the default run")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch shapes (no autotuning)")
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="target seconds per oracle leg")
@@ -164,12 +166,23 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(op: str, kernel: str, config: dict):
+def with_traffic(rec: dict, traffic, ms: float) -> dict:
+    """Adds the HBM bytes the counters saw per launch (each random 64-byte
+    block read is served by one 128-byte DRAM request) as a rate and a
+    fraction of the peak."""
+    rec["traffic"] = traffic
+    if traffic:
+        rec["traffic_GBs"] = round(traffic / (ms / 1e3) / 1e9, 1)
+        rec["traffic_frac"] = round(traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    return rec
+
+
+def measured_traffic(op: str, kernel: str, config: dict, summary: str = "traffic.json"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
     calibration), or None if the summary is absent, was taken on a different
     kernel source or workload configuration, or has no such launch shape."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -552,6 +565,13 @@ def bench_small(args):
 
 
 def bench_batch(args):
+    rec = batch_workload(args)
+    print(json.dumps(rec), flush=True)
+    if not rec["zero_false_negatives"]:
+        sys.exit(1)
+
+
+def batch_workload(args, compact: bool = False) -> dict:
     """256 filters with key counts log-uniform in [2^10, 2^24], 10-16 bits
     per key (k = round(b ln 2)), 2 choices, EXP cost; each filter gets its
     own seeded keys and is queried with as many never-inserted keys. Five
@@ -559,7 +579,9 @@ def bench_batch(args):
     one plain launch per filter and operation (on one stream, and spread
     over 8 streams), one persistent launch per operation, the persistent
     launches in a hipGraph, and the same after the autotuner picked each
-    operation's launch shape."""
+    operation's launch shape. compact: only the plain launches on one
+    stream and the persistent launches in a hipGraph with the default
+    shapes, no CPU baseline (a leg of the default run)."""
     import numpy as np
     import torch
 
@@ -674,20 +696,27 @@ def bench_batch(args):
 
     results = {}
     measure("plain_per_filter", plain_insert, plain_query)
-    measure("plain_per_filter_8_streams", plain_insert_streams, plain_query_streams)
-    measure("persistent", lambda: ins_plan.insert(ins, stream), lambda: q_plan.query(qry, out=out, stream=stream))
+    if not compact:
+        measure("plain_per_filter_8_streams", plain_insert_streams, plain_query_streams)
+        measure("persistent", lambda: ins_plan.insert(ins, stream),
+                lambda: q_plan.query(qry, out=out, stream=stream))
     graph = bbfc.Graph(insert_batch=ins_plan, insert_keys=ins, query_batch=q_plan, query_keys=qry, out=out)
     measure("persistent_graph", lambda: ins_plan.insert(ins, stream), lambda: q_plan.query(qry, out=out, stream=stream),
             both_fn=lambda: graph.launch(stream))
     graph.close()
-    clear_all()  # tune the insert on empty filters, as it runs in a step
-    shape_i = ins_plan.tune(bbfc.OP_INSERT, ins, reps=2)
-    ins_plan.insert(ins, stream)  # tune the query on built filters
-    shape_q = q_plan.tune(bbfc.OP_QUERY, qry, out, reps=2)
-    graph = bbfc.Graph(insert_batch=ins_plan, insert_keys=ins, query_batch=q_plan, query_keys=qry, out=out)
-    measure("tuned_persistent_graph", lambda: ins_plan.insert(ins, stream),
-            lambda: q_plan.query(qry, out=out, stream=stream), both_fn=lambda: graph.launch(stream))
-    graph.close()
+    shape_i = ins_plan.get_shape(bbfc.OP_INSERT)
+    shape_q = q_plan.get_shape(bbfc.OP_QUERY)
+    best_tag = "persistent_graph"
+    if not compact:
+        clear_all()  # tune the insert on empty filters, as it runs in a step
+        shape_i = ins_plan.tune(bbfc.OP_INSERT, ins, reps=2)
+        ins_plan.insert(ins, stream)  # tune the query on built filters
+        shape_q = q_plan.tune(bbfc.OP_QUERY, qry, out, reps=2)
+        graph = bbfc.Graph(insert_batch=ins_plan, insert_keys=ins, query_batch=q_plan, query_keys=qry, out=out)
+        measure("tuned_persistent_graph", lambda: ins_plan.insert(ins, stream),
+                lambda: q_plan.query(qry, out=out, stream=stream), both_fn=lambda: graph.launch(stream))
+        graph.close()
+        best_tag = "tuned_persistent_graph"
 
     # correctness guard: every filter's inserted keys answer true
     clear_all()
@@ -698,12 +727,17 @@ def bench_batch(args):
     for wo, n in zip(q_plan.out_offsets, ns):
         bits = bbfc.unpack_bits(words[wo:wo + (2 * n + 63) // 64], 2 * n)
         fn_free &= bool(bits[:n].all())
-    best = results["tuned_persistent_graph"]
+    best = results[best_tag]
     t_best = best["insert_query_ms"]
     dom = "insert" if best["insert_ms"] >= best["query_ms"] else "query"
     dom_ms = best[dom + "_ms"]
     dom_bytes = INSERT_BYTES_PER_KEY * total if dom == "insert" else QUERY_BYTES_PER_KEY * 2 * total
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
+    sh = shape_i if dom == "insert" else shape_q
+    dom_kernel = (f"batch_insert_kernel<2, {sh['lanes_per_key']}, {sh['tiles_per_wave']}>" if dom == "insert" else
+                  f"batch_query_kernel<2, {sh['lanes_per_key']}, {sh['tiles_per_wave']}, true>")
+    traffic = measured_traffic(dom, dom_kernel, {"workload": "batch", "filters": args.filters, "total_keys": total},
+                               "traffic_batch.json")
     rec = {
         "metric": "Mkeys/s insert & query, 2-choice 512b blocks; % of random-access HBM peak",
         "value": round(3 * total / t_best / 1e3, 1),
@@ -723,20 +757,19 @@ def bench_batch(args):
                    "filters": args.filters, "total_keys": total,
                    "filter_bytes": sum(fl.n_blocks * 64 for fl in filters)},
         "variants": results,
-        "tuned_shapes": {"insert": shape_i, "query": shape_q},
+        ("shapes" if compact else "tuned_shapes"): {"insert": shape_i, "query": shape_q},
         "zero_false_negatives": fn_free,
-        "roofline": {"bound": "hbm", "kernel": f"batch_{dom}_kernel", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "launch_ms": dom_ms},
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_batch(specs, args.cpu_seconds),
+        "roofline": with_traffic({"bound": "hbm", "kernel": dom_kernel, "achieved": round(achieved, 1),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                  "bytes_per_launch_algorithmic": int(dom_bytes), "launch_ms": dom_ms},
+                                 traffic, dom_ms),
+        "cpu_baseline": None if (args.no_cpu_baseline or compact) else cpu_baseline_batch(specs, args.cpu_seconds),
         "host": host_info(),
         "kernel_source_sha": kernel_source_sha(),
     }
     for fl in filters:
         fl.close()
-    print(json.dumps(rec), flush=True)
-    if not fn_free:
-        sys.exit(1)
+    return rec
 
 
 def bench_serve(args):
@@ -906,6 +939,13 @@ def bench_serve(args):
 
 
 def bench_kmer(args):
+    rec = kmer_workload(args)
+    print(json.dumps(rec), flush=True)
+    if not rec["reads_hit_ok"]:
+        sys.exit(1)
+
+
+def kmer_workload(args, compact: bool = False) -> dict:
     """DNA q-grams: a synthetic genome of uniform random bases (2-bit
     packed, made on the device) and its canonical 31-mers inserted into a
     filter of 12 bits per key (3 choices, k = 8, MIX cost); queried with the
@@ -913,7 +953,8 @@ def bench_kmer(args):
     and of as many uniform random reads. One step = clear + insert the
     genome's 31-mers + query both read sets; the fused kernels compute each
     31-mer from the packed bases, the unfused comparison writes the keys out
-    first and then runs the plain kernels."""
+    first and then runs the plain kernels. compact: no CPU baseline (a leg
+    of the default run)."""
     import numpy as np
     import torch
 
@@ -1029,9 +1070,16 @@ def bench_kmer(args):
     n_q = (2 if with_neg else 1) * n_r
     total = n_g + n_q
     q_ms = ph[2] + ph[3]
-    dom, dom_ms, dom_bytes = ("query", q_ms, (0.25 + 64 * 3 + 1 / 8) * n_q) if q_ms >= ph[1] else \
+    # the timed phases: one insert launch, one or two query launches of n_r keys
+    n_qlaunch = 2 if with_neg else 1
+    dom, dom_ms, dom_bytes = ("query", q_ms / n_qlaunch, (0.25 + 64 * 3 + 1 / 8) * n_r) if q_ms >= ph[1] else \
         ("insert", ph[1], (0.25 + 64 * 3 + 64) * n_g)
     achieved = dom_bytes / (dom_ms / 1e3) / 1e9
+    qs = filt.get_shape(bbfc.OP_QUERY)
+    dom_kernel = (f"query_kernel<3, {qs['lanes_per_key']}, {qs['tiles_per_wave']}, true, KmerKeys>" if dom == "query"
+                  else "insert_kernel<3, 8, 1, KmerKeys>")
+    traffic = measured_traffic(dom, dom_kernel, {"workload": "kmer", "genome_bases": G, "reads": R,
+                                                 "repeat_fraction": args.repeat_fraction}, "traffic_kmer.json")
     rec = {
         "metric": "Mkeys/s insert & query, 2-choice 512b blocks; % of random-access HBM peak",
         "value": round(total / t_fused / 1e3, 1),
@@ -1065,17 +1113,18 @@ def bench_kmer(args):
         "hit_rate_reads": round(hit_pos, 5),
         "hit_rate_random": hit_neg,
         "error_free_share": round(0.99 ** q, 5),
-        "roofline": {"bound": "hbm", "kernel": f"{dom}_kernel<3, ..., KmerKeys>", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "launch_ms": round(dom_ms, 3)},
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_kmer(M, args.kmer_k, 21, n_g, n_q, args.cpu_seconds),
+        "reads_hit_ok": bool(ok),
+        "roofline": with_traffic({"bound": "hbm", "kernel": dom_kernel, "achieved": round(achieved, 1),
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                                  "bytes_per_launch_algorithmic": int(dom_bytes), "launch_ms": round(dom_ms, 3)},
+                                 traffic, dom_ms),
+        "cpu_baseline": (None if (args.no_cpu_baseline or compact) else
+                         cpu_baseline_kmer(M, args.kmer_k, 21, n_g, n_q, args.cpu_seconds)),
         "host": host_info(),
         "kernel_source_sha": kernel_source_sha(),
     }
     filt.close()
-    print(json.dumps(rec), flush=True)
-    if not ok:
-        sys.exit(1)
+    return rec
 
 
 def main():
@@ -1200,16 +1249,6 @@ def main():
     traffic_cfg = {"n_keys": n, "n_blocks": n_blocks, "bit_selection": args.bits, "subarrays": T,
                    "insert": args.insert}
 
-    def with_traffic(rec, traffic, ms):
-        # HBM bytes the counters saw per launch (each random 64-byte block
-        # read is served by one 128-byte DRAM request), as a rate and a
-        # fraction of the peak
-        rec["traffic"] = traffic
-        if traffic:
-            rec["traffic_GBs"] = round(traffic / (ms / 1e3) / 1e9, 1)
-            rec["traffic_frac"] = round(traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
-        return rec
-
     roofline = with_traffic({
         "bound": "hbm",
         "kernel": dom_kernel,
@@ -1318,9 +1357,45 @@ def main():
         "kernel_source_sha": kernel_source_sha(),
     }
     filt.close()
+    legs_ok = True
+    if not args.no_legs and args.log2_keys == 30 and T == 1 and args.insert == "racing" and args.bits == "random":
+        del keys, out
+        torch.cuda.empty_cache()
+        rec["legs"], legs_ok = run_legs(args)
     print(json.dumps(rec), flush=True)
-    if not fn_free:
+    if not fn_free or not legs_ok:
         sys.exit(1)
+
+
+# what a leg keeps of its workload's full record
+_LEG_DROP = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "host",
+             "kernel_source_sha", "steps", "warmup")
+
+
+def run_legs(args):
+    """The other workloads, compact, after the headline: the small filter
+    (its three inserts and the oracle on the whole workload), the batch of
+    256 filters (plain launches per filter against the persistent launches in
+    a hipGraph) and the DNA q-grams (fused against unfused kernels). Each leg
+    carries its own value, steps and roofline."""
+    legs = {}
+    ok = True
+    print("legs: small filter", file=sys.stderr, flush=True)
+    legs["small"] = small_workload(10, 3, not args.no_cpu_baseline)
+    legs["small"]["steps"], legs["small"]["warmup"] = 10, 3
+    ok &= all(v["zero_false_negatives"] for v in legs["small"]["variants"].values())
+    leg_args = argparse.Namespace(**vars(args))
+    leg_args.steps, leg_args.warmup = 3, 1
+    print("legs: batch", file=sys.stderr, flush=True)
+    b = batch_workload(leg_args, compact=True)
+    ok &= b["zero_false_negatives"]
+    print("legs: kmer", file=sys.stderr, flush=True)
+    k = kmer_workload(leg_args, compact=True)
+    ok &= k["reads_hit_ok"]
+    for name, r in (("batch", b), ("kmer", k)):
+        legs[name] = {key: v for key, v in r.items() if key not in _LEG_DROP}
+        legs[name]["steps"], legs[name]["warmup"] = leg_args.steps, leg_args.warmup
+    return legs, bool(ok)
 
 
 if __name__ == "__main__":
