@@ -86,7 +86,9 @@ def run_probes(stream=None, n_blocks=1 << 25, n_keys=1 << 30, k=11):
     line) over a 4 GiB buffer, beyond the Infinity Cache; then the insert's
     pattern (two reads, then at most one line rewritten with a k-bit mask) for
     n_keys keys on a zeroed buffer of the filter's size (n_blocks lines,
-    rounded down to a power of two, at most 4 GiB)."""
+    rounded down to a power of two, at most 4 GiB), as the insert schedules
+    it, software-pipelined, and with the rewritten line chosen without the
+    reads (the same traffic without the read-to-write dependency)."""
     import torch
 
     import paper_2501_18977_amd as bbfc
@@ -105,6 +107,9 @@ def run_probes(stream=None, n_blocks=1 << 25, n_keys=1 << 30, k=11):
         ("rand64_atomic_or", lambda a: bbfc.probe_atomic64(buf, a, 9, stream), 1 << 27),
         ("insert_pattern_2reads", lambda a: bbfc.probe_insert_pattern(pat, a, 0, 11, sink, stream), n_keys),
         ("insert_pattern_2reads_atomic", lambda a: bbfc.probe_insert_pattern(pat, a, k, 13, sink, stream), n_keys),
+        ("insert_pattern_pipelined", lambda a: bbfc.probe_insert_schedule(pat, a, k, 1, 13, sink, stream), n_keys),
+        ("insert_pattern_blind_choice", lambda a: bbfc.probe_insert_schedule(pat, a, k, 2, 13, sink, stream),
+         n_keys),
     ):
         fn(acc >> 4)
         if name.startswith("insert_pattern"):

@@ -585,6 +585,21 @@ bbfc_status bbfc_probe_atomic64(uint64_t *d_buf, uint64_t n_lines, uint64_t n_ac
 bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t mask_bits,
                                       uint64_t seed, uint64_t *d_sink, hipStream_t stream);
 
+/* The insert's pattern of bbfc_probe_insert_pattern (mask_bits in [1, 32])
+ * under three schedules, to locate the insert's ceiling:
+ *   0  as bbfc_probe_insert_pattern: a unit's reads, then its atomics;
+ *   1  pipelined: a wavefront decides a unit's 64 keys, then issues their
+ *      atomics (an OR of zero where a word gains nothing) and right after
+ *      them the next unit's reads, so no wait for reads covers atomics;
+ *   2  the line that receives the mask is chosen from the key alone, not
+ *      from the words read, so the atomics do not wait for the reads. Not
+ *      an insert: it measures the same traffic without the dependency of
+ *      the write on the reads.
+ * Arguments and errors as bbfc_probe_insert_pattern, plus EINVAL for
+ * another schedule. */
+bbfc_status bbfc_probe_insert_schedule(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t mask_bits,
+                                       int32_t schedule, uint64_t seed, uint64_t *d_sink, hipStream_t stream);
+
 /* Plain copy of n_words words, to calibrate the traffic counters. With
  * request_bytes == 128 every lane moves 16 contiguous bytes (128-byte
  * requests, a streaming copy; an odd last word is not copied). With

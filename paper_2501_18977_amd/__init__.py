@@ -38,6 +38,7 @@ __all__ = [
     "probe_gather",
     "probe_atomic64",
     "probe_copy",
+    "probe_insert_schedule",
     "unpack_bits",
 ]
 
@@ -135,6 +136,7 @@ def lib() -> ctypes.CDLL:
         "bbfc_probe_atomic64": (_st, [_vp, _u64, _u64, _u64, _vp]),
         "bbfc_probe_copy": (_st, [_vp, _vp, _u64, _u32, _vp]),
         "bbfc_probe_insert_pattern": (_st, [_vp, _u64, _u64, ctypes.c_int32, _u64, _vp, _vp]),
+        "bbfc_probe_insert_schedule": (_st, [_vp, _u64, _u64, ctypes.c_int32, ctypes.c_int32, _u64, _vp, _vp]),
         "bbfc_batch_create": (_st, [_vp, _vp, _u32, _vp]),
         "bbfc_batch_destroy": (_st, [_vp]),
         "bbfc_batch_layout": (_st, [_vp, _vp, _vp]),
@@ -758,6 +760,14 @@ def probe_insert_pattern(buf, n_keys: int, mask_bits: int, seed: int, sink, stre
     n_lines = buf.numel() // 8
     _check(lib().bbfc_probe_insert_pattern(buf.data_ptr(), n_lines, n_keys, int(mask_bits), seed, sink.data_ptr(),
                                            _stream_handle(stream)))
+
+
+def probe_insert_schedule(buf, n_keys: int, mask_bits: int, schedule: int, seed: int, sink, stream=None) -> None:
+    """The insert's pattern under schedule 0 (reads, then atomics), 1
+    (pipelined) or 2 (line chosen without the reads; see bbfc.h)."""
+    n_lines = buf.numel() // 8
+    _check(lib().bbfc_probe_insert_schedule(buf.data_ptr(), n_lines, n_keys, int(mask_bits), int(schedule), seed,
+                                            sink.data_ptr(), _stream_handle(stream)))
 
 
 def probe_copy(src, dst, request_bytes: int = 128, stream=None) -> None:

@@ -884,6 +884,20 @@ bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching insert-pattern probe");
 }
 
+bbfc_status bbfc_probe_insert_schedule(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t mask_bits,
+                                       int32_t schedule, uint64_t seed, uint64_t *d_sink, hipStream_t stream)
+{
+    if (d_buf == nullptr || d_sink == nullptr || !is_pow2(n_lines))
+        return fail(BBFC_EINVAL, "probe needs buffers and a power-of-two line count");
+    if (mask_bits < 1 || mask_bits > 32)
+        return fail(BBFC_EINVAL, "mask_bits must be in [1, 32], got %d", mask_bits);
+    if (schedule < 0 || schedule > 2)
+        return fail(BBFC_EINVAL, "schedule must be 0, 1 or 2, got %d", schedule);
+    hipError_t e =
+        bbfc::launch_probe_insert_schedule(d_buf, n_lines, n_keys, mask_bits, schedule, seed, d_sink, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching insert-schedule probe");
+}
+
 bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, uint32_t request_bytes,
                             hipStream_t stream)
 {

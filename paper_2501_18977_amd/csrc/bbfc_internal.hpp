@@ -115,6 +115,8 @@ hipError_t launch_probe_atomic64(uint64_t *buf, uint64_t n_lines, uint64_t n_acc
                                  hipStream_t s);
 hipError_t launch_probe_insert_pattern(uint64_t *buf, uint64_t n_lines, uint64_t n_keys, int mask_bits, uint64_t seed,
                                        uint64_t *sink, hipStream_t s);
+hipError_t launch_probe_insert_schedule(uint64_t *buf, uint64_t n_lines, uint64_t n_keys, int mask_bits,
+                                        int schedule, uint64_t seed, uint64_t *sink, hipStream_t s);
 hipError_t launch_probe_copy(const uint64_t *src, uint64_t *dst, uint64_t n_words, uint32_t request_bytes,
                              hipStream_t s);
 

@@ -158,6 +158,74 @@ __global__ __launch_bounds__(kProbeWG) void probe_insert_pattern_kernel(uint64_t
         sink[blockIdx.x & 0xFFFF] = acc;
 }
 
+// Two other schedules of the insert's pattern (same keys, lines and masks as
+// probe_insert_pattern_kernel<true>):
+//   PIPELINED  a wavefront decides all 64 keys of its unit first, then
+//              issues their atomics (every lane, an OR of 0 where its word
+//              gains nothing) and right after them the next unit's line
+//              reads, so no wait for reads ever covers the atomics;
+//   BLIND      the line is chosen from the key alone (one hash bit), not
+//              from the words read: the atomics no longer depend on the
+//              reads and issue together with them. This is not an insert
+//              (the choice ignores the blocks); it shows what the same
+//              traffic costs without the read-to-write dependency.
+template <int MODE>
+__global__ __launch_bounds__(kProbeWG) void probe_insert_schedule_kernel(uint64_t *__restrict__ buf,
+                                                                          uint64_t line_mask, uint64_t n_keys,
+                                                                          int mask_bits, uint64_t seed)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = lane >> 3;
+    const uint32_t w = lane & 7;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t n_waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    uint64_t base = wave * 64;
+    if (base >= n_keys)
+        return;
+    uint64_t v0[8], v1[8], l0[8], l1[8];
+    auto read_unit = [&](uint64_t b) __attribute__((always_inline)) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint64_t h = probe_line(seed, b + g * 8 + r);
+            l0[r] = h & line_mask;
+            l1[r] = ((h >> 32) ^ (h << 7)) & line_mask;
+            v0[r] = buf[l0[r] * 8 + w]; // lines are masked into the buffer, also past n_keys
+            v1[r] = buf[l1[r] * 8 + w];
+        }
+    };
+    read_unit(base);
+    for (;;) {
+        uint64_t cl[8], cm[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const uint64_t key = base + g * 8 + r;
+            const uint64_t m = key < n_keys ? probe_mask_word(seed, key, w, mask_bits) : 0;
+            bool second;
+            if constexpr (MODE == 1) {
+                int d = __popcll(m & ~v0[r]) - __popcll(m & ~v1[r]);
+                d += __shfl_xor(d, 1);
+                d += __shfl_xor(d, 2);
+                d += __shfl_xor(d, 4);
+                second = d > 0;
+                const uint64_t old = second ? v1[r] : v0[r];
+                cm[r] = (m & ~old) ? m : 0ull;
+            } else {
+                second = (probe_line(seed ^ 0x632BE59BD9B4E019ull, key) >> 63) != 0;
+                cm[r] = m;
+            }
+            cl[r] = second ? l1[r] : l0[r];
+        }
+        const uint64_t next = base + n_waves * 64;
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            __hip_atomic_fetch_or(&buf[cl[r] * 8 + w], cm[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (next >= n_keys)
+            break;
+        base = next;
+        read_unit(base);
+    }
+}
+
 // 64-byte requests: a wavefront takes 8 consecutive 128-byte lines per
 // unit; group g (lanes 8g..8g+7) moves the low 64-byte half of line g, then,
 // in a second instruction, its high half.
@@ -234,6 +302,26 @@ hipError_t launch_probe_insert_pattern(uint64_t *buf, uint64_t n_lines, uint64_t
     else
         hipLaunchKernelGGL(probe_insert_pattern_kernel<false>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1,
                            n_keys, 0, seed, sink);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_insert_schedule(uint64_t *buf, uint64_t n_lines, uint64_t n_keys, int mask_bits,
+                                        int schedule, uint64_t seed, uint64_t *sink, hipStream_t s)
+{
+    if (schedule == 0)
+        return launch_probe_insert_pattern(buf, n_lines, n_keys, mask_bits, seed, sink, s);
+    const void *k = schedule == 1 ? (const void *)probe_insert_schedule_kernel<1>
+                                  : (const void *)probe_insert_schedule_kernel<2>;
+    uint32_t grid = probe_grid(k);
+    const uint64_t need = (n_keys + 255) / 256;
+    if (need < grid)
+        grid = (uint32_t)(need ? need : 1);
+    if (schedule == 1)
+        hipLaunchKernelGGL(probe_insert_schedule_kernel<1>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_keys,
+                           mask_bits, seed);
+    else
+        hipLaunchKernelGGL(probe_insert_schedule_kernel<2>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_keys,
+                           mask_bits, seed);
     return hipGetLastError();
 }
 

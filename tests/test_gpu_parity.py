@@ -439,6 +439,17 @@ def test_probes_run(dev):
     assert 0 < ones <= 11 * (1 << 18)
     with pytest.raises(bbfc.BBFCError, match="mask_bits"):
         bbfc.probe_insert_pattern(buf, 1, 33, 4, sink)
+    # the same keys and masks under the other schedules set the same number
+    # of bits at most, each key's mask in one of its two lines
+    for schedule in (0, 1, 2):
+        buf.zero_()
+        bbfc.probe_insert_schedule(buf, 1 << 18, 11, schedule, 4, sink)
+        torch.cuda.synchronize()
+        got = int(np.bitwise_count(buf.cpu().numpy().view(np.uint64)).sum())
+        assert 0 < got <= 11 * (1 << 18), schedule
+    with pytest.raises(bbfc.BBFCError, match="schedule"):
+        bbfc.probe_insert_schedule(buf, 1, 11, 3, 4, sink)
+    buf.zero_()
     bbfc.probe_atomic64(buf, 1 << 18, 2)
     dst = torch.empty_like(buf)
     bbfc.probe_copy(buf, dst)
