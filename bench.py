@@ -165,7 +165,7 @@ def device_props(props) -> dict:
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     for rel in ("paper_2501_18977_amd/csrc/bbfc_kernels.hip", "paper_2501_18977_amd/csrc/bbfc_common.hpp",
-                "paper_2501_18977_amd/csrc/bbfc_tile.hpp"):
+                "paper_2501_18977_amd/csrc/bbfc_tile.hpp", "paper_2501_18977_amd/csrc/bbfc_batch.hip"):
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
