@@ -182,6 +182,19 @@ def with_traffic(rec: dict, traffic, ms: float) -> dict:
     return rec
 
 
+def measured_fetch_kib(kernel: str, config: dict, summary: str = "traffic.json"):
+    """FETCH_SIZE KiB per dispatch of `kernel` from the committed counter
+    summary, under the same validity rules as measured_traffic."""
+    try:
+        with open(os.path.join(ROOT, "profiles", summary)) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha") != kernel_source_sha() or rec.get("config") != config:
+        return None
+    return rec.get("fetch_kib_per_dispatch", {}).get(kernel)
+
+
 def measured_traffic(op: str, kernel: str, config: dict, summary: str = "traffic.json"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE per dispatch, scaled by the copy
@@ -1276,6 +1289,17 @@ def main():
         "bytes_per_launch_algorithmic": int(q_bytes),
         "launch_ms": round(avg_qry, 3),
     }, measured_traffic("query", q_kernel, traffic_cfg), avg_qry)
+    # With early exit a query reads candidate 2 only for keys candidate 1 did
+    # not answer. The counters give the blocks actually read per key: one
+    # 128-byte request per block, FETCH_SIZE counting 64 bytes per request,
+    # less the key stream's 8 bytes per key (1/16 request).
+    fkib = measured_fetch_kib(q_kernel, traffic_cfg)
+    if fkib:
+        blocks = fkib * 1024 / 64 / n_q - 8 / 128
+        ee_bytes = (8 + 64 * blocks + 1 / 8) * n_q
+        roofline_query["blocks_per_key_read"] = round(blocks, 4)
+        roofline_query["bytes_per_launch_early_exit"] = int(ee_bytes)
+        roofline_query["frac_early_exit_bytes"] = round(ee_bytes / (avg_qry / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
 
     probe = None
     if not args.no_probe:
@@ -1361,12 +1385,20 @@ def main():
         "paper_cpu_reference": PAPER_CPU_REFERENCE,
         "kernel_source_sha": kernel_source_sha(),
     }
-    filt.close()
     legs_ok = True
-    if not args.no_legs and args.log2_keys == 30 and T == 1 and args.insert == "racing" and args.bits == "random":
+    with_legs = not args.no_legs and args.log2_keys == 30 and T == 1 and args.insert == "racing" and args.bits == "random"
+    if with_legs:
         del keys, out
         torch.cuda.empty_cache()
-        rec["legs"], legs_ok = run_legs(args)
+        print("legs: serve", file=sys.stderr, flush=True)
+        serve = serve_leg(filt, n)
+        legs_ok &= serve["same_as_plain_query"]
+    filt.close()
+    if with_legs:
+        torch.cuda.empty_cache()
+        rec["legs"], ok = run_legs(args)
+        rec["legs"]["serve"] = serve
+        legs_ok &= ok
     print(json.dumps(rec), flush=True)
     if not fn_free or not legs_ok:
         sys.exit(1)
@@ -1375,6 +1407,87 @@ def main():
 # what a leg keeps of its workload's full record
 _LEG_DROP = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "host",
              "kernel_source_sha", "steps", "warmup")
+
+
+def serve_leg(filt, n: int, n_requests: int = 10000) -> dict:
+    """Serving, compact, on the headline's built filter: a Poisson stream of
+    query requests (sizes log-uniform in [1, 65536], half inserted keys) with
+    keys and answers in device memory, replayed through the continuous-
+    batching server (4 slots of 2^20 keys) at two offered loads, beside one
+    plain query launch per request. Sampled requests' answers must equal a
+    plain query of the same keys."""
+    import numpy as np
+    import torch
+
+    import paper_2501_18977_amd as bbfc
+    import workload
+
+    dev = torch.device("cuda:0")
+    sizes, pst, nst = workload.serve_requests(11, n_requests, n)
+    parts = []
+    for sz, p, q in zip(sizes, pst, nst):
+        npos = (sz + 1) // 2
+        parts.append(workload.splitmix64_keys(0, p, npos))
+        parts.append(workload.splitmix64_keys(0, q, sz - npos))
+    flat = np.concatenate(parts)
+    offs = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(sizes)
+    total = int(offs[-1])
+    mean_size = total / len(sizes)
+    d_flat = torch.from_numpy(flat.view(np.int64)).to(dev)
+    dout = torch.empty(1024, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    srv = bbfc.Server(filt, n_slots=4, max_batch_keys=1 << 20, max_pending_keys=1 << 27)
+    n_warm = min(1000, len(sizes))
+    srv.replay_device(d_flat[: int(offs[n_warm])], offs[: n_warm + 1], np.zeros(n_warm))
+    rng = np.random.default_rng(5)
+    loads = []
+    out = None
+    # each offered load replays the stream three times (a few ms each); the
+    # median replay is reported, the three achieved rates beside it
+    for offered in (8e9, 32e9):
+        reps = []
+        for _ in range(3):
+            arrivals = np.cumsum(rng.exponential(mean_size / offered, size=len(sizes)))
+            out, oo, lat, wall = srv.replay_device(d_flat, offs, arrivals, out=out)
+            reps.append((total / wall / 1e6, float(np.percentile(lat, 50)), float(np.percentile(lat, 99))))
+        reps_sorted = sorted(reps)
+        med = reps_sorted[1]
+        loads.append({"offered_mkeys_s": offered / 1e6, "achieved_mkeys_s": round(med[0], 1),
+                      "p50_us": round(med[1], 1), "p99_us": round(med[2], 1),
+                      "achieved_each_mkeys_s": [round(r[0], 1) for r in reps]})
+    srv.close()
+    n_base = min(len(sizes), 2000)
+    lat_b = []
+    t0 = time.perf_counter()
+    for i in range(n_base):
+        t = time.perf_counter()
+        filt.query(d_flat[int(offs[i]):int(offs[i + 1])], out=dout)
+        torch.cuda.synchronize()
+        lat_b.append((time.perf_counter() - t) * 1e6)
+    base_wall = time.perf_counter() - t0
+    words = out.cpu().numpy().view(np.uint64)
+    same = True
+    for i in range(0, len(sizes), max(1, len(sizes) // 200)):
+        want = filt.query(d_flat[int(offs[i]):int(offs[i + 1])]).cpu().numpy().view(np.uint64)
+        same &= bool(np.array_equal(words[int(oo[i]):int(oo[i + 1])], want[: int(oo[i + 1] - oo[i])]))
+    best = max(loads, key=lambda r: r["achieved_mkeys_s"])
+    del d_flat, out
+    return {
+        "value": best["achieved_mkeys_s"],
+        "unit": "Mkeys/s",
+        "config": {"workload": (f"serve: the headline's filter; {len(sizes)} Poisson query requests, sizes log-uniform "
+                                f"in [1, 65536] (mean {mean_size:.0f} keys), half inserted keys, keys and answers in "
+                                "device memory; continuous batching over 4 slots of 2^20 keys"),
+                   "requests": len(sizes), "total_keys_per_load": total},
+        "loads_device": loads,
+        "plain_device_one_request_at_a_time": {"requests": n_base,
+                                               "mkeys_s": round(int(offs[n_base]) / base_wall / 1e6, 1),
+                                               "p50_us": round(float(np.percentile(lat_b, 50)), 1),
+                                               "p99_us": round(float(np.percentile(lat_b, 99)), 1)},
+        "same_as_plain_query": same,
+        "roofline": None,
+    }
 
 
 def run_legs(args):

@@ -478,13 +478,19 @@ typedef struct bbfc_server *bbfc_server_handle;
  *     keys submitted but not yet staged (a request is still admitted when
  *     nothing is pending, whatever its size); poll_us: a slot's worker polls
  *     its batch for completion, yielding between polls for the first 1 ms
- *     and then sleeping poll_us between polls (0: yielding throughout). Defaults (config == NULL): 4 slots,
- *     2^20 keys per batch, 2^28 pending keys, 20 us. */
+ *     and then sleeping poll_us between polls (0: yielding throughout);
+ *     batch_window_us: while other batches are on the device, the worker
+ *     gathering the next batch waits up to this long after the oldest
+ *     pending request's arrival for more requests (or until half a batch is
+ *     pending); with the device idle a batch goes at once (0: never wait).
+ *     Both at most 100000. Defaults (config == NULL): 4 slots, 2^20 keys per
+ *     batch, 2^28 pending keys, 20 us, 20 us. */
 typedef struct {
     uint32_t n_slots;
     uint64_t max_batch_keys;
     uint64_t max_pending_keys;
     uint32_t poll_us;
+    uint32_t batch_window_us;
 } bbfc_server_config;
 
 /* Starts one worker thread per slot serving queries on `filter`. Requests

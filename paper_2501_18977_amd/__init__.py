@@ -73,7 +73,8 @@ class _Config(ctypes.Structure):
 
 class _ServerConfig(ctypes.Structure):
     _fields_ = [("n_slots", ctypes.c_uint32), ("max_batch_keys", ctypes.c_uint64),
-                ("max_pending_keys", ctypes.c_uint64), ("poll_us", ctypes.c_uint32)]
+                ("max_pending_keys", ctypes.c_uint64), ("poll_us", ctypes.c_uint32),
+                ("batch_window_us", ctypes.c_uint32)]
 
 
 class _Shape(ctypes.Structure):
@@ -627,9 +628,9 @@ class Server:
     GPU tensors (submit_device, replay_device)."""
 
     def __init__(self, filt: Filter, n_slots: int = 4, max_batch_keys: int = 1 << 20,
-                 max_pending_keys: int = 1 << 28, poll_us: int = 20):
+                 max_pending_keys: int = 1 << 28, poll_us: int = 20, batch_window_us: int = 20):
         self._filter = filt
-        cfg = _ServerConfig(n_slots, max_batch_keys, max_pending_keys, poll_us)
+        cfg = _ServerConfig(n_slots, max_batch_keys, max_pending_keys, poll_us, batch_window_us)
         h = ctypes.c_void_p()
         _check(lib().bbfc_server_create(filt.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -14,7 +14,13 @@
 // cores at once and batches of different slots overlap on the device.
 // Admission is by memory: at most max_pending_keys keys are queued (submit
 // answers BBFC_EBUSY beyond that), and a batch never holds more than a
-// slot's staging.
+// slot's staging. One worker at a time gathers the next batch: a submission
+// wakes a worker only when one waits and none is gathering, and while other
+// batches are on the device the gatherer waits up to batch_window_us from the
+// oldest request's arrival for more requests (or half a batch). Without the
+// window, idle workers woken once per request launch one-request batches,
+// and their wake-ups slow the submitting thread so much that no backlog ever
+// builds up to form larger batches.
 //
 // Requests whose keys and answers are in device memory join the same queue.
 // A batch holds requests of one kind: a device batch stages nothing; its
@@ -93,6 +99,9 @@ struct bbfc_server {
     std::unordered_map<uint64_t, std::shared_ptr<Request>> by_ticket;
     uint64_t next_ticket = 1;
     uint64_t pending_keys = 0;
+    uint32_t idle = 0;       // workers waiting for work
+    uint32_t in_flight = 0;  // batches on the device
+    bool collecting = false; // a worker is gathering the next batch
     bool stop = false;
     hipError_t error = hipSuccess;
     // statistics
@@ -217,16 +226,35 @@ void slot_worker(bbfc_server *sp, Slot *slot_p)
     bbfc::DeviceGuard guard(s.filter->device);
     std::unique_lock<std::mutex> lk(s.mu);
     for (;;) {
-        s.cv_work.wait(lk, [&] { return s.stop || !s.pending.empty(); });
+        // one worker at a time gathers the next batch; the others wait
+        ++s.idle;
+        s.cv_work.wait(lk, [&] { return s.stop || (!s.pending.empty() && !s.collecting); });
+        --s.idle;
         if (s.pending.empty())
             break; // stopping, and nothing left to serve
+        s.collecting = true;
+        // Batching window: while another batch is on the device, wait up to
+        // batch_window_us after the oldest pending request's arrival for more
+        // requests, unless half a batch is pending already. With the device
+        // idle the batch goes at once.
+        if (s.cfg.batch_window_us > 0 && s.in_flight > 0) {
+            const Clock::time_point until =
+                s.pending.front()->t_submit + std::chrono::microseconds(s.cfg.batch_window_us);
+            while (!s.stop && s.pending_keys < s.cfg.max_batch_keys / 2 && Clock::now() < until) {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            }
+        }
         const uint64_t used = plan_slot(s, slot);
-        if (!s.pending.empty())
+        s.collecting = false;
+        if (!s.pending.empty() && s.idle > 0)
             s.cv_work.notify_one(); // more work than this slot holds: wake another worker
         if (used == 0)
             continue;
         s.batches++;
         s.batched_keys += used;
+        s.in_flight++;
         lk.unlock();
         hipError_t e = launch_slot(s, slot, used);
         if (e == hipSuccess)
@@ -237,6 +265,7 @@ void slot_worker(bbfc_server *sp, Slot *slot_p)
             (void)hipStreamSynchronize(slot.stream); // nothing of this batch may still read the staging
         const Clock::time_point now = Clock::now();
         lk.lock();
+        s.in_flight--;
         if (e != hipSuccess && s.error == hipSuccess)
             s.error = e;
         finish_slot(s, slot, now);
@@ -244,46 +273,83 @@ void slot_worker(bbfc_server *sp, Slot *slot_p)
     }
 }
 
-bbfc_status submit_at(bbfc_server_handle s, const uint64_t *h_keys, uint64_t n, uint64_t *h_out_bits,
-                      uint64_t *ticket, Clock::time_point t_arrival, bool device)
+// Checks a request's arguments (no lock) and makes its record.
+bbfc_status make_request(const uint64_t *keys, uint64_t n, uint64_t *out, Clock::time_point t_arrival, bool device,
+                         std::shared_ptr<Request> &r)
 {
-    if (s == nullptr || ticket == nullptr || (n > 0 && (h_keys == nullptr || h_out_bits == nullptr)))
-        return bbfc::fail(BBFC_EINVAL, "null server, ticket, keys or output");
+    if (n > 0 && (keys == nullptr || out == nullptr))
+        return bbfc::fail(BBFC_EINVAL, "null keys or output");
     if (device && n > 0) {
-        const uintptr_t k0 = (uintptr_t)h_keys, k1 = k0 + n * 8;
-        const uintptr_t o0 = (uintptr_t)h_out_bits, o1 = o0 + ((n + 63) / 64) * 8;
+        const uintptr_t k0 = (uintptr_t)keys, k1 = k0 + n * 8;
+        const uintptr_t o0 = (uintptr_t)out, o1 = o0 + ((n + 63) / 64) * 8;
         if (k0 < o1 && o0 < k1)
             return bbfc::fail(BBFC_EINVAL, "output overlaps the keys");
     }
-    auto r = std::make_shared<Request>();
-    r->keys = h_keys;
+    r = std::make_shared<Request>();
+    r->keys = keys;
     r->n = n;
-    r->out = h_out_bits;
+    r->out = out;
     r->device = device;
     r->t_submit = t_arrival;
+    return BBFC_OK;
+}
+
+// Admits reqs[0 .. count) in order under one lock acquisition, as far as
+// admission allows (the first one always fits when nothing is pending);
+// tickets[i] receives each admitted request's ticket. *admitted receives how
+// many were; BBFC_EBUSY when admission stopped short.
+bbfc_status admit(bbfc_server_handle s, const std::shared_ptr<Request> *reqs, size_t count, uint64_t *tickets,
+                  size_t *admitted)
+{
+    size_t i = 0;
+    bool wake = false;
+    bbfc_status st = BBFC_OK;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop)
             return bbfc::fail(BBFC_EINVAL, "server is stopping");
         if (s->error != hipSuccess)
             return bbfc::hip_fail(s->error, "server failed earlier");
-        if (n > 0 && s->pending_keys + n > s->cfg.max_pending_keys && !s->pending.empty())
-            return bbfc::fail(BBFC_EBUSY, "admission: %llu keys already pending",
-                              (unsigned long long)s->pending_keys);
-        r->ticket = s->next_ticket++;
-        s->by_ticket[r->ticket] = r;
-        if (n == 0) {
-            r->done = true;
-            r->t_done = r->t_submit;
-            s->completed++;
-        } else {
-            s->pending.push_back(r);
-            s->pending_keys += n;
+        for (; i < count; ++i) {
+            const std::shared_ptr<Request> &r = reqs[i];
+            if (r->n > 0 && s->pending_keys + r->n > s->cfg.max_pending_keys && !s->pending.empty()) {
+                st = bbfc::fail(BBFC_EBUSY, "admission: %llu keys already pending",
+                                (unsigned long long)s->pending_keys);
+                break;
+            }
+            r->ticket = s->next_ticket++;
+            s->by_ticket[r->ticket] = r;
+            if (r->n == 0) {
+                r->done = true;
+                r->t_done = r->t_submit;
+                s->completed++;
+            } else {
+                s->pending.push_back(r);
+                s->pending_keys += r->n;
+                // wake a worker only if one is waiting and none is gathering
+                // a batch already (that one sees the new requests under the lock)
+                wake = wake || (s->idle > 0 && !s->collecting);
+            }
+            tickets[i] = r->ticket;
         }
-        *ticket = r->ticket;
     }
-    s->cv_work.notify_one();
-    return BBFC_OK;
+    if (wake)
+        s->cv_work.notify_one();
+    *admitted = i;
+    return st;
+}
+
+bbfc_status submit_at(bbfc_server_handle s, const uint64_t *h_keys, uint64_t n, uint64_t *h_out_bits,
+                      uint64_t *ticket, Clock::time_point t_arrival, bool device)
+{
+    if (s == nullptr || ticket == nullptr)
+        return bbfc::fail(BBFC_EINVAL, "null server or ticket");
+    std::shared_ptr<Request> r;
+    const bbfc_status st = make_request(h_keys, n, h_out_bits, t_arrival, device, r);
+    if (st != BBFC_OK)
+        return st;
+    size_t admitted = 0;
+    return admit(s, &r, 1, ticket, &admitted);
 }
 
 } // namespace
@@ -297,7 +363,7 @@ bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *con
 {
     if (filter == nullptr || out == nullptr)
         return fail(BBFC_EINVAL, "null filter or output handle");
-    bbfc_server_config cfg{4, 1u << 20, 1ull << 28, 20};  // defaults
+    bbfc_server_config cfg{4, 1u << 20, 1ull << 28, 20, 20};  // defaults
     if (config)
         cfg = *config;
     if (cfg.n_slots < 1 || cfg.n_slots > 16)
@@ -308,6 +374,8 @@ bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *con
         return fail(BBFC_EINVAL, "max_pending_keys must be >= 1");
     if (cfg.poll_us > 100000)
         return fail(BBFC_EINVAL, "poll_us must be <= 100000");
+    if (cfg.batch_window_us > 100000)
+        return fail(BBFC_EINVAL, "batch_window_us must be <= 100000");
     auto *s = new bbfc_server();
     s->filter = filter;
     s->cfg = cfg;
@@ -445,23 +513,40 @@ bbfc_status replay(bbfc_server_handle s, const uint64_t *h_keys, const uint64_t 
     for (uint32_t i = 0; i + 1 < n_requests; ++i)
         if (arrival_s[i + 1] < arrival_s[i])
             return fail(BBFC_EINVAL, "arrival times must be non-decreasing");
+    std::vector<std::shared_ptr<Request>> reqs(n_requests);
     std::vector<uint64_t> tickets(n_requests, 0);
     const Clock::time_point t0 = Clock::now();
-    for (uint32_t i = 0; i < n_requests; ++i) {
-        const Clock::time_point due = t0 + std::chrono::duration_cast<Clock::duration>(
-                                               std::chrono::duration<double>(arrival_s[i]));
+    auto due_at = [&](uint32_t i) {
+        return t0 + std::chrono::duration_cast<Clock::duration>(std::chrono::duration<double>(arrival_s[i]));
+    };
+    uint32_t next = 0; // first request not admitted yet
+    while (next < n_requests) {
+        const Clock::time_point due = due_at(next);
         while (Clock::now() < due) {
         }
-        for (;;) {
-            // latency counts from the scheduled arrival, also while admission waits
-            const bbfc_status st = submit_at(s, h_keys + req_offsets[i], req_offsets[i + 1] - req_offsets[i],
-                                             h_out_bits + out_offsets[i], &tickets[i], due, device);
-            if (st == BBFC_OK)
-                break;
-            if (st != BBFC_EBUSY)
-                return st;
-            std::this_thread::sleep_for(std::chrono::microseconds(10)); // admission: retry when memory frees
+        // every request whose arrival has passed is admitted together, with
+        // one lock acquisition: a submitter behind its schedule catches up
+        // instead of falling further behind
+        const Clock::time_point now = Clock::now();
+        uint32_t end = next + 1;
+        while (end < n_requests && due_at(end) <= now)
+            ++end;
+        for (uint32_t i = next; i < end; ++i) {
+            if (!reqs[i]) {
+                // latency counts from the scheduled arrival, also while admission waits
+                const bbfc_status st = make_request(h_keys + req_offsets[i], req_offsets[i + 1] - req_offsets[i],
+                                                    h_out_bits + out_offsets[i], due_at(i), device, reqs[i]);
+                if (st != BBFC_OK)
+                    return st;
+            }
         }
+        size_t admitted = 0;
+        const bbfc_status st = admit(s, reqs.data() + next, end - next, tickets.data() + next, &admitted);
+        next += (uint32_t)admitted;
+        if (st == BBFC_EBUSY)
+            std::this_thread::sleep_for(std::chrono::microseconds(10)); // admission: retry when memory frees
+        else if (st != BBFC_OK)
+            return st;
     }
     for (uint32_t i = 0; i < n_requests; ++i) {
         const bbfc_status st = bbfc_server_wait(s, tickets[i], -1.0, &latency_us[i]);

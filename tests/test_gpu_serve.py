@@ -166,6 +166,24 @@ def test_device_replay_under_tight_admission(served, dev):
         assert np.array_equal(words[int(oo[i]):int(oo[i + 1])], ref.query_bits(r)), i
 
 
+@pytest.mark.parametrize("window", [0, 200])
+def test_device_requests_with_and_without_batching_window(served, dev, window):
+    """Gathering batches for a window (or never) changes only how requests
+    are grouped: every answer equals the oracle's."""
+    ref, f, keys = served
+    reqs = make_requests(keys, [1, 5000, 64, 70_000, 3, 4097] * 4, 15)
+    d_reqs = [_dev(r, dev) for r in reqs]
+    torch.cuda.synchronize()
+    srv = bbfc.Server(f, n_slots=4, max_batch_keys=1 << 14, batch_window_us=window)
+    try:
+        tickets = [srv.submit_device(r) for r in d_reqs]
+        got = [_host_words(srv.wait(t)[0]).copy() for t in tickets]
+    finally:
+        srv.close()
+    for r, g in zip(reqs, got):
+        assert np.array_equal(g, ref.query_bits(r))
+
+
 def test_device_request_overlapping_output_rejected(served, dev):
     _, f, _ = served
     buf = torch.zeros(4096, dtype=torch.int64, device=dev)
@@ -263,7 +281,8 @@ def test_replay_under_tight_admission(served):
 
 def test_server_config_validation(served):
     _, f, _ = served
-    for kw in ({"n_slots": 0}, {"n_slots": 17}, {"max_batch_keys": 100}, {"max_pending_keys": 0}):
+    for kw in ({"n_slots": 0}, {"n_slots": 17}, {"max_batch_keys": 100}, {"max_pending_keys": 0},
+               {"batch_window_us": 100001}):
         with pytest.raises(bbfc.BBFCError):
             bbfc.Server(f, **kw)
 
