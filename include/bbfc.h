@@ -340,7 +340,9 @@ uint64_t bbfc_blocks_for(uint64_t n_keys, double space_bits_per_key);
  * (k+1)*513 entries. Pure host computation (no device needed). */
 bbfc_status bbfc_rank_table(bbfc_cost cost, uint32_t bits_per_key, uint16_t *out);
 
-const char *bbfc_status_string(bbfc_status s);
+/* Text of a status code (a bbfc_status value, taken as a plain int so that
+ * any value is valid); unknown codes give "unknown status". */
+const char *bbfc_status_string(int32_t s);
 const char *bbfc_last_error(void);
 
 /* ------------------------------------------------------------------ */

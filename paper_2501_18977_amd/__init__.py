@@ -51,7 +51,9 @@ DECISION_PRESENT = 0xFF
 _COST_BY_NAME = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libbbfc.so")
+# BBFC_LIBRARY names another build of the same library to load instead (the
+# CPU tests use it for a build whose host code carries sanitizers).
+_LIB_PATH = os.environ.get("BBFC_LIBRARY") or os.path.join(_HERE, "libbbfc.so")
 
 
 class BBFCError(RuntimeError):

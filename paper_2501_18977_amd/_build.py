@@ -70,6 +70,42 @@ def build(extra_flags: list[str] | None = None, out: str | None = None, verbose:
     return out
 
 
+# Host code under AddressSanitizer and UndefinedBehaviorSanitizer (device
+# code is not instrumented: each flag applies to the host pass only).
+HOST_SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+HOST_SANITIZED = ["bbfc_api.cpp", "bbfc_server.cpp"]
+SAN_LIB = os.path.join(HERE, "_build", "libbbfc_hostsan.so")
+
+
+def build_host_sanitized() -> str:
+    """libbbfc_hostsan.so: the library with the host code of the C ABI and
+    the server (the sources whose host logic runs without a device) built
+    with sanitizers, linked with the other objects of the regular build
+    (which must exist: build() makes them). Loaded through BBFC_LIBRARY by
+    the CPU tests, with the compiler's ASan runtime preloaded."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    flags = [hipcc(), *[f for f in HIP_FLAGS if f not in ("-shared", "-O3")], "-O1", "-g", *HOST_SANITIZE,
+             "-I", os.path.join(ROOT, "include")]
+
+    def compile_one(src: str) -> str:
+        obj = os.path.join(objdir, src + ".hostsan.o")
+        subprocess.run([*flags, "-c", "-o", obj, os.path.join(CSRC, src)], check=True)
+        return obj
+
+    others = [os.path.join(objdir, s + ".o") for s in SOURCES if s not in HOST_SANITIZED]
+    missing = [o for o in others if not os.path.exists(o)]
+    if missing:
+        raise RuntimeError(f"regular objects missing ({missing[0]}): run build() first")
+    with ThreadPoolExecutor(max_workers=2) as ex:
+        objs = list(ex.map(compile_one, HOST_SANITIZED))
+    tmp = SAN_LIB + ".tmp"
+    subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *others], check=True)
+    os.replace(tmp, SAN_LIB)
+    return SAN_LIB
+
+
 def is_stale() -> bool:
     if not os.path.exists(LIB):
         return True

@@ -828,7 +828,7 @@ bbfc_status bbfc_rank_table(bbfc_cost cost, uint32_t bits_per_key, uint16_t *out
     return BBFC_OK;
 }
 
-const char *bbfc_status_string(bbfc_status s)
+const char *bbfc_status_string(int32_t s)
 {
     switch (s) {
     case BBFC_OK:
