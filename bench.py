@@ -275,6 +275,53 @@ def cpu_baseline(n_blocks, c, k, target_s, distinct=False, subarrays=1):
     }
 
 
+def cpu_baseline_scaled(n_keys, n_blocks, c, k, scale=32):
+    """The sequential oracle on the whole workload scaled down by `scale`:
+    n_keys/scale keys (SplitMix64 counters of seed 0) inserted one at a time
+    into n_blocks/scale blocks (the same bits per key, k, c and cost, so the
+    filter passes through every load level of the real build), then the
+    inserted keys and as many never-inserted keys queried, one thread; the
+    query also on all host threads (up to 16)."""
+    import numpy as np
+
+    import oracle
+    import workload
+
+    n_s, m_s = n_keys // scale, n_blocks // scale
+    f = oracle.OracleFilter(m_s, c, k, oracle.COST_LA, None, seed=0)
+    keys = workload.positive_keys(0, n_s)
+    probe = np.concatenate([keys, workload.negative_keys(0, n_s, n_s)])
+    t = time.perf_counter()
+    f.insert(keys)
+    t_ins = time.perf_counter() - t
+    t = time.perf_counter()
+    f.count_hits(probe)
+    t_q = time.perf_counter() - t
+    from concurrent.futures import ThreadPoolExecutor
+
+    n_thr = max(1, min(16, os.cpu_count() or 1))
+    parts = np.array_split(probe, n_thr)
+    t = time.perf_counter()
+    with ThreadPoolExecutor(n_thr) as ex:
+        sum(ex.map(f.count_hits, parts))
+    t_qmt = time.perf_counter() - t
+    r_ins, r_q = n_s / t_ins, 2 * n_s / t_q
+    return {
+        "value": round(3.0 / (1.0 / r_ins + 2.0 / r_q) / 1e6, 3),
+        "unit": "Mkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"the whole workload at 1/{scale} scale: {n_s} sequential inserts into {m_s} blocks "
+                   f"({m_s * 64 >> 20} MiB; the same 16 bits per key, k, c and cost, so every load level of the "
+                   f"build), then {2 * n_s} queries (half inserted), one thread, {t_ins + t_q:.1f} s; rates "
+                   "combined with the step's 1 insert : 2 queries mix"),
+        "insert_mkeys_s": round(r_ins / 1e6, 3),
+        "query_mkeys_s": round(r_q / 1e6, 3),
+        "query_threads": n_thr,
+        "query_all_threads_mkeys_s": round(2 * n_s / t_qmt / 1e6, 3),
+    }
+
+
 def cpu_baseline_batch(specs, target_s):
     """The sequential oracle on a bounded sample of the batch workload: the
     filters in order, each built from its own keys and queried with as many
@@ -1331,7 +1378,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(n_blocks, c, k, args.cpu_seconds, distinct=args.bits == "distinct", subarrays=T)
+        if args.bits == "random" and T == 1 and n >= (1 << 25):
+            cpu = cpu_baseline_scaled(n, n_blocks, c, k)
+            # the earlier sample on the full-size (nearly empty) filter, beside it
+            cpu["full_size_sample"] = cpu_baseline(n_blocks, c, k, args.cpu_seconds / 2)
+        else:
+            cpu = cpu_baseline(n_blocks, c, k, args.cpu_seconds, distinct=args.bits == "distinct", subarrays=T)
 
     rec = {
         "metric": "Mkeys/s insert & query, 2-choice 512b blocks; % of random-access HBM peak",
