@@ -486,7 +486,7 @@ typedef struct bbfc_server *bbfc_server_handle;
  *     pending request's arrival for more requests (or until half a batch is
  *     pending); with the device idle a batch goes at once (0: never wait).
  *     Both at most 100000. Defaults (config == NULL): 4 slots, 2^20 keys per
- *     batch, 2^28 pending keys, 20 us, 20 us. */
+ *     batch, 2^28 pending keys, 20 us, 0. */
 typedef struct {
     uint32_t n_slots;
     uint64_t max_batch_keys;

@@ -630,7 +630,7 @@ class Server:
     GPU tensors (submit_device, replay_device)."""
 
     def __init__(self, filt: Filter, n_slots: int = 4, max_batch_keys: int = 1 << 20,
-                 max_pending_keys: int = 1 << 28, poll_us: int = 20, batch_window_us: int = 20):
+                 max_pending_keys: int = 1 << 28, poll_us: int = 20, batch_window_us: int = 0):
         self._filter = filt
         cfg = _ServerConfig(n_slots, max_batch_keys, max_pending_keys, poll_us, batch_window_us)
         h = ctypes.c_void_p()

@@ -14,13 +14,13 @@
 // cores at once and batches of different slots overlap on the device.
 // Admission is by memory: at most max_pending_keys keys are queued (submit
 // answers BBFC_EBUSY beyond that), and a batch never holds more than a
-// slot's staging. One worker at a time gathers the next batch: a submission
-// wakes a worker only when one waits and none is gathering, and while other
-// batches are on the device the gatherer waits up to batch_window_us from the
-// oldest request's arrival for more requests (or half a batch). Without the
-// window, idle workers woken once per request launch one-request batches,
-// and their wake-ups slow the submitting thread so much that no backlog ever
-// builds up to form larger batches.
+// slot's staging. One worker at a time gathers the next batch, and a
+// submission wakes a worker only when one waits and none is gathering, so a
+// stream of single submissions does not pay a wake-up each. With
+// batch_window_us > 0, while other batches are on the device the gatherer
+// waits up to that long from the oldest request's arrival for more requests
+// (or half a batch): larger batches for submitters that cannot hand over
+// their requests together, at the price of latency.
 //
 // Requests whose keys and answers are in device memory join the same queue.
 // A batch holds requests of one kind: a device batch stages nothing; its
@@ -363,7 +363,7 @@ bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *con
 {
     if (filter == nullptr || out == nullptr)
         return fail(BBFC_EINVAL, "null filter or output handle");
-    bbfc_server_config cfg{4, 1u << 20, 1ull << 28, 20, 20};  // defaults
+    bbfc_server_config cfg{4, 1u << 20, 1ull << 28, 20, 0};  // defaults
     if (config)
         cfg = *config;
     if (cfg.n_slots < 1 || cfg.n_slots > 16)
