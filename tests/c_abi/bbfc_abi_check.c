@@ -12,7 +12,13 @@
  *  4. argument errors return BBFC_EINVAL with a message and enqueue nothing;
  *  5. a filter with sub-arrays (Section 3.4) from bbfc_create_config, filled
  *     by the bulk insert in a caller-owned workspace, is the oracle's
- *     one-at-a-time build word for word.
+ *     one-at-a-time build word for word;
+ *  6. the racing insert that records its decisions: every decision names a
+ *     candidate or "present", and the oracle's placement of the decided
+ *     keys' masks is the filter word for word (Sections 3.1, 3.2);
+ *  7. the sequential insert without allocation, on an input larger than one
+ *     window, equals the allocating one and the oracle, twice in a row;
+ *  8. the server with device-resident requests answers as the oracle.
  */
 #include <math.h>
 #include <stdio.h>
@@ -33,6 +39,9 @@ uint64_t bbo_query(const uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t 
 void bbo_derive_multipliers(uint64_t seed, uint64_t M, uint64_t T, uint32_t c, uint32_t k, int distinct,
                             uint64_t *block_mult, uint64_t *bit_mult, uint64_t *sub_mult);
 double bbo_default_param(int kind, uint32_t k);
+uint64_t bbo_place(uint64_t *W, const bbo_layout *L, uint32_t c, uint32_t k, int distinct, const uint64_t *block_mult,
+                   const uint64_t *bit_mult, const uint64_t *keys, const uint8_t *decision, uint64_t n,
+                   uint64_t part_mod, uint64_t part_rem);
 
 static int failures = 0;
 
@@ -166,6 +175,89 @@ int main(void)
         free(got5);
         free(want5);
         CHECK(bbfc_destroy(s5) == BBFC_OK, "destroy");
+    }
+
+    /* 6. the racing insert with recorded decisions */
+    {
+        const uint64_t M6 = 4096;
+        bbfc_handle r6 = NULL;
+        CHECK(bbfc_create_seeded(M6, 2, 11, la, 6, &r6) == BBFC_OK, "create: %s", bbfc_last_error());
+        uint8_t *d_dec = NULL;
+        HIP(hipMalloc((void **)&d_dec, n));
+        CHECK(bbfc_insert_recorded(r6, d_keys, n, d_dec, NULL) == BBFC_OK, "insert_recorded: %s", bbfc_last_error());
+        CHECK(bbfc_insert_recorded(r6, d_keys, 10, (uint8_t *)d_keys + 8, NULL) == BBFC_EINVAL,
+              "decisions overlapping the keys accepted");
+        uint8_t *dec = malloc(n);
+        HIP(hipMemcpy(dec, d_dec, n, hipMemcpyDeviceToHost));
+        uint64_t bm6[4], am6[32];
+        CHECK(bbfc_get_params(r6, NULL, NULL, NULL, NULL, bm6, am6) == BBFC_OK, "get_params");
+        uint64_t bad_dec = 0;
+        for (uint64_t t = 0; t < n; t++)
+            bad_dec += dec[t] >= 2 && dec[t] != BBFC_DECISION_PRESENT;
+        CHECK(bad_dec == 0, "%llu decisions name no candidate", (unsigned long long)bad_dec);
+        uint64_t *got6 = malloc(M6 * 64), *want6 = calloc(M6 * 8, 8);
+        CHECK(bbfc_download(r6, got6, NULL) == BBFC_OK, "download");
+        const bbo_layout L6 = {M6, 1, 0};
+        bbo_place(want6, &L6, 2, 11, 0, bm6, am6, h_keys, dec, n, 1, 0);
+        CHECK(memcmp(got6, want6, M6 * 64) == 0, "the recorded decisions do not rebuild the filter");
+        HIP(hipFree(d_dec));
+        free(dec);
+        free(got6);
+        free(want6);
+        CHECK(bbfc_destroy(r6) == BBFC_OK, "destroy");
+    }
+
+    /* 7. the sequential insert without allocation (inputs above one window use
+     * the static scratch), twice in a row, against the allocating insert and
+     * the oracle */
+    for (int call = 0; call < 2; call++) {
+        const uint64_t n7 = call == 0 ? nq : nq - 20000; /* both above 2^16 keys */
+        bbfc_handle x = NULL, y = NULL;
+        CHECK(bbfc_create_seeded(M, c, k, exp_cost, 5, &x) == BBFC_OK, "create");
+        CHECK(bbfc_create_seeded(M, c, k, exp_cost, 5, &y) == BBFC_OK, "create");
+        CHECK(bbfc_insert_deterministic_noalloc(x, d_keys, n7, NULL) == BBFC_OK, "noalloc: %s", bbfc_last_error());
+        CHECK(bbfc_insert_deterministic(y, d_keys, n7, NULL) == BBFC_OK, "deterministic: %s", bbfc_last_error());
+        uint64_t *wx = malloc(M * 64), *wy = malloc(M * 64), *wo = calloc(M * 8, 8);
+        CHECK(bbfc_download(x, wx, NULL) == BBFC_OK && bbfc_download(y, wy, NULL) == BBFC_OK, "download");
+        bbo_insert(wo, &L, c, k, 0, BBFC_COST_EXP, bbo_default_param(BBFC_COST_EXP, k), bm, am, h_keys, n7);
+        CHECK(memcmp(wx, wy, M * 64) == 0, "call %d: the no-allocation insert differs from the allocating one", call);
+        CHECK(memcmp(wx, wo, M * 64) == 0, "call %d: the no-allocation insert differs from the oracle", call);
+        free(wx);
+        free(wy);
+        free(wo);
+        CHECK(bbfc_destroy(x) == BBFC_OK && bbfc_destroy(y) == BBFC_OK, "destroy");
+    }
+
+    /* 8. device-resident requests against the deterministic filter `a`: each
+     * request starts on a 64-key boundary, so its answer words are the
+     * oracle's words from there, the last one cut at its length */
+    {
+        bbfc_server_handle srv = NULL;
+        CHECK(bbfc_server_create(a, NULL, &srv) == BBFC_OK, "server_create: %s", bbfc_last_error());
+        const uint64_t starts[4] = {0, 640, 6400, 50048}, lens[4] = {1, 4097, 30000, 49000};
+        uint64_t *d_ans = NULL;
+        HIP(hipMalloc((void **)&d_ans, 4 * 1024 * 8));
+        uint64_t tickets[4];
+        for (int i = 0; i < 4; i++)
+            CHECK(bbfc_server_submit_device(srv, d_keys + starts[i], lens[i], d_ans + i * 1024, &tickets[i]) == BBFC_OK,
+                  "submit_device: %s", bbfc_last_error());
+        for (int i = 0; i < 4; i++)
+            CHECK(bbfc_server_wait(srv, tickets[i], -1.0, NULL) == BBFC_OK, "wait: %s", bbfc_last_error());
+        uint64_t *ans = malloc(4 * 1024 * 8);
+        HIP(hipMemcpy(ans, d_ans, 4 * 1024 * 8, hipMemcpyDeviceToHost));
+        for (int i = 0; i < 4; i++) {
+            const uint64_t words = (lens[i] + 63) / 64;
+            for (uint64_t w = 0; w < words; w++) {
+                uint64_t want = want_bits[starts[i] / 64 + w];
+                if (w == words - 1 && lens[i] % 64)
+                    want &= (1ull << (lens[i] % 64)) - 1;
+                CHECK(ans[i * 1024 + w] == want, "request %d word %llu differs from the oracle", i,
+                      (unsigned long long)w);
+            }
+        }
+        CHECK(bbfc_server_destroy(srv) == BBFC_OK, "server_destroy");
+        HIP(hipFree(d_ans));
+        free(ans);
     }
 
     CHECK(bbfc_destroy(a) == BBFC_OK, "destroy");
