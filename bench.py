@@ -67,7 +67,13 @@ def parse_args():
     ap.add_argument("--insert", choices=["racing", "bulk", "exact"], default="racing",
                     help="plain workload: racing atomic insert, the sequential bulk insert (needs sub-arrays), "
                          "or the sequential insert on any layout (bbfc_insert_deterministic)")
+    ap.add_argument("--insert-tile", type=int, choices=[0, 1, 2], default=0,
+                    help="plain workload, racing insert: keys per wavefront tile chosen by the library (0), "
+                         "64 keys (1) or 8 keys (2)")
     ap.add_argument("--filters", type=int, default=256, help="batch workload: number of filters")
+    ap.add_argument("--cap-sweep", action="store_true",
+                    help="small workload: instead of the step, sweep the racing insert's keys-in-flight bound over "
+                         "several small filters (insert time and false positives against the sequential build)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
                     help="plain workload: skip the small-filter, batch and kmer legs of the default run")
@@ -478,8 +484,9 @@ def small_workload(steps: int, warmup: int, with_cpu: bool) -> dict:
     2^20 never-inserted keys are queried. One step = clear + insert + query.
 
     Three inserts are timed: the library's default racing insert (keys in
-    flight capped at n_blocks/32 = 1024), the racing insert with every key
-    allowed in flight at once, and the sequential insert (exact). Each build's
+    flight capped at n_blocks/8 = 4096, in tiles of 8 keys), the racing
+    insert with every key allowed in flight at once (tiles of 64 keys), and
+    the sequential insert (exact). Each build's
     false-positive count over 2^24 further never-inserted keys is compared
     with the sequential build's (outside the timed steps). The roofline is the
     insert's algorithmic bytes against the HBM peak, beside random-line read
@@ -536,10 +543,11 @@ def small_workload(steps: int, warmup: int, with_cpu: bool) -> dict:
     variants = {}
     cap = f.get_option(bbfc.OPT_INSERT_INFLIGHT)
     variants["racing_default_cap"] = run(lambda: f.insert(keys[:n], stream))
-    variants["racing_default_cap"]["keys_in_flight"] = M // 32 if cap == 0 else cap
+    default_launch = f.insert_launch_info(n)
+    variants["racing_default_cap"].update(default_launch)
     f.set_option(bbfc.OPT_INSERT_INFLIGHT, n)
     variants["racing_uncapped"] = run(lambda: f.insert(keys[:n], stream))
-    variants["racing_uncapped"]["keys_in_flight"] = n
+    variants["racing_uncapped"].update(f.insert_launch_info(n))
     f.set_option(bbfc.OPT_INSERT_INFLIGHT, cap)
     variants["exact"] = run(lambda: f.insert_deterministic(keys[:n], stream))
     fp_exact = variants["exact"]["false_positives"]
@@ -568,6 +576,20 @@ def small_workload(steps: int, warmup: int, with_cpu: bool) -> dict:
         ms = e0.elapsed_time(e1)
         key = "_Gkeys_s" if name.startswith("insert") else "_Glines_s"
         probe[name + key] = round(acc / (ms / 1e3) / 1e9, 2)
+    # one wavefront's round trips: over the filter-sized buffer, and the key
+    # stream from a 64 MiB buffer (fresh lines every step)
+    lat = torch.zeros(1, dtype=torch.float64, device=dev)
+    stream_buf = torch.zeros(1 << 23, dtype=torch.int64, device=dev)
+    for name, kind, b in (("line_read", 0, buf), ("atomic_or", 1, buf), ("read_then_atomic_or", 2, buf),
+                          ("key_load", 3, stream_buf)):
+        bbfc.probe_latency(b, kind, lat, 2000, stream)
+        torch.cuda.synchronize()
+        probe[f"latency_ns_{name}"] = round(float(lat.item()), 1)
+    del stream_buf
+    # one tile's time in the default insert: each working wavefront handles
+    # n / keys_in_flight tiles one after another
+    probe["default_insert_us_per_tile"] = round(
+        default["insert_ms"] * 1e3 / (n / default_launch["keys_in_flight"]), 3)
     probe["buffer_bytes"] = M * 64
     probe["query_ceiling_mkeys_s"] = round(probe["rand64_read_Glines_s"] * 1e3 / c, 1)
     probe["query_frac_of_ceiling"] = round(default["query_mkeys_s"] / probe["query_ceiling_mkeys_s"], 4)
@@ -589,17 +611,104 @@ def small_workload(steps: int, warmup: int, with_cpu: bool) -> dict:
         "insert_mkeys_s": default["insert_mkeys_s"],
         "query_mkeys_s": default["query_mkeys_s"],
         "variants": variants,
-        "roofline": {"bound": "hbm", "kernel": f"insert_kernel<{c}, 8, 1, ArrayKeys>",
+        "roofline": {"bound": "hbm",
+                     "kernel": (f"insert_narrow_kernel<{c}, ArrayKeys, false>" if default_launch["tile_keys"] == 8
+                                else f"insert_kernel<{c}, 8, 1, ArrayKeys>"),
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_launch_algorithmic": int(ins_bytes),
                      "launch_ms": default["insert_ms"], "traffic": None,
-                     "note": "the filter is cache resident and the default insert keeps 1024 keys in flight: "
-                             "bound by the latency of its memory round trips, not by bandwidth"},
+                     "note": f"the filter is cache resident and the default insert keeps "
+                             f"{default_launch['keys_in_flight']} keys in flight in tiles of "
+                             f"{default_launch['tile_keys']} keys: bound by the latency of its memory round trips, "
+                             "not by bandwidth"},
         "probe": probe,
         "cpu_baseline": cpu_baseline_small(n, M, c, k) if with_cpu else None,
     }
     f.close()
     return rec
+
+
+def default_inflight(n_blocks: int, c: int) -> int:
+    """The library's default bound on a racing insert's keys in flight
+    (BBFC_OPT_INSERT_INFLIGHT = 0), for labels only."""
+    return 1 << 62 if c == 1 else max(64, n_blocks // (8 * (c - 1)))
+
+
+# (n_blocks, choices, k, cost, bits per key) of the bound sweep
+CAP_SWEEP_CONFIGS = [
+    (1 << 15, 2, 14, "la", 16),
+    (1 << 15, 2, 11, "la", 16),
+    (1 << 15, 3, 8, "mix", 12),
+    (1 << 15, 4, 12, "la", 16),
+    (1 << 15, 2, 6, "exp", 8),
+    (1 << 15, 3, 14, "exp", 20),
+    (1 << 18, 2, 11, "la", 16),
+    (3000, 2, 11, "la", 16),
+]
+
+
+def cap_sweep(args):
+    """For each small filter: the sequential build's false positives over 2^28
+    never-inserted keys, then five racing builds at each bound on keys in
+    flight (n_blocks/32 .. n_blocks, with tiles of 8 and of 64 keys, and the
+    default), with the launch (tile, keys in flight, workgroups), the median
+    insert time and the mean false positives relative to the sequential
+    build.
+    Keys: SplitMix64 seed 2 from 0 (n = n_blocks * 512 / bits per key);
+    negatives: seed 1. One JSON line per filter."""
+    import numpy as np
+    import torch
+
+    import paper_2501_18977_amd as bbfc
+    import workload
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    chunk, n_chunks, reps = 1 << 24, 16, 5
+    neg = [workload.device_keys(1, i * chunk, chunk, device=dev) for i in range(n_chunks)]
+    out = torch.empty(chunk // 64, dtype=torch.int64, device=dev)
+    for M, c, k, cost, bpk in CAP_SWEEP_CONFIGS:
+        n = M * 512 // bpk
+        keys = workload.device_keys(2, 0, n, device=dev)
+        f = bbfc.Filter(M, c, k, cost, seed=3)
+
+        def false_positives():
+            tot = 0
+            for q in neg:
+                f.query(q, out=out, stream=stream)
+                tot += int(np.bitwise_count(out.cpu().numpy().view(np.uint64)).sum())
+            return tot
+
+        f.clear(stream)
+        f.insert_deterministic(keys, stream)
+        torch.cuda.synchronize()
+        fp_seq = false_positives()
+        row = {"n_blocks": M, "choices": c, "k": k, "cost": cost, "bits_per_key": bpk, "n_keys": n,
+               "negatives": chunk * n_chunks, "sequential_fp": fp_seq,
+               "sequential_fp_sigma_rel": round(fp_seq ** -0.5, 5), "default_keys_in_flight": default_inflight(M, c),
+               "bounds": {}}
+        runs = [(f"n_blocks/{d} {tile_name}", max(64, M // d), tile)
+                for d in (32, 16, 8, 4, 2, 1) for tile_name, tile in (("tile8", 2), ("tile64", 1))]
+        for label, bound, tile in runs + [("default", 0, 0)]:
+            f.set_option(bbfc.OPT_INSERT_INFLIGHT, bound)
+            f.set_option(bbfc.OPT_INSERT_TILE, tile)
+            times, fps = [], []
+            for _ in range(reps):
+                f.clear(stream)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                f.insert(keys, stream)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+                fps.append(false_positives())
+            ms = float(np.median(times))
+            row["bounds"][label] = {**f.insert_launch_info(n), "insert_ms": round(ms, 4),
+                                    "insert_gkeys_s": round(n / ms / 1e6, 3),
+                                    "fp_vs_sequential_rel": round(float(np.mean(fps)) / fp_seq - 1, 5)}
+        f.close()
+        print(json.dumps(row), flush=True)
 
 
 def bench_small(args):
@@ -1205,7 +1314,7 @@ def main():
         print(json.dumps(run_probes()), flush=True)
         return
     if args.workload == "small":
-        bench_small(args)
+        cap_sweep(args) if args.cap_sweep else bench_small(args)
         return
     if args.workload == "batch":
         bench_batch(args)
@@ -1242,6 +1351,7 @@ def main():
     if args.insert == "bulk" and T == 1:
         sys.exit("--insert bulk needs --subarray-blocks (at most 1024)")
     filt = bbfc.Filter(n_blocks, c, k, "la", seed=0, bit_selection=args.bits, subarrays=T)
+    filt.set_option(bbfc.OPT_INSERT_TILE, args.insert_tile)
     ws = None
     if args.insert == "bulk":
         ws = torch.empty(filt.bulk_workspace_bytes(n), dtype=torch.uint8, device=dev)
@@ -1305,7 +1415,8 @@ def main():
     avg_qry = sum(qry_ms) / len(qry_ms)
     if avg_ins >= avg_qry and args.insert == "racing":
         dom, dom_ms, dom_bytes = "insert", avg_ins, INSERT_BYTES_PER_KEY * n
-        dom_kernel = kernel_name("insert", c, filt.get_shape(bbfc.OP_INSERT))
+        dom_kernel = (kernel_name("insert", c, filt.get_shape(bbfc.OP_INSERT))
+                      if filt.insert_launch_info(n)["tile_keys"] == 64 else f"insert_narrow_kernel<{c}, ArrayKeys, false>")
     else:
         dom, dom_ms, dom_bytes = "query", avg_qry, QUERY_BYTES_PER_KEY * n_q
         dom_kernel = kernel_name("query", c, filt.get_shape(bbfc.OP_QUERY))
@@ -1426,6 +1537,7 @@ def main():
         "zero_false_negatives": fn_free,
         "fpr_negatives": fpr,
         "tuned_shapes": tuned,
+        "insert_launch": filt.insert_launch_info(n) if args.insert == "racing" else None,
         "roofline": roofline,
         "roofline_query": roofline_query,
         "probe": probe,
@@ -1438,7 +1550,8 @@ def main():
         "kernel_source_sha": kernel_source_sha(),
     }
     legs_ok = True
-    with_legs = not args.no_legs and args.log2_keys == 30 and T == 1 and args.insert == "racing" and args.bits == "random"
+    with_legs = (not args.no_legs and args.log2_keys == 30 and T == 1 and args.insert == "racing"
+                 and args.bits == "random" and args.insert_tile == 0)
     if with_legs:
         del keys, out
         torch.cuda.empty_cache()

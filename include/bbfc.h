@@ -169,9 +169,9 @@ bbfc_status bbfc_destroy(bbfc_handle h);
  * call decide on block contents that may miss the bits of keys still in
  * flight, so the filter may differ from a one-key-at-a-time build; the
  * library bounds the keys in flight to a fraction of n_blocks (see
- * BBFC_OPT_INSERT_INFLIGHT) so that the false-positive rate stays that of
- * the sequential build. With choices == 1 the result equals the sequential
- * build bit for bit. n == 0 is a no-op. Errors: EINVAL (null handle, null
+ * BBFC_OPT_INSERT_INFLIGHT) so that the false-positive rate stays within
+ * about 1% of the sequential build's. With choices == 1 the result equals
+ * the sequential build bit for bit, and the keys in flight are not bounded. n == 0 is a no-op. Errors: EINVAL (null handle, null
  * keys with n > 0), EHIP. */
 bbfc_status bbfc_insert(bbfc_handle h, const uint64_t *d_keys, uint64_t n, hipStream_t stream);
 
@@ -283,21 +283,45 @@ bbfc_status bbfc_get_words(bbfc_handle h, uint64_t **d_words);
 /* Launch options of one filter (all have defaults; none changes a result
  * except where stated):
  *   BBFC_OPT_INSERT_INFLIGHT  upper bound on keys a racing insert keeps in
- *       flight; 0 (default) means n_blocks/32, at least one wavefront of 64.
- *       A larger bound is faster on small filters, at the price of
- *       decisions on staler block contents (the filter can differ, its
- *       false-positive rate drifts upwards; zero false negatives holds).
+ *       flight; 0 (default) means n_blocks/(8(choices-1)), at least one
+ *       wavefront of 64, and no bound with one choice. The bound matters
+ *       only where it is below what the GPU holds resident (about 2.6e5
+ *       keys, so filters under about 2^21 blocks with two choices): there
+ *       the insert is bound by memory latency and its rate grows with the
+ *       bound, at the price of decisions on staler block contents (the
+ *       filter can differ, its false-positive rate drifts upwards; zero
+ *       false negatives holds).
  *   BBFC_OPT_QUERY_EARLY_EXIT  1 (default): a query reads candidate i+1
  *       only for keys that candidates 1..i did not answer; 0: every
  *       candidate is read. Answers are identical either way.
+ *   BBFC_OPT_INSERT_TILE  keys per wavefront tile of the racing insert.
+ *       0 (default): chosen by the bound on keys in flight; bounds up to
+ *       65536 keys take tiles of 8 keys (eight lanes per key, each key's
+ *       hashing spread over its lanes, one short round per tile, at most
+ *       four workgroups of 4 wavefronts per CU, for inserts bound by
+ *       latency), larger bounds tiles of 64 keys with the insert's launch
+ *       shape (which the tiles of 8 keys do not use). 1: tiles of 64 keys;
+ *       2: tiles of 8 keys. The racing insert's guarantees hold either way.
  * Errors: EINVAL (null handle or pointer, unknown option, value out of
  * range). */
 typedef enum {
     BBFC_OPT_INSERT_INFLIGHT = 1,
-    BBFC_OPT_QUERY_EARLY_EXIT = 2
+    BBFC_OPT_QUERY_EARLY_EXIT = 2,
+    BBFC_OPT_INSERT_TILE = 3
 } bbfc_option;
 bbfc_status bbfc_set_option(bbfc_handle h, int32_t option, int64_t value);
 bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value);
+
+/* What bbfc_insert of n keys would launch on this filter under its current
+ * options and shape; nothing is enqueued. *tile_keys: keys per wavefront
+ * tile (64 or 8); *keys_in_flight: the most keys the launch works on at
+ * once (working wavefronts x tiles per wavefront x keys per tile), which
+ * is the bound of BBFC_OPT_INSERT_INFLIGHT rounded down to whole
+ * wavefronts (at least one), and at most n rounded up to whole tiles;
+ * *workgroups: the grid. Outputs may be null. Errors: EINVAL (null
+ * handle), EHIP. */
+bbfc_status bbfc_insert_launch_info(bbfc_handle h, uint64_t n, uint32_t *tile_keys, uint64_t *keys_in_flight,
+                                    uint64_t *workgroups);
 
 /* Launch shape of the kernels for one operation (a filter and a batch plan
  * hold one per operation): lanes per key (8 or 4: 8 or 16 bytes per lane
@@ -607,6 +631,21 @@ bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_
  * another schedule. */
 bbfc_status bbfc_probe_insert_schedule(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t mask_bits,
                                        int32_t schedule, uint64_t seed, uint64_t *d_sink, hipStream_t stream);
+
+/* Round-trip latency of one wavefront's dependent memory steps: `waves`
+ * workgroups of one wavefront (1..1024) each time `iters` steps (1..2^20)
+ * with the device's constant-rate clock and write the mean nanoseconds
+ * per step to d_out[w] (device memory, `waves` doubles). d_buf holds
+ * n_lines 64-byte lines (a power of two, >= 8); eight lanes share a line,
+ * as in the filter kernels. kind 0: a random line read whose address
+ * depends on the previous read; 1: a random 64-bit atomic OR and the wait
+ * for it (sets bits in d_buf); 2: a random line read, then an atomic OR
+ * into the line just read, and the wait for both (the racing insert's
+ * round trip); 3: a coalesced 512-byte load of the next words of d_buf
+ * (read as a key stream), its address depending on the previous load.
+ * Errors: EINVAL for null buffers or arguments out of range; EHIP. */
+bbfc_status bbfc_probe_latency(uint64_t *d_buf, uint64_t n_lines, int32_t kind, uint32_t iters, uint32_t waves,
+                               double *d_out, hipStream_t stream);
 
 /* Plain copy of n_words words, to calibrate the traffic counters. With
  * request_bytes == 128 every lane moves 16 contiguous bytes (128-byte

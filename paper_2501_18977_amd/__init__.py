@@ -46,7 +46,7 @@ COST_NONE, COST_MIX, COST_LA, COST_EXP = 0, 1, 2, 3
 BITS_RANDOM, BITS_DISTINCT = 0, 1
 _BITS_BY_NAME = {"random": BITS_RANDOM, "distinct": BITS_DISTINCT}
 OP_INSERT, OP_QUERY = 0, 1
-OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT = 1, 2
+OPT_INSERT_INFLIGHT, OPT_QUERY_EARLY_EXIT, OPT_INSERT_TILE = 1, 2, 3
 DECISION_PRESENT = 0xFF
 _COST_BY_NAME = {"none": COST_NONE, "mix": COST_MIX, "la": COST_LA, "exp": COST_EXP}
 
@@ -131,6 +131,7 @@ def lib() -> ctypes.CDLL:
         "bbfc_get_words": (_st, [_vp, _vp]),
         "bbfc_set_option": (_st, [_vp, ctypes.c_int32, ctypes.c_int64]),
         "bbfc_get_option": (_st, [_vp, ctypes.c_int32, _vp]),
+        "bbfc_insert_launch_info": (_st, [_vp, ctypes.c_uint64, _vp, _vp, _vp]),
         "bbfc_blocks_for": (_u64, [_u64, ctypes.c_double]),
         "bbfc_rank_table": (_st, [_Cost, _u32, _vp]),
         "bbfc_status_string": (ctypes.c_char_p, [_st]),
@@ -140,6 +141,7 @@ def lib() -> ctypes.CDLL:
         "bbfc_probe_copy": (_st, [_vp, _vp, _u64, _u32, _vp]),
         "bbfc_probe_insert_pattern": (_st, [_vp, _u64, _u64, ctypes.c_int32, _u64, _vp, _vp]),
         "bbfc_probe_insert_schedule": (_st, [_vp, _u64, _u64, ctypes.c_int32, ctypes.c_int32, _u64, _vp, _vp]),
+        "bbfc_probe_latency": (_st, [_vp, _u64, ctypes.c_int32, _u32, _u32, _vp, _vp]),
         "bbfc_batch_create": (_st, [_vp, _vp, _u32, _vp]),
         "bbfc_batch_destroy": (_st, [_vp]),
         "bbfc_batch_layout": (_st, [_vp, _vp, _vp]),
@@ -355,6 +357,14 @@ class Filter:
         v = ctypes.c_int64()
         _check(lib().bbfc_get_option(self.handle, option, ctypes.byref(v)))
         return int(v.value)
+
+    def insert_launch_info(self, n: int) -> dict:
+        """What an insert of n keys would launch: keys per wavefront tile,
+        the keys it works on at once, and workgroups (nothing launched)."""
+        tile, inflight, wgs = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().bbfc_insert_launch_info(self.handle, int(n), ctypes.byref(tile), ctypes.byref(inflight),
+                                             ctypes.byref(wgs)))
+        return {"tile_keys": int(tile.value), "keys_in_flight": int(inflight.value), "workgroups": int(wgs.value)}
 
     def set_shape(self, op: int, lanes_per_key: int = 8, tiles_per_wave: int = 1, wgs_per_cu: int = 0) -> None:
         _check(lib().bbfc_set_shape(self.handle, op, _Shape(lanes_per_key, tiles_per_wave, wgs_per_cu, 0, 0.0)))
@@ -771,6 +781,18 @@ def probe_insert_schedule(buf, n_keys: int, mask_bits: int, schedule: int, seed:
     n_lines = buf.numel() // 8
     _check(lib().bbfc_probe_insert_schedule(buf.data_ptr(), n_lines, n_keys, int(mask_bits), int(schedule), seed,
                                             sink.data_ptr(), _stream_handle(stream)))
+
+
+def probe_latency(buf, kind: int, out, iters: int = 2000, stream=None) -> None:
+    """Mean nanoseconds per dependent step of one memory round trip, one
+    wavefront per entry of out (a float64 device tensor): kind 0 line read,
+    1 atomic OR, 2 read then atomic OR on that line, 3 key-stream load (see
+    bbfc.h)."""
+    if out.dtype.itemsize != 8 or not out.is_contiguous():
+        raise BBFCError(-1, "out must be a contiguous float64 tensor")
+    n_lines = buf.numel() // 8
+    _check(lib().bbfc_probe_latency(buf.data_ptr(), n_lines, int(kind), int(iters), out.numel(), out.data_ptr(),
+                                    _stream_handle(stream)))
 
 
 def probe_copy(src, dst, request_bytes: int = 128, stream=None) -> None:

@@ -675,6 +675,11 @@ bbfc_status bbfc_set_option(bbfc_handle h, int32_t option, int64_t value)
             return fail(BBFC_EINVAL, "BBFC_OPT_QUERY_EARLY_EXIT takes 0 or 1");
         h->query_early_exit = (int)value;
         return BBFC_OK;
+    case BBFC_OPT_INSERT_TILE:
+        if (value > 2)
+            return fail(BBFC_EINVAL, "BBFC_OPT_INSERT_TILE takes 0 (by keys in flight), 1 (64 keys) or 2 (8 keys)");
+        h->insert_tile = (int)value;
+        return BBFC_OK;
     default:
         return fail(BBFC_EINVAL, "unknown option %d", (int)option);
     }
@@ -691,9 +696,33 @@ bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value)
     case BBFC_OPT_QUERY_EARLY_EXIT:
         *value = h->query_early_exit;
         return BBFC_OK;
+    case BBFC_OPT_INSERT_TILE:
+        *value = h->insert_tile;
+        return BBFC_OK;
     default:
         return fail(BBFC_EINVAL, "unknown option %d", (int)option);
     }
+}
+
+bbfc_status bbfc_insert_launch_info(bbfc_handle h, uint64_t n, uint32_t *tile_keys, uint64_t *keys_in_flight,
+                                    uint64_t *workgroups)
+{
+    if (h == nullptr)
+        return fail(BBFC_EINVAL, "null handle");
+    if (n > kMaxKeys)
+        return fail(BBFC_EINVAL, "n = %llu keys exceeds 2^56", (unsigned long long)n);
+    DeviceGuard guard(h->device);
+    bbfc::InsertGeom g{};
+    const hipError_t e = bbfc::insert_geometry(*h, n, &g);
+    if (e != hipSuccess)
+        return hip_fail(e, "insert launch geometry");
+    if (tile_keys != nullptr)
+        *tile_keys = g.tile_keys;
+    if (keys_in_flight != nullptr)
+        *keys_in_flight = g.waves * g.tiles_per_wave * g.tile_keys;
+    if (workgroups != nullptr)
+        *workgroups = g.workgroups;
+    return BBFC_OK;
 }
 
 bbfc_status bbfc_set_shape(bbfc_handle h, int32_t op, bbfc_launch_shape shape)
@@ -896,6 +925,19 @@ bbfc_status bbfc_probe_insert_schedule(uint64_t *d_buf, uint64_t n_lines, uint64
     hipError_t e =
         bbfc::launch_probe_insert_schedule(d_buf, n_lines, n_keys, mask_bits, schedule, seed, d_sink, stream);
     return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching insert-schedule probe");
+}
+
+bbfc_status bbfc_probe_latency(uint64_t *d_buf, uint64_t n_lines, int32_t kind, uint32_t iters, uint32_t waves,
+                               double *d_out, hipStream_t stream)
+{
+    if (d_buf == nullptr || d_out == nullptr || !is_pow2(n_lines) || n_lines < 8)
+        return fail(BBFC_EINVAL, "probe needs buffers and a power-of-two line count of at least 8");
+    if (kind < 0 || kind > 3)
+        return fail(BBFC_EINVAL, "kind must be 0..3, got %d", kind);
+    if (iters < 1 || iters > (1u << 20) || waves < 1 || waves > 1024)
+        return fail(BBFC_EINVAL, "iters must be in [1, 2^20] and waves in [1, 1024]");
+    hipError_t e = bbfc::launch_probe_latency(d_buf, n_lines, kind, iters, waves, d_out, stream);
+    return e == hipSuccess ? BBFC_OK : hip_fail(e, "launching latency probe");
 }
 
 bbfc_status bbfc_probe_copy(const uint64_t *d_src, uint64_t *d_dst, uint64_t n_words, uint32_t request_bytes,

@@ -26,8 +26,9 @@ struct bbfc_filter {
     std::vector<uint16_t> h_rank;
     int device = 0;
     int num_cus = 0;
-    uint64_t max_inflight = 0;    // 0: n_blocks/32
+    uint64_t max_inflight = 0;    // 0: n_blocks/(8(c-1)), no bound for c = 1
     int query_early_exit = 1;     // load choice i+1 only for keys still unanswered
+    int insert_tile = 0;          // racing insert kernel: 0 by keys in flight, 1 tiles of 64 keys, 2 of 8 keys
     // launch shape per operation, [BBFC_OP_INSERT] and [BBFC_OP_QUERY]
     bbfc_launch_shape shape[2] = {{8, 1, 0, 0, 0.0f}, {8, 1, 0, 0, 0.0f}};
     size_t max_lds = 65536;       // LDS bytes a workgroup may use on this device
@@ -65,6 +66,17 @@ size_t rank_lds_bytes(uint32_t c, uint32_t k);
 
 // Keys in flight for a racing insert on this filter.
 uint64_t insert_inflight(const bbfc_filter &f);
+// Keys per wavefront tile of the racing insert the filter launches (64 or 8).
+uint32_t insert_tile_keys(const bbfc_filter &f);
+// What a racing insert of n keys launches: keys per tile, tiles per
+// wavefront, working wavefronts and workgroups (nothing is launched).
+struct InsertGeom {
+    uint32_t tile_keys;
+    uint32_t tiles_per_wave;
+    uint64_t waves;
+    uint64_t workgroups;
+};
+hipError_t insert_geometry(const bbfc_filter &f, uint64_t n, InsertGeom *geom);
 
 hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s);
 // The racing insert that also writes each key's decision (bbfc_insert_recorded).
@@ -117,6 +129,8 @@ hipError_t launch_probe_insert_pattern(uint64_t *buf, uint64_t n_lines, uint64_t
                                        uint64_t *sink, hipStream_t s);
 hipError_t launch_probe_insert_schedule(uint64_t *buf, uint64_t n_lines, uint64_t n_keys, int mask_bits,
                                         int schedule, uint64_t seed, uint64_t *sink, hipStream_t s);
+hipError_t launch_probe_latency(uint64_t *buf, uint64_t n_lines, int kind, uint32_t iters, uint32_t waves,
+                                double *out, hipStream_t s);
 hipError_t launch_probe_copy(const uint64_t *src, uint64_t *dst, uint64_t n_words, uint32_t request_bytes,
                              hipStream_t s);
 

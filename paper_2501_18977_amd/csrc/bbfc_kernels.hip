@@ -4,6 +4,7 @@
 // of one filter to resident wavefronts.
 #include <stdint.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include <hip/hip_runtime.h>
@@ -68,7 +69,8 @@ __global__ __launch_bounds__(kWGSize) void query_pieces_kernel(KParams p, const 
 }
 
 template <int C, int LPK, int T, typename Src>
-__global__ __launch_bounds__(kWGSize) void insert_kernel(KParams p, Src keys, uint64_t n, uint64_t n_units)
+__global__ __launch_bounds__(kWGSize) void insert_kernel(KParams p, Src keys, uint64_t n, uint64_t n_units,
+                                                         uint64_t n_waves)
 {
     __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
     __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
@@ -76,16 +78,42 @@ __global__ __launch_bounds__(kWGSize) void insert_kernel(KParams p, Src keys, ui
     load_rank_table<C>(p, s_rank);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave;
-    const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerWG;
-    for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerWG + wv; u < n_units; u += n_waves)
+    // n_waves <= the grid's wavefronts: the ones past it idle, which bounds
+    // the keys in flight to n_waves * T * 64 exactly
+    const uint64_t first = (uint64_t)blockIdx.x * kWavesPerWG + wv;
+    for (uint64_t u = first < n_waves ? first : n_units; u < n_units; u += n_waves)
         insert_tiles<C, LPK, T>(p, s_rank, keys, n, u * T * kTile, lane, s_mask[wv], s_blk[wv]);
+}
+
+// Racing insert in tiles of 8 keys (insert_narrow_tile), for bounds on the
+// keys in flight that leave the GPU mostly idle; n_waves as in insert_kernel.
+template <int C, typename Src, bool REC>
+__global__ __launch_bounds__(kWGSize) void insert_narrow_kernel(KParams p, Src keys, uint64_t n, uint64_t n_units,
+                                                                uint64_t n_waves, uint8_t *__restrict__ rec)
+{
+    __shared__ uint32_t s_mask[kWavesPerWG][kNarrowKeys * kSlotDw];
+    extern __shared__ uint16_t s_rank[];
+    load_rank_table<C>(p, s_rank);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wv = threadIdx.x / kWave;
+    // multipliers of f_(8j + l) for this lane's l, selected with constant
+    // indices so that they stay in registers
+    const uint32_t l = lane % 8;
+    uint64_t am[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < (int)BBFC_MAX_BITS_PER_KEY; ++i)
+        if ((uint32_t)(i % 8) == l)
+            am[i / 8] = p.bit_mult[i];
+    const uint64_t first = (uint64_t)blockIdx.x * kWavesPerWG + wv;
+    for (uint64_t u = first < n_waves ? first : n_units; u < n_units; u += n_waves)
+        insert_narrow_tile<C, Src, REC>(p, s_rank, keys, n, u * kNarrowKeys, lane, am, s_mask[wv], rec);
 }
 
 // insert_kernel that also writes each key's decision to rec[t] (see
 // insert_tiles): a checking aid with the same schedule, never the timed kernel.
 template <int C, int LPK, int T, typename Src>
 __global__ __launch_bounds__(kWGSize) void insert_recorded_kernel(KParams p, Src keys, uint64_t n, uint64_t n_units,
-                                                                  uint8_t *__restrict__ rec)
+                                                                  uint64_t n_waves, uint8_t *__restrict__ rec)
 {
     __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
     __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
@@ -93,8 +121,8 @@ __global__ __launch_bounds__(kWGSize) void insert_recorded_kernel(KParams p, Src
     load_rank_table<C>(p, s_rank);
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave;
-    const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerWG;
-    for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerWG + wv; u < n_units; u += n_waves)
+    const uint64_t first = (uint64_t)blockIdx.x * kWavesPerWG + wv;
+    for (uint64_t u = first < n_waves ? first : n_units; u < n_units; u += n_waves)
         insert_tiles<C, LPK, T, Src, true>(p, s_rank, keys, n, u * T * kTile, lane, s_mask[wv], s_blk[wv], rec);
 }
 
@@ -154,8 +182,34 @@ KParams make_kparams(const bbfc_filter &f)
 
 uint64_t insert_inflight(const bbfc_filter &f)
 {
-    uint64_t lim = f.max_inflight ? f.max_inflight : f.M / 32;
+    uint64_t lim = f.max_inflight;
+    if (lim == 0) {
+        // One candidate: the filter is the OR of every key's mask in any
+        // order, so nothing is gained by holding keys back.
+        if (f.c == 1)
+            return UINT64_MAX >> 8;
+        // A decision can miss bits that keys still in flight are about to
+        // set in the candidates it weighs; the drift of the false-positive
+        // rate grows with keys in flight per block and with the number of
+        // other candidates weighed, c - 1.
+        lim = f.M / (8 * (uint64_t)(f.c - 1));
+    }
     return lim < (uint64_t)kTile ? (uint64_t)kTile : lim;
+}
+
+// Bounds up to this many keys in flight take the tiles of 8 keys: there the
+// wide tiles would leave most of the GPU idle and each wavefront's own
+// latency sets the rate.
+constexpr uint64_t kNarrowMaxInflight = 1u << 16;
+// Workgroups of tiles of 8 keys per CU at most (128 keys): more resident
+// workgroups lowered the rate (on 2^18- and 2^25-block filters).
+constexpr int kNarrowWgsPerCU = 4;
+
+uint32_t insert_tile_keys(const bbfc_filter &f)
+{
+    if (f.insert_tile != 0)
+        return f.insert_tile == 2 ? (uint32_t)kNarrowKeys : (uint32_t)kTile;
+    return insert_inflight(f) <= kNarrowMaxInflight ? (uint32_t)kNarrowKeys : (uint32_t)kTile;
 }
 
 size_t rank_lds_bytes(uint32_t c, uint32_t k)
@@ -194,27 +248,58 @@ uint64_t grid_for(K kernel, size_t dyn_lds, int num_cus, int wgs_per_cu, uint64_
 }
 
 template <int C, int LPK, int T, typename Src, bool REC = false>
-hipError_t insert_launch(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr)
+hipError_t insert_launch(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr,
+                         InsertGeom *geom = nullptr)
 {
     const uint64_t n_units = (n + (uint64_t)T * kTile - 1) / ((uint64_t)T * kTile);
     const size_t lds = rank_lds_bytes(f.c, f.k);
-    // keys in flight = wavefronts * T * 64, bounded by the filter's cap
-    const uint64_t cap_waves = insert_inflight(f) / ((uint64_t)T * kTile);
-    const uint64_t cap_wgs = (cap_waves + kWavesPerWG - 1) / kWavesPerWG;
-    uint64_t need = (n_units + kWavesPerWG - 1) / kWavesPerWG;
-    if (cap_wgs < need)
-        need = cap_wgs;
+    // keys in flight = working wavefronts * T * 64, bounded by the filter's cap
+    uint64_t cap_waves = insert_inflight(f) / ((uint64_t)T * kTile);
+    if (cap_waves < 1)
+        cap_waves = 1;
+    if (cap_waves > n_units)
+        cap_waves = n_units;
+    const uint64_t need = (cap_waves + kWavesPerWG - 1) / kWavesPerWG;
     if constexpr (REC) {
         const uint64_t wgs = grid_for(insert_recorded_kernel<C, LPK, T, Src>, lds, f.num_cus,
                                       f.shape[BBFC_OP_INSERT].wgs_per_cu, need);
+        const uint64_t n_waves = std::min<uint64_t>(wgs * kWavesPerWG, cap_waves);
         hipLaunchKernelGGL((insert_recorded_kernel<C, LPK, T, Src>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s,
-                           make_kparams(f), keys, n, n_units, rec);
+                           make_kparams(f), keys, n, n_units, n_waves, rec);
     } else {
         const uint64_t wgs =
             grid_for(insert_kernel<C, LPK, T, Src>, lds, f.num_cus, f.shape[BBFC_OP_INSERT].wgs_per_cu, need);
+        const uint64_t n_waves = std::min<uint64_t>(wgs * kWavesPerWG, cap_waves);
+        if (geom != nullptr) {
+            *geom = InsertGeom{(uint32_t)kTile, (uint32_t)T, n_waves, wgs};
+            return hipSuccess;
+        }
         hipLaunchKernelGGL((insert_kernel<C, LPK, T, Src>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s,
-                           make_kparams(f), keys, n, n_units);
+                           make_kparams(f), keys, n, n_units, n_waves);
     }
+    return hipGetLastError();
+}
+
+template <int C, typename Src, bool REC = false>
+hipError_t insert_narrow_launch(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec,
+                                InsertGeom *geom = nullptr)
+{
+    const uint64_t n_units = (n + kNarrowKeys - 1) / kNarrowKeys;
+    uint64_t cap_waves = insert_inflight(f) / kNarrowKeys;
+    if (cap_waves < 1)
+        cap_waves = 1;
+    if (cap_waves > n_units)
+        cap_waves = n_units;
+    const uint64_t need = (cap_waves + kWavesPerWG - 1) / kWavesPerWG;
+    const size_t lds = rank_lds_bytes(f.c, f.k);
+    const uint64_t wgs = grid_for(insert_narrow_kernel<C, Src, REC>, lds, f.num_cus, kNarrowWgsPerCU, need);
+    const uint64_t n_waves = std::min<uint64_t>(wgs * kWavesPerWG, cap_waves);
+    if (geom != nullptr) {
+        *geom = InsertGeom{(uint32_t)kNarrowKeys, 1, n_waves, wgs};
+        return hipSuccess;
+    }
+    hipLaunchKernelGGL((insert_narrow_kernel<C, Src, REC>), dim3((uint32_t)wgs), dim3(kWGSize), lds, s,
+                       make_kparams(f), keys, n, n_units, n_waves, rec);
     return hipGetLastError();
 }
 
@@ -271,14 +356,17 @@ constexpr size_t insert_static_lds(int C, int T)
 }
 
 template <int C, typename Src, bool REC = false>
-hipError_t insert_c(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr)
+hipError_t insert_c(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr,
+                    InsertGeom *geom = nullptr)
 {
+    if (insert_tile_keys(f) == kNarrowKeys)
+        return insert_narrow_launch<C, Src, REC>(f, keys, n, s, rec, geom);
     // two tiles per wave only where their LDS and the rank table fit a workgroup
     int tpw = f.shape[BBFC_OP_INSERT].tiles_per_wave;
     if (tpw == 2 && insert_static_lds(C, 2) + rank_lds_bytes(f.c, f.k) > f.max_lds)
         tpw = 1;
     return with_shape(f.shape[BBFC_OP_INSERT].lanes_per_key, tpw, [&](auto L, auto T) {
-        return insert_launch<C, decltype(L)::value, decltype(T)::value, Src, REC>(f, keys, n, s, rec);
+        return insert_launch<C, decltype(L)::value, decltype(T)::value, Src, REC>(f, keys, n, s, rec, geom);
     });
 }
 
@@ -296,17 +384,18 @@ hipError_t query_c(const bbfc_filter &f, const Src &keys, uint64_t n, uint64_t *
 }
 
 template <typename Src, bool REC = false>
-hipError_t insert_any(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr)
+hipError_t insert_any(const bbfc_filter &f, const Src &keys, uint64_t n, hipStream_t s, uint8_t *rec = nullptr,
+                      InsertGeom *geom = nullptr)
 {
     switch (f.c) {
     case 1:
-        return insert_c<1, Src, REC>(f, keys, n, s, rec);
+        return insert_c<1, Src, REC>(f, keys, n, s, rec, geom);
     case 2:
-        return insert_c<2, Src, REC>(f, keys, n, s, rec);
+        return insert_c<2, Src, REC>(f, keys, n, s, rec, geom);
     case 3:
-        return insert_c<3, Src, REC>(f, keys, n, s, rec);
+        return insert_c<3, Src, REC>(f, keys, n, s, rec, geom);
     case 4:
-        return insert_c<4, Src, REC>(f, keys, n, s, rec);
+        return insert_c<4, Src, REC>(f, keys, n, s, rec, geom);
     default:
         return hipErrorInvalidValue;
     }
@@ -356,6 +445,11 @@ KmerKeys make_kmer_src(const uint64_t *seq, uint64_t seg_len, uint32_t q)
 hipError_t launch_insert(const bbfc_filter &f, const uint64_t *keys, uint64_t n, hipStream_t s)
 {
     return insert_any(f, ArrayKeys{keys}, n, s);
+}
+
+hipError_t insert_geometry(const bbfc_filter &f, uint64_t n, InsertGeom *geom)
+{
+    return insert_any(f, ArrayKeys{nullptr}, n, nullptr, nullptr, geom);
 }
 
 hipError_t launch_insert_recorded(const bbfc_filter &f, const uint64_t *keys, uint64_t n, uint8_t *decisions,

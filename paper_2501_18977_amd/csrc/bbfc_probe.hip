@@ -14,6 +14,7 @@ namespace bbfc {
 namespace {
 
 constexpr int kProbeWG = 256;
+constexpr int kProbeWave = 64;
 
 // Counter-based line index (SplitMix64 finaliser of seed + i).
 __device__ inline uint64_t probe_line(uint64_t seed, uint64_t i)
@@ -258,6 +259,50 @@ uint32_t probe_grid(const void *kernel)
 
 } // namespace
 
+// One wavefront per workgroup times `iters` dependent steps of one kind of
+// memory round trip with the device's constant-rate clock and writes the
+// mean nanoseconds per step to out[blockIdx.x]. Lanes 8g..8g+7 share one
+// line, as in the filter kernels. kind 0: a random line read whose address
+// depends on the previous read; 1: a random 64-bit atomic OR and the wait
+// for it; 2: a random line read, then an atomic OR into the line just read,
+// and the wait for both; 3: a coalesced 512-byte load of fresh words, its
+// address depending on the previous load, and the wait for it.
+__global__ __launch_bounds__(kProbeWave) void probe_latency_kernel(uint64_t *__restrict__ buf, uint64_t line_mask,
+                                                               int kind, uint32_t iters, double ns_per_tick,
+                                                               double *__restrict__ out)
+{
+    const uint32_t lane = threadIdx.x;
+    const uint32_t w = lane % 8;
+    const uint64_t word_mask = line_mask * 8 + 7;
+    uint64_t x = probe_line(0x5851F42D4C957F2Dull * (blockIdx.x + 1), lane / 8);
+    uint64_t acc = 0;
+    const uint64_t t0 = wall_clock64();
+    for (uint32_t i = 0; i < iters; ++i) {
+        if (kind == 0) {
+            acc += buf[((x ^ acc) & line_mask) * 8 + w] + 1;
+        } else if (kind == 1) {
+            __hip_atomic_fetch_or(buf + (x & line_mask) * 8 + w, 1ull << (i & 63), __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+        } else if (kind == 2) {
+            uint64_t *word = buf + ((x ^ (acc & 1)) & line_mask) * 8 + w;
+            const uint64_t v = *word;
+            acc += v;
+            __hip_atomic_fetch_or(word, (1ull << (i & 63)) | (v & 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+        } else {
+            const uint64_t idx = ((uint64_t)i * gridDim.x + blockIdx.x) * kProbeWave + lane;
+            acc += buf[(idx + (acc & 1)) & word_mask];
+        }
+        x = probe_line(x, i);
+    }
+    const uint64_t t1 = wall_clock64();
+    // acc keeps the loads; the term it adds is below a double's resolution here
+    const double keep = acc == 0x9E3779B97F4A7C15ull ? 1e-300 : 0.0;
+    if (lane == 0)
+        out[blockIdx.x] = (double)(t1 - t0) * ns_per_tick / iters + keep;
+}
+
 hipError_t launch_probe_gather(const uint64_t *buf, uint64_t n_lines64, uint32_t access_bytes, uint64_t n_access,
                                uint64_t seed, uint64_t *sink, hipStream_t s)
 {
@@ -322,6 +367,22 @@ hipError_t launch_probe_insert_schedule(uint64_t *buf, uint64_t n_lines, uint64_
     else
         hipLaunchKernelGGL(probe_insert_schedule_kernel<2>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_keys,
                            mask_bits, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_latency(uint64_t *buf, uint64_t n_lines, int kind, uint32_t iters, uint32_t waves,
+                                double *out, hipStream_t s)
+{
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess)
+        return e;
+    if (khz <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(probe_latency_kernel, dim3(waves), dim3(kProbeWave), 0, s, buf, n_lines - 1, kind, iters,
+                       1e6 / (double)khz, out);
     return hipGetLastError();
 }
 

@@ -420,4 +420,70 @@ __device__ __forceinline__ void insert_tiles(const KParams &p, const uint16_t *r
     wave_sync();
 }
 
+// Narrow racing insert: a wavefront holds 8 keys, lane (g, l) = (lane / 8,
+// lane % 8) works on key g and owns word l of its blocks and mask, and each
+// step of a key is spread over its 8 lanes, so one tile is a single round:
+// lane l computes the bit addresses f_i with i = l mod 8 (am[j] holds the
+// multiplier of f_(8j+l), zero past k) and ORs them into the key's mask slot
+// in LDS; each lane computes the key's c block indices itself; the 8 lanes
+// read one block together; DPP sums give j and a (Section 3.2). For inserts
+// whose keys in flight are few (small filters), where a tile's time is the
+// latency of its own instructions and memory round trips rather than
+// bandwidth. The distinct strategy (App. B) draws its addresses in order, so
+// lane 0 of each group draws them all.
+constexpr int kNarrowKeys = 8; // keys per wavefront tile
+
+template <int C, typename Src, bool REC = false>
+__device__ __forceinline__ void insert_narrow_tile(const KParams &p, const uint16_t *rank, const Src &keys, uint64_t n,
+                                                   uint64_t base, uint32_t lane, const uint64_t (&am)[4],
+                                                   uint32_t *smask, uint8_t *__restrict__ rec = nullptr)
+{
+    const uint32_t g = lane / 8;
+    const uint32_t l = lane % 8;
+    const uint64_t t = base + g;
+    const bool live = t < n;
+    const uint64_t x = live ? keys.load(t) : 0; // past n: key 0, whose blocks are in range
+    uint32_t *slot = smask + g * kSlotDw;
+    slot[2 * l] = 0;
+    slot[2 * l + 1] = 0;
+    wave_sync();
+    auto set_bit = [slot](uint32_t f) { atomicOr(slot + (f >> 5), 1u << (f & 31)); };
+    if (p.distinct) {
+        if (l == 0)
+            distinct_bits(p.bit_mult, p.k, x, set_bit);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (8 * j + l < p.k)
+                set_bit(bit_hash(am[j], x));
+    }
+    const uint64_t first = sub_base(p, x);
+    uint64_t blk[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+        blk[i] = first + block_hash_rt(p, p.block_mult[i], x);
+    uint64_t B[C][1];
+#pragma unroll
+    for (int i = 0; i < C; ++i)
+        B[i][0] = p.words[blk[i] * 8 + l];
+    wave_sync();
+    uint64_t m[1];
+    m[0] = (uint64_t)slot[2 * l] | ((uint64_t)slot[2 * l + 1] << 32);
+    const JA<C> ja = reduce_ja<C, 8, 1>(B, m);
+    const int best = decide<C>(ja, rank);
+    if constexpr (REC) {
+        if (l == 0 && live)
+            rec[t] = best < 0 ? kPresent : (uint8_t)best;
+    }
+    if (best >= 0 && live) {
+        uint64_t b = 0;
+#pragma unroll
+        for (int i = 0; i < C; ++i)
+            b |= blk[i] & (0ull - (uint64_t)(best == i));
+        if (m[0] & ~pick<C, 1>(B, best, 0))
+            atomic_or_word(p.words + b * 8 + l, m[0]);
+    }
+    wave_sync();
+}
+
 } // namespace bbfc

@@ -85,10 +85,10 @@ def test_racing_fpr_distinct_and_subarrays(dev, distinct, sub):
 
 
 def test_in_flight_cap_keeps_the_fpr(dev):
-    """The racing insert caps its keys in flight at M/32: a decision can miss
-    bits that in-flight keys are about to set, and with every key of the call
-    in flight at once the FPR rises well beyond the 2% tolerance. M = 2^15,
-    n = 2^20, k = 14, LA (16 bits per key)."""
+    """The racing insert caps its keys in flight at M/(8(c-1)), M/8 here: a
+    decision can miss bits that in-flight keys are about to set, and with
+    every key of the call in flight at once the FPR rises well beyond the 2%
+    tolerance. M = 2^15, n = 2^20, k = 14, LA (16 bits per key)."""
     M, n, k = 1 << 15, 1 << 20, 14
     f = bbfc.Filter(M, 2, k, "la", seed=77)
     try:
@@ -98,15 +98,47 @@ def test_in_flight_cap_keeps_the_fpr(dev):
         neg = workload.negative_keys(77, n, 1 << 20)
         want = ref.conditional_fpr(neg)
         got = {}
-        for cap in (0, 1 << 20):  # 0: the default, M/32
+        for cap in (0, 1 << 20):  # 0: the default, M/8
             f.clear()
             f.set_option(bbfc.OPT_INSERT_INFLIGHT, cap)
             f.insert(keys_d)
             got[cap] = ref.conditional_fpr(neg, words=f.download())
             assert bbfc.unpack_bits(from_dev(f.query(keys_d)), n).all()
-        print(f"conditional FPR: sequential {want:.4e}, cap M/32 {got[0]:.4e}, all in flight {got[1 << 20]:.4e}",
+        print(f"conditional FPR: sequential {want:.4e}, cap M/8 {got[0]:.4e}, all in flight {got[1 << 20]:.4e}",
               flush=True)
         assert got[0] == pytest.approx(want, rel=0.02)
         assert got[1 << 20] > 1.05 * want
+    finally:
+        f.close()
+
+
+@pytest.mark.parametrize("M,c,k,cost,bits", [
+    (1 << 15, 3, 14, "exp", 20),
+    (1 << 15, 4, 12, "la", 16),
+    (1 << 15, 3, 8, "mix", 12),
+    (3000, 2, 11, "la", 16),
+])
+def test_default_in_flight_bound_by_choices(dev, M, c, k, cost, bits):
+    """The default bound on keys in flight, M/(8(c-1)), keeps the racing
+    build's conditional FPR within 2% of the oracle's sequential build for
+    three and four choices too, where each decision weighs more candidates
+    that in-flight keys may be writing."""
+    n = M * 512 // bits
+    seed = 7 * M + c
+    f = bbfc.Filter(M, c, k, cost, seed=seed)
+    try:
+        assert f.get_option(bbfc.OPT_INSERT_INFLIGHT) == 0
+        ref = oracle.OracleFilter(M, c, k, oracle.COST_NAMES[cost], None, list(f.params.block_mult),
+                                  list(f.params.bit_mult))
+        keys_d = workload.device_keys(seed, 0, n, device=dev)
+        f.insert(keys_d)
+        ref.insert(from_dev(keys_d))
+        neg = workload.negative_keys(seed, n, 1 << 20)
+        got = ref.conditional_fpr(neg, words=f.download())
+        want = ref.conditional_fpr(neg)
+        print(f"M={M} c={c} k={k} {cost}: conditional FPR racing {got:.4e} sequential {want:.4e} "
+              f"({got / want - 1:+.2%})", flush=True)
+        assert got == pytest.approx(want, rel=0.02)
+        assert bbfc.unpack_bits(from_dev(f.query(keys_d)), n).all()
     finally:
         f.close()

@@ -255,11 +255,15 @@ RACING_CONFIGS = [
     (6, 2, 7, "la", 500),                 # overloaded: many keys find themselves present
     (1 << 12, 2, 32, "exp", 1 << 12 + 7), # k = 32
 ])
-@pytest.mark.parametrize("lpk,tpw", [(8, 1), (8, 2), (4, 1), (4, 2)])
-def test_racing_insert_decisions_rebuild_the_filter(dev, M, c, k, cost, n, lpk, tpw):
-    ref, gpu = make_pair(M, c, k, cost, seed=c * k + M + lpk + tpw)
+@pytest.mark.parametrize("tile,lpk,tpw", [(1, 8, 1), (1, 8, 2), (1, 4, 1), (1, 4, 2), (2, 8, 1)])
+def test_racing_insert_decisions_rebuild_the_filter(dev, M, c, k, cost, n, tile, lpk, tpw):
+    """Both racing kernels (tiles of 64 keys in every launch shape, tiles of
+    8 keys): the recorded decisions rebuild the filter exactly."""
+    ref, gpu = make_pair(M, c, k, cost, seed=c * k + M + lpk + tpw + tile)
     try:
+        gpu.set_option(bbfc.OPT_INSERT_TILE, tile)
         gpu.set_shape(bbfc.OP_INSERT, lpk, tpw)
+        assert gpu.insert_launch_info(n)["tile_keys"] == (64 if tile == 1 else 8)
         keys_d = workload.device_keys(M + 2, 0, n, device=dev)
         keys = from_dev(keys_d)
         keys = np.concatenate([keys, keys[: n // 8]])  # repeats: decided present or placed again
@@ -286,10 +290,16 @@ def test_racing_insert_decisions_on_top_of_a_filter(dev):
         gpu.close()
 
 
+@pytest.mark.parametrize("tile", [0, 1])
 @pytest.mark.parametrize("M,c,k,cost,n", RACING_CONFIGS)
-def test_racing_insert_invariants_and_fpr(dev, M, c, k, cost, n):
+def test_racing_insert_invariants_and_fpr(dev, M, c, k, cost, n, tile):
+    """The default racing insert (tiles of 8 keys at these bounds) and the
+    one with tiles of 64 keys: exact validity, zero false negatives, the
+    envelope, and the FPR gate against the oracle's sequential build."""
     ref, gpu = make_pair(M, c, k, cost, seed=c * k + M)
     try:
+        gpu.set_option(bbfc.OPT_INSERT_TILE, tile)
+        assert gpu.insert_launch_info(n)["tile_keys"] == (8 if tile == 0 else 64)
         keys_d = workload.device_keys(M, 0, n, device=dev)
         keys = from_dev(keys_d)
         ref.insert(keys)
@@ -390,7 +400,11 @@ def test_option_validation(dev):
         assert gpu.get_option(bbfc.OPT_INSERT_INFLIGHT) == 0
         gpu.set_option(bbfc.OPT_INSERT_INFLIGHT, 4096)
         assert gpu.get_option(bbfc.OPT_INSERT_INFLIGHT) == 4096
-        for opt, val in ((bbfc.OPT_QUERY_EARLY_EXIT, 2), (bbfc.OPT_INSERT_INFLIGHT, -1), (99, 0)):
+        assert gpu.get_option(bbfc.OPT_INSERT_TILE) == 0
+        gpu.set_option(bbfc.OPT_INSERT_TILE, 2)
+        assert gpu.get_option(bbfc.OPT_INSERT_TILE) == 2
+        for opt, val in ((bbfc.OPT_QUERY_EARLY_EXIT, 2), (bbfc.OPT_INSERT_INFLIGHT, -1), (bbfc.OPT_INSERT_TILE, 3),
+                         (99, 0)):
             with pytest.raises(bbfc.BBFCError):
                 gpu.set_option(opt, val)
     finally:
@@ -423,6 +437,32 @@ def test_overlapping_output_rejected(dev):
             gpu.query(buf[:512], out=buf[500:])
     finally:
         gpu.close()
+
+
+def test_latency_probe(dev):
+    """The latency probe: every kind gives a plausible time per step for
+    each wavefront, the atomic kinds set bits, and bad arguments are
+    rejected before anything runs."""
+    buf = torch.zeros(8 * (1 << 15), dtype=torch.int64, device=dev)
+    out = torch.zeros(4, dtype=torch.float64, device=dev)
+    got = {}
+    for kind in (0, 1, 2, 3):
+        out.zero_()
+        bbfc.probe_latency(buf, kind, out, iters=500)
+        torch.cuda.synchronize()
+        got[kind] = out.cpu().numpy()
+        assert np.all(got[kind] > 20) and np.all(got[kind] < 1e5), (kind, got[kind])
+    print("latency ns per step (kind: per wavefront):", {k: np.round(v, 1).tolist() for k, v in got.items()},
+          flush=True)
+    assert buf.ne(0).any()  # kinds 1 and 2 ORed bits in
+    # an atomic with its wait takes longer than no step at all, and a read
+    # followed by an atomic longer than the atomic alone
+    assert got[2].mean() > got[1].mean() * 0.8
+    for kwargs in ({"kind": 4}, {"kind": 0, "iters": 0}):
+        with pytest.raises(bbfc.BBFCError):
+            bbfc.probe_latency(buf, out=out, **kwargs)
+    with pytest.raises(bbfc.BBFCError, match="power-of-two"):
+        bbfc.probe_latency(buf[:8 * 7], 0, out)
 
 
 def test_probes_run(dev):
@@ -488,5 +528,33 @@ def test_query_concurrent_with_insert_sees_a_subset(dev):
         d, a = from_dev(during), from_dev(after)
         assert not np.any(d & ~a), "the concurrent query saw a bit the finished filter does not have"
         assert bbfc.unpack_bits(a, 2 * n)[:n].all()
+    finally:
+        gpu.close()
+
+
+@pytest.mark.parametrize("M,c", [(1 << 15, 2), (1 << 15, 3), (3000, 4), (1 << 25, 2), (1 << 15, 1), (1, 2)])
+def test_insert_launch_info_realises_the_bound(dev, M, c):
+    """The default bound on keys in flight, M/(8(c-1)) (none for one
+    choice), is what the launch realises, rounded down to whole wavefronts
+    of the tile size the bound selects (8 keys up to 2^16 in flight, else
+    64), and never more than the call's keys."""
+    gpu = bbfc.Filter(M, c, 11 if c > 1 else 10, "la" if c > 1 else "none", seed=2)
+    try:
+        n = 1 << 22
+        info = gpu.insert_launch_info(n)
+        bound = (1 << 62) if c == 1 else max(64, M // (8 * (c - 1)))
+        tile = 8 if bound <= 1 << 16 else 64
+        assert info["tile_keys"] == tile
+        if bound <= info["workgroups"] * 4 * tile:  # the grid holds the bound
+            assert info["keys_in_flight"] == max(tile, bound // tile * tile)
+        assert info["keys_in_flight"] <= max(bound, tile)
+        assert gpu.insert_launch_info(100)["keys_in_flight"] <= 128  # one wide unit holds 64 or 128 keys
+        gpu.set_option(bbfc.OPT_INSERT_INFLIGHT, 1000)
+        gpu.set_option(bbfc.OPT_INSERT_TILE, 1)
+        info = gpu.insert_launch_info(n)
+        assert info["tile_keys"] == 64 and info["keys_in_flight"] == 960 and info["workgroups"] == 4
+        gpu.set_option(bbfc.OPT_INSERT_TILE, 2)
+        info = gpu.insert_launch_info(n)
+        assert info["tile_keys"] == 8 and info["keys_in_flight"] == 1000 and info["workgroups"] == 32
     finally:
         gpu.close()
