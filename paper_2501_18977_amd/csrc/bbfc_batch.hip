@@ -219,7 +219,9 @@ struct bbfc_batch {
     int num_cus = 0;
     uint64_t total_keys = 0;
     uint64_t total_words = 0;
-    bbfc_launch_shape shape[2] = {{8, 1, 0, 1, 0.0f}, {8, 1, 0, 0, 0.0f}}; // [BBFC_OP_INSERT], [BBFC_OP_QUERY]
+    // [BBFC_OP_INSERT], [BBFC_OP_QUERY]; queries take units in order, 16 per
+    // grab, so that few filters are read at once
+    bbfc_launch_shape shape[2] = {{8, 1, 0, 1, 0.0f}, {8, 1, 0, 16, 0.0f}};
     // device tables, rebuilt when a shape changes (graphs keep their own copies)
     bbfc::Tables t;
     int tables_tpw_query = 0;
