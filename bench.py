@@ -59,6 +59,10 @@ def parse_args():
     ap.add_argument("--no-unfused", action="store_true", help="kmer workload: skip the unfused comparison")
     ap.add_argument("--reads", type=float, default=1e7, help="kmer workload: reads of 150 bp (and as many random)")
     ap.add_argument("--requests", type=int, default=20000, help="serve workload: requests per offered load")
+    ap.add_argument("--serve-slots", type=int, default=0,
+                    help="serve workload: server slots (0: the library's default)")
+    ap.add_argument("--serve-batch-keys", type=int, default=0,
+                    help="serve workload: keys per batch (0: the library's default)")
     ap.add_argument("--log2-keys", type=int, default=30, help="keys to insert (2^n); blocks = keys/32")
     ap.add_argument("--bits", choices=["random", "distinct"], default="random",
                     help="plain workload: bit selection strategy (Section 3.3)")
@@ -950,7 +954,8 @@ def bench_serve(args):
     """Serving: the 2^30-key filter stays resident; query requests with
     sizes log-uniform in [1, 65536] keys (half inserted, half never inserted)
     arrive as a Poisson stream. Each offered load replays the same requests
-    through the continuous-batching server (4 slots of 2^20 keys), first from
+    through the continuous-batching server (the library's default slots,
+    or --serve-slots / --serve-batch-keys), first from
     host memory, then with keys and answers in device memory; the baselines
     serve the requests one at a time with one plain query launch each
     (upload, query, download, synchronise; or query and synchronise)."""
@@ -1005,7 +1010,13 @@ def bench_serve(args):
                 "p50_us": round(float(np.percentile(base_lat, 50)), 1),
                 "p99_us": round(float(np.percentile(base_lat, 99)), 1)}
 
-    srv = bbfc.Server(filt, n_slots=4, max_batch_keys=1 << 20, max_pending_keys=1 << 27)
+    srv_cfg = {"max_pending_keys": 1 << 27}
+    if args.serve_slots:
+        srv_cfg["n_slots"] = args.serve_slots
+    if args.serve_batch_keys:
+        srv_cfg["max_batch_keys"] = args.serve_batch_keys
+    srv = bbfc.Server(filt, **srv_cfg)
+    srv_cfg = srv.config()
     # untimed warm-up: the first 1000 requests at once (worker threads, staging pages)
     n_warm = min(1000, len(sizes))
     srv.replay(flat[: int(offs[n_warm])], offs[: n_warm + 1], np.zeros(n_warm))
@@ -1090,7 +1101,7 @@ def bench_serve(args):
                                 f"in [1, 65536] (mean {mean_size:.0f} keys), half inserted keys; replayed with keys "
                                 "and answers in host memory (staged) and in device memory (in place); value: the "
                                 "device path's best achieved rate"),
-                   "requests": len(sizes), "total_keys_per_load": total},
+                   "requests": len(sizes), "total_keys_per_load": total, "server": srv_cfg},
         "loads": loads,
         "best": best,
         "plain_one_request_at_a_time": baseline,
@@ -1578,7 +1589,7 @@ def serve_leg(filt, n: int, n_requests: int = 10000) -> dict:
     """Serving, compact, on the headline's built filter: a Poisson stream of
     query requests (sizes log-uniform in [1, 65536], half inserted keys) with
     keys and answers in device memory, replayed through the continuous-
-    batching server (4 slots of 2^20 keys) at two offered loads, beside one
+    batching server (the library's default slots) at two offered loads, beside one
     plain query launch per request. Sampled requests' answers must equal a
     plain query of the same keys."""
     import numpy as np
@@ -1602,7 +1613,8 @@ def serve_leg(filt, n: int, n_requests: int = 10000) -> dict:
     d_flat = torch.from_numpy(flat.view(np.int64)).to(dev)
     dout = torch.empty(1024, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
-    srv = bbfc.Server(filt, n_slots=4, max_batch_keys=1 << 20, max_pending_keys=1 << 27)
+    srv = bbfc.Server(filt, max_pending_keys=1 << 27)
+    srv_cfg = srv.config()
     n_warm = min(1000, len(sizes))
     srv.replay_device(d_flat[: int(offs[n_warm])], offs[: n_warm + 1], np.zeros(n_warm))
     rng = np.random.default_rng(5)
@@ -1610,7 +1622,7 @@ def serve_leg(filt, n: int, n_requests: int = 10000) -> dict:
     out = None
     # each offered load replays the stream three times (a few ms each); the
     # median replay is reported, the three achieved rates beside it
-    for offered in (8e9, 32e9):
+    for offered in (8e9, 64e9):  # moderate load, and beyond saturation
         reps = []
         for _ in range(3):
             arrivals = np.cumsum(rng.exponential(mean_size / offered, size=len(sizes)))
@@ -1643,7 +1655,8 @@ def serve_leg(filt, n: int, n_requests: int = 10000) -> dict:
         "unit": "Mkeys/s",
         "config": {"workload": (f"serve: the headline's filter; {len(sizes)} Poisson query requests, sizes log-uniform "
                                 f"in [1, 65536] (mean {mean_size:.0f} keys), half inserted keys, keys and answers in "
-                                "device memory; continuous batching over 4 slots of 2^20 keys"),
+                                f"device memory; continuous batching over {srv_cfg['n_slots']} slots of "
+                                f"{srv_cfg['max_batch_keys']} keys (the library's defaults)"),
                    "requests": len(sizes), "total_keys_per_load": total},
         "loads_device": loads,
         "plain_device_one_request_at_a_time": {"requests": n_base,

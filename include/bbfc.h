@@ -520,6 +520,10 @@ typedef struct {
     uint32_t batch_window_us;
 } bbfc_server_config;
 
+/* Writes the defaults that config == NULL stands for into *config.
+ * Errors: EINVAL (null config). */
+bbfc_status bbfc_server_default_config(bbfc_server_config *config);
+
 /* Starts one worker thread per slot serving queries on `filter`. Requests
  * that arrive while others are in flight are admitted into the next batch
  * as slots and memory free up: the oldest pending work fills a free slot's

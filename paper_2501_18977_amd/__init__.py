@@ -131,6 +131,7 @@ def lib() -> ctypes.CDLL:
         "bbfc_get_words": (_st, [_vp, _vp]),
         "bbfc_set_option": (_st, [_vp, ctypes.c_int32, ctypes.c_int64]),
         "bbfc_get_option": (_st, [_vp, ctypes.c_int32, _vp]),
+        "bbfc_server_default_config": (_st, [_vp]),
         "bbfc_insert_launch_info": (_st, [_vp, ctypes.c_uint64, _vp, _vp, _vp]),
         "bbfc_blocks_for": (_u64, [_u64, ctypes.c_double]),
         "bbfc_rank_table": (_st, [_Cost, _u32, _vp]),
@@ -639,14 +640,27 @@ class Server:
     are numpy uint64 key arrays in host memory (submit, replay) or 64-bit
     GPU tensors (submit_device, replay_device)."""
 
-    def __init__(self, filt: Filter, n_slots: int = 4, max_batch_keys: int = 1 << 20,
-                 max_pending_keys: int = 1 << 28, poll_us: int = 20, batch_window_us: int = 0):
+    def __init__(self, filt: Filter, n_slots: int | None = None, max_batch_keys: int | None = None,
+                 max_pending_keys: int | None = None, poll_us: int | None = None,
+                 batch_window_us: int | None = None):
+        """Arguments left None take the library's defaults."""
         self._filter = filt
-        cfg = _ServerConfig(n_slots, max_batch_keys, max_pending_keys, poll_us, batch_window_us)
+        cfg = _ServerConfig()
+        _check(lib().bbfc_server_default_config(ctypes.byref(cfg)))
+        for name, v in (("n_slots", n_slots), ("max_batch_keys", max_batch_keys),
+                        ("max_pending_keys", max_pending_keys), ("poll_us", poll_us),
+                        ("batch_window_us", batch_window_us)):
+            if v is not None:
+                setattr(cfg, name, int(v))
+        self._cfg = {name: int(getattr(cfg, name)) for name, _ in _ServerConfig._fields_}
         h = ctypes.c_void_p()
         _check(lib().bbfc_server_create(filt.handle, ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
         self._live = {}  # ticket -> (keys, out) kept alive until waited for
+
+    def config(self) -> dict:
+        """The configuration the server was created with."""
+        return dict(self._cfg)
 
     def submit(self, keys) -> int:
         import numpy as np

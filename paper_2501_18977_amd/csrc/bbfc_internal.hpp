@@ -98,8 +98,10 @@ struct QueryPiece {
     uint64_t n;
     uint64_t unit_off;
 };
+constexpr uint32_t kMaxQueryPieces = 1024; // pieces per launch
 
-// Enqueues one query launch over h_pieces[0..n_pieces) (pinned host memory,
+// Enqueues one query launch over h_pieces[0..n_pieces) (n_pieces <=
+// kMaxQueryPieces; pinned host memory,
 // keys/out/n filled by the caller; unit offsets are written here), whose
 // table is copied to d_pieces on the stream first. The host table must stay
 // untouched until the stream has passed the copy.

@@ -45,21 +45,40 @@ __global__ __launch_bounds__(kWGSize) void query_kernel(KParams p, Src keys, uin
 }
 
 // A query over several key arrays of one filter (a batch of requests that
-// live in device memory): units are numbered piece after piece and strided
-// over the wavefronts; a wavefront's units only increase, so its piece
-// cursor only moves forward.
+// live in device memory): units are numbered piece after piece and each
+// wavefront takes one contiguous run of them. The pieces' first units are
+// staged in LDS; a binary search there finds the piece of a wavefront's first
+// unit, and a cursor that only moves forward (about one step per piece of
+// the run) finds the rest.
 template <int C, int LPK, int T, bool EARLY>
 __global__ __launch_bounds__(kWGSize) void query_pieces_kernel(KParams p, const QueryPiece *__restrict__ pieces,
                                                                uint32_t n_pieces, uint64_t n_units)
 {
     __shared__ uint32_t s_mask[kWavesPerWG][T * kTile * kSlotDw];
     __shared__ uint64_t s_blk[kWavesPerWG][T * kTile * C];
+    __shared__ uint32_t s_first[kMaxQueryPieces];
+    for (uint32_t i = threadIdx.x; i < n_pieces; i += blockDim.x)
+        s_first[i] = (uint32_t)pieces[i].unit_off;
+    __syncthreads();
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wv = threadIdx.x / kWave;
     const uint64_t n_waves = (uint64_t)gridDim.x * kWavesPerWG;
-    uint32_t f = 0;
-    for (uint64_t u = (uint64_t)blockIdx.x * kWavesPerWG + wv; u < n_units; u += n_waves) {
-        while (f + 1 < n_pieces && pieces[f + 1].unit_off <= u)
+    const uint64_t per = (n_units + n_waves - 1) / n_waves;
+    const uint64_t u0 = ((uint64_t)blockIdx.x * kWavesPerWG + wv) * per;
+    const uint64_t u1 = u0 + per < n_units ? u0 + per : n_units;
+    if (u0 >= u1)
+        return;
+    // the last piece whose first unit is <= u0 (s_first[0] == 0)
+    uint32_t f = 0, hi = n_pieces - 1;
+    while (f < hi) {
+        const uint32_t mid = (f + hi + 1) / 2;
+        if (s_first[mid] <= u0)
+            f = mid;
+        else
+            hi = mid - 1;
+    }
+    for (uint64_t u = u0; u < u1; ++u) {
+        while (f + 1 < n_pieces && s_first[f + 1] <= u)
             ++f;
         const QueryPiece pc = pieces[f];
         const uint64_t lu = u - pc.unit_off;
@@ -325,6 +344,8 @@ hipError_t query_pieces_launch(const bbfc_filter &f, QueryPiece *h, QueryPiece *
     }
     if (units == 0)
         return hipSuccess;
+    if (n_pieces > kMaxQueryPieces || units > UINT32_MAX)
+        return hipErrorInvalidValue; // the kernel stages the first units in 32-bit LDS words
     hipError_t e = hipMemcpyAsync(d, h, n_pieces * sizeof(QueryPiece), hipMemcpyHostToDevice, s);
     if (e != hipSuccess)
         return e;

@@ -50,7 +50,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr uint32_t kMaxDevicePieces = 1024;
+constexpr uint32_t kMaxDevicePieces = bbfc::kMaxQueryPieces;
+
+// slots, keys per batch, pending keys, poll interval (us), gathering window (us)
+constexpr bbfc_server_config kDefaultConfig{4, 1u << 20, 1ull << 28, 20, 0};
 
 struct Request {
     uint64_t ticket = 0;
@@ -359,13 +362,19 @@ using bbfc::hip_fail;
 
 extern "C" {
 
+bbfc_status bbfc_server_default_config(bbfc_server_config *config)
+{
+    if (config == nullptr)
+        return fail(BBFC_EINVAL, "null config");
+    *config = kDefaultConfig;
+    return BBFC_OK;
+}
+
 bbfc_status bbfc_server_create(bbfc_handle filter, const bbfc_server_config *config, bbfc_server_handle *out)
 {
     if (filter == nullptr || out == nullptr)
         return fail(BBFC_EINVAL, "null filter or output handle");
-    bbfc_server_config cfg{4, 1u << 20, 1ull << 28, 20, 0};  // defaults
-    if (config)
-        cfg = *config;
+    bbfc_server_config cfg = config ? *config : kDefaultConfig;
     if (cfg.n_slots < 1 || cfg.n_slots > 16)
         return fail(BBFC_EINVAL, "n_slots must be in [1, 16]");
     if (cfg.max_batch_keys < 64 || cfg.max_batch_keys % 64 || cfg.max_batch_keys > (1ull << 30))

@@ -198,6 +198,17 @@ def test_null_handle_calls_are_rejected():
     assert L.bbfc_clear(None, None) == -1
 
 
+def test_server_default_config():
+    """The defaults that a null server config stands for (host-only call)."""
+    import ctypes
+
+    cfg = bbfc._ServerConfig()
+    assert bbfc.lib().bbfc_server_default_config(ctypes.byref(cfg)) == 0
+    assert (cfg.n_slots, cfg.max_batch_keys, cfg.max_pending_keys, cfg.poll_us, cfg.batch_window_us) == \
+        (4, 1 << 20, 1 << 28, 20, 0)
+    assert bbfc.lib().bbfc_server_default_config(None) == -1
+
+
 def test_workload_generators_agree():
     keys = workload.splitmix64_keys(123, 1000, 64)
     for i, v in enumerate(keys):
