@@ -13,9 +13,10 @@
  *  5. a filter with sub-arrays (Section 3.4) from bbfc_create_config, filled
  *     by the bulk insert in a caller-owned workspace, is the oracle's
  *     one-at-a-time build word for word;
- *  6. the racing insert that records its decisions: every decision names a
- *     candidate or "present", and the oracle's placement of the decided
- *     keys' masks is the filter word for word (Sections 3.1, 3.2);
+ *  6. the racing insert that records its decisions, in tiles of 8 and of 64
+ *     keys: every decision names a candidate or "present", and the oracle's
+ *     placement of the decided keys' masks is the filter word for word
+ *     (Sections 3.1, 3.2);
  *  7. the sequential insert without allocation, on an input larger than one
  *     window, equals the allocating one and the oracle, twice in a row;
  *  8. the server with device-resident requests answers as the oracle.
@@ -140,6 +141,21 @@ int main(void)
     CHECK(bbfc_insert(b, NULL, 10, NULL) == BBFC_EINVAL, "null keys accepted");
     CHECK(bbfc_insert(b, NULL, 0, NULL) == BBFC_OK, "an empty insert is not a no-op");
     CHECK(strcmp(bbfc_status_string(BBFC_EINVAL), "invalid argument") == 0, "status string");
+    CHECK(bbfc_set_option(b, BBFC_OPT_INSERT_TILE, 3) == BBFC_EINVAL, "tile option 3 accepted");
+    {
+        /* 4096 blocks, two choices: the default bound is 4096/8 = 512 keys,
+         * which takes tiles of 8 keys; forced tiles of 64 keep the bound */
+        uint32_t tk = 0;
+        uint64_t kif = 0, wg = 0;
+        CHECK(bbfc_insert_launch_info(b, n, &tk, &kif, &wg) == BBFC_OK, "launch info: %s", bbfc_last_error());
+        CHECK(tk == 8 && kif == 512 && wg == 16, "launch info: tile %u, %llu keys in flight, %llu workgroups", tk,
+              (unsigned long long)kif, (unsigned long long)wg);
+        CHECK(bbfc_set_option(b, BBFC_OPT_INSERT_TILE, 1) == BBFC_OK, "tile option");
+        CHECK(bbfc_insert_launch_info(b, n, &tk, &kif, NULL) == BBFC_OK && tk == 64 && kif == 512,
+              "launch info with tiles of 64: tile %u, %llu keys in flight", tk, (unsigned long long)kif);
+        CHECK(bbfc_set_option(b, BBFC_OPT_INSERT_TILE, 0) == BBFC_OK, "tile option");
+        CHECK(bbfc_insert_launch_info(NULL, n, &tk, &kif, &wg) == BBFC_EINVAL, "null handle accepted");
+    }
 
     /* 5. sub-arrays and the bulk insert */
     {
@@ -177,11 +193,13 @@ int main(void)
         CHECK(bbfc_destroy(s5) == BBFC_OK, "destroy");
     }
 
-    /* 6. the racing insert with recorded decisions */
-    {
+    /* 6. the racing insert with recorded decisions, in tiles of 8 keys (the
+     * default at this size) and of 64 keys */
+    for (int tile = 2; tile >= 1; tile--) {
         const uint64_t M6 = 4096;
         bbfc_handle r6 = NULL;
         CHECK(bbfc_create_seeded(M6, 2, 11, la, 6, &r6) == BBFC_OK, "create: %s", bbfc_last_error());
+        CHECK(bbfc_set_option(r6, BBFC_OPT_INSERT_TILE, tile) == BBFC_OK, "tile option");
         uint8_t *d_dec = NULL;
         HIP(hipMalloc((void **)&d_dec, n));
         CHECK(bbfc_insert_recorded(r6, d_keys, n, d_dec, NULL) == BBFC_OK, "insert_recorded: %s", bbfc_last_error());
@@ -199,7 +217,8 @@ int main(void)
         CHECK(bbfc_download(r6, got6, NULL) == BBFC_OK, "download");
         const bbo_layout L6 = {M6, 1, 0};
         bbo_place(want6, &L6, 2, 11, 0, bm6, am6, h_keys, dec, n, 1, 0);
-        CHECK(memcmp(got6, want6, M6 * 64) == 0, "the recorded decisions do not rebuild the filter");
+        CHECK(memcmp(got6, want6, M6 * 64) == 0, "tile option %d: the recorded decisions do not rebuild the filter",
+              tile);
         HIP(hipFree(d_dec));
         free(dec);
         free(got6);
