@@ -114,6 +114,32 @@ def test_racing_insert(dev, M, c, k, cost, n):
         gpu.close()
 
 
+@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("M,c,k,cost,n", [cfg for cfg in CONFIGS if cfg[1] > 1])
+def test_racing_insert_decisions_rebuild_the_filter(dev, M, c, k, cost, n, tile):
+    """Both racing kernels with distinct addresses (tiles of 64 keys; tiles
+    of 8 keys, where lane 0 of each group draws the key's addresses in
+    order): every recorded decision names a candidate or "present", the
+    oracle's placement of the decided keys' F(x) is the filter word for
+    word, and every "present" key is held (Sections 3.1, 3.2, App. B)."""
+    ref, gpu = make_pair(M, c, k, cost, seed=7 * M + c + k + tile)
+    try:
+        gpu.set_option(bbfc.OPT_INSERT_TILE, tile)
+        keys = workload.positive_keys(5 * M + k, n)
+        keys = np.concatenate([keys, keys[: n // 8]])
+        dec = gpu.insert_recorded(to_dev(keys, dev)).cpu().numpy()
+        words = gpu.download()
+        assert not ((dec >= c) & (dec != 0xFF)).any()
+        assert np.array_equal(ref.place(keys, dec), words)
+        chk = oracle.OracleFilter(M, c, k, oracle.COST_NAMES[cost], None, ref.block_mult, ref.bit_mult,
+                                  distinct=True)
+        chk.words[:] = words
+        assert chk.query(keys[dec == 0xFF]).all()
+        assert chk.query(keys).all()
+    finally:
+        gpu.close()
+
+
 def test_racing_insert_fpr_matches_sequential_build(dev):
     """A full-size-per-block build (k = 14, three choices, EXP): the racing
     build's conditional FPR within 2% of the oracle's sequential build."""
