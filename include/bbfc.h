@@ -434,7 +434,7 @@ bbfc_status bbfc_batch_destroy(bbfc_batch_handle b);
 bbfc_status bbfc_batch_layout(bbfc_batch_handle b, uint64_t *total_keys, uint64_t *total_out_words);
 
 /* Racing insert of every filter's keys in one persistent launch. Each
- * filter keeps at most its own cap of keys in flight
+ * filter keeps at most its own bound on keys in flight
  * (BBFC_OPT_INSERT_INFLIGHT of that filter), as bbfc_insert does. */
 bbfc_status bbfc_batch_insert(bbfc_batch_handle b, const uint64_t *d_keys, hipStream_t stream);
 
