@@ -331,8 +331,9 @@ bbfc_status bbfc_insert_launch_info(bbfc_handle h, uint64_t n, uint32_t *tile_ke
  * CU (0 = as many as fit) and, for a batch plan's queries, the schedule:
  * units_per_grab == 0 strides units of tiles_per_wave tiles statically over
  * the wavefronts; 1..4096 hands them out in order, that many per atomic
- * grab (single filters always stride; batch inserts always grab one slot
- * at a time). Defaults {8, 1, 0, 0} (batch queries {8, 1, 0, 16}, batch
+ * grab, from eight queues (one per XCD) that deal the blocks of units in
+ * turn (single filters always stride; batch inserts always grab one slot
+ * at a time). Defaults {8, 1, 0, 0} (batch queries {8, 1, 0, 8}, batch
  * inserts {8, 1, 0, 1}). ms is
  * filled by the tuners. Shapes change speed only, never answers, and never
  * the deterministic insert; a racing insert's filter is schedule dependent

@@ -575,7 +575,7 @@ class Batch:
     def set_shape(self, op: int, lanes_per_key: int = 8, tiles_per_wave: int = 1, wgs_per_cu: int = 0,
                   units_per_grab: int | None = None) -> None:
         if units_per_grab is None:  # the plan's defaults
-            units_per_grab = 1 if op == OP_INSERT else 16
+            units_per_grab = 1 if op == OP_INSERT else 8
         _check(lib().bbfc_batch_set_shape(self.handle, op, _Shape(lanes_per_key, tiles_per_wave, wgs_per_cu,
                                                                   units_per_grab, 0.0)))
 

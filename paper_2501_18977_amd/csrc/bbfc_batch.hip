@@ -65,11 +65,22 @@ __device__ inline uint64_t first_lane_u64(uint64_t v)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Work counters: one queue per XCD, each counter on its own 128-byte line.
+// The batch insert uses queue 0's counter for its slots.
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 16; // 64-bit words between counters
+constexpr int kCounterWords = kQueues * kQueueStride;
+
 // Two schedules, chosen per launch: grab == 0 strides units statically over
 // the resident wavefronts; grab > 0 hands out units in increasing order,
-// `grab` at a time, from an atomic counter, which keeps the units in flight
-// in one moving window (fewer filters read at once, better cache reuse) at
-// the price of one counter atomic per grab.
+// `grab` at a time, which keeps the units in flight in one moving window
+// (fewer filters read at once, better cache reuse). The blocks of `grab`
+// units are dealt to kQueues queues in turn (block b to queue b % kQueues),
+// each with its own counter, so that grabs contend on eight addresses rather
+// than one: workgroup w draws from queue w % kQueues first (the dispatcher
+// places consecutive workgroups on consecutive XCDs), then takes what is
+// left in the other queues, so every unit is served wherever the workgroups
+// run.
 template <int C, int LPK, int T, bool EARLY>
 __global__ __launch_bounds__(kWGSize) void batch_query_kernel(const BatchFilter *__restrict__ filt, uint32_t n_filters,
                                                               uint64_t total_units, uint32_t grab,
@@ -83,6 +94,8 @@ __global__ __launch_bounds__(kWGSize) void batch_query_kernel(const BatchFilter 
     const uint32_t wv = wave_index();
     uint32_t f = 0;
     auto unit = [&](uint64_t u) __attribute__((always_inline)) {
+        if (filt[f].unit_off > u) // a queue taken over from another XCD starts lower
+            f = 0;
         while (f + 1 < n_filters && filt[f + 1].unit_off <= u)
             ++f;
         const BatchFilter &bf = filt[f];
@@ -96,16 +109,22 @@ __global__ __launch_bounds__(kWGSize) void batch_query_kernel(const BatchFilter 
             unit(u);
         return;
     }
-    for (;;) {
-        unsigned long long first = 0;
-        if (lane == 0)
-            first = atomicAdd(counter, (unsigned long long)grab);
-        first = first_lane_u64(first);
-        if (first >= total_units)
-            break;
-        const uint64_t last = first + grab < total_units ? first + grab : total_units;
-        for (uint64_t u = first; u < last; ++u)
-            unit(u);
+    const uint64_t n_blocks = (total_units + grab - 1) / grab;
+    const uint32_t q0 = blockIdx.x % kQueues;
+    for (uint32_t qi = 0; qi < kQueues; ++qi) {
+        const uint32_t q = (q0 + qi) % kQueues;
+        for (;;) {
+            unsigned long long i = 0;
+            if (lane == 0)
+                i = atomicAdd(counter + q * kQueueStride, 1ull);
+            const uint64_t b = first_lane_u64(i) * kQueues + q;
+            if (b >= n_blocks)
+                break;
+            const uint64_t first = b * grab;
+            const uint64_t last = first + grab < total_units ? first + grab : total_units;
+            for (uint64_t u = first; u < last; ++u)
+                unit(u);
+        }
     }
 }
 
@@ -138,8 +157,8 @@ __global__ __launch_bounds__(kWGSize) void batch_insert_kernel(const BatchFilter
 // memset, so that graphs replay it correctly).
 __global__ void reset_counter_kernel(unsigned long long *counter)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0)
-        *counter = 0;
+    for (int i = threadIdx.x; i < kCounterWords; i += blockDim.x)
+        counter[i] = 0;
 }
 
 template <int V>
@@ -219,9 +238,9 @@ struct bbfc_batch {
     int num_cus = 0;
     uint64_t total_keys = 0;
     uint64_t total_words = 0;
-    // [BBFC_OP_INSERT], [BBFC_OP_QUERY]; queries take units in order, 16 per
+    // [BBFC_OP_INSERT], [BBFC_OP_QUERY]; queries take units in order, 8 per
     // grab, so that few filters are read at once
-    bbfc_launch_shape shape[2] = {{8, 1, 0, 1, 0.0f}, {8, 1, 0, 16, 0.0f}};
+    bbfc_launch_shape shape[2] = {{8, 1, 0, 1, 0.0f}, {8, 1, 0, 8, 0.0f}};
     // device tables, rebuilt when a shape changes (graphs keep their own copies)
     bbfc::Tables t;
     int tables_tpw_query = 0;
@@ -270,7 +289,7 @@ hipError_t copy_tables(const Tables &src, Tables &dst)
     if (e == hipSuccess)
         e = hipMalloc(&dst.d_slots, src.slot_bytes);
     if (e == hipSuccess)
-        e = hipMalloc(&dst.d_counter, sizeof(unsigned long long));
+        e = hipMalloc(&dst.d_counter, kCounterWords * sizeof(unsigned long long));
     if (e == hipSuccess)
         e = hipMemcpy(dst.d_filt, src.d_filt, src.n_filters * sizeof(BatchFilter), hipMemcpyDeviceToDevice);
     if (e == hipSuccess)
@@ -447,7 +466,7 @@ bbfc_status bbfc_batch_create(const bbfc_handle *filters, const uint64_t *n_keys
         b->total_words += (n_keys[f] + 63) / 64;
     }
     bbfc::DeviceGuard guard(b->device);
-    hipError_t e = hipMalloc(&b->t.d_counter, sizeof(unsigned long long));
+    hipError_t e = hipMalloc(&b->t.d_counter, bbfc::kCounterWords * sizeof(unsigned long long));
     if (e != hipSuccess) {
         delete b;
         return hip_fail(e, "allocating the batch counter");
@@ -588,13 +607,13 @@ bbfc_status bbfc_batch_tune(bbfc_batch_handle b, int32_t op, const uint64_t *d_k
     bbfc_launch_shape winner = saved;
     float best_ms = -1.0f;
     // Candidates: lanes per key x tiles per wavefront x occupancy cap, and
-    // for queries the schedule (static stride, or ordered grabs of 16 units).
+    // for queries the schedule (static stride, or ordered grabs of 8 units).
     std::vector<bbfc_launch_shape> cands = {saved}; // the shape in force is tried first
     for (int lpk : {8, 4})
         for (int tpw : {1, 2})
             for (int occ : {0, 2})
-                for (int grab : {0, 16}) {
-                    if (op == BBFC_OP_INSERT && grab == 16)
+                for (int grab : {0, 8}) {
+                    if (op == BBFC_OP_INSERT && grab == 8)
                         continue; // inserts always take whole slots, one per grab
                     const bbfc_launch_shape c{lpk, tpw, occ, op == BBFC_OP_INSERT ? 1 : grab, 0.0f};
                     if (!bbfc::same_shape(c, saved))
