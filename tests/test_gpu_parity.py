@@ -246,6 +246,7 @@ RACING_CONFIGS = [
     (1 << 15, 2, 14, "la", 1 << 20),     # 2^20 keys, 16 bits/key, LA
     (1 << 14, 3, 8, "mix", 3 << 18),    # three choices, MIX, ~10.7 bits/key
     (3000, 2, 11, "exp", 3000 * 32),    # even non-power-of-two M, EXP
+    (1 << 18, 2, 11, "la", 1 << 23),    # 32768 keys in flight: the tiles of 8 keys on 1024 workgroups
 ]
 
 
