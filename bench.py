@@ -603,6 +603,8 @@ def small_workload(steps: int, warmup: int, with_cpu: bool) -> dict:
 
     ins_bytes = INSERT_BYTES_PER_KEY * n
     achieved = ins_bytes / (default["insert_ms"] / 1e3) / 1e9
+    ins_kernel = (f"insert_narrow_kernel<{c}, ArrayKeys, false>" if default_launch["tile_keys"] == 8
+                  else f"insert_kernel<{c}, 8, 1, ArrayKeys>")
     rec = {
         "value": default["mkeys_s"],
         "unit": "Mkeys/s",
@@ -615,16 +617,17 @@ def small_workload(steps: int, warmup: int, with_cpu: bool) -> dict:
         "insert_mkeys_s": default["insert_mkeys_s"],
         "query_mkeys_s": default["query_mkeys_s"],
         "variants": variants,
-        "roofline": {"bound": "hbm",
-                     "kernel": (f"insert_narrow_kernel<{c}, ArrayKeys, false>" if default_launch["tile_keys"] == 8
-                                else f"insert_kernel<{c}, 8, 1, ArrayKeys>"),
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_launch_algorithmic": int(ins_bytes),
-                     "launch_ms": default["insert_ms"], "traffic": None,
-                     "note": f"the filter is cache resident and the default insert keeps "
-                             f"{default_launch['keys_in_flight']} keys in flight in tiles of "
-                             f"{default_launch['tile_keys']} keys: bound by the latency of its memory round trips, "
-                             "not by bandwidth"},
+        "roofline": with_traffic({
+            "bound": "hbm", "kernel": ins_kernel,
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "bytes_per_launch_algorithmic": int(ins_bytes),
+            "launch_ms": default["insert_ms"],
+            "note": f"the filter is cache resident and the default insert keeps "
+                    f"{default_launch['keys_in_flight']} keys in flight in tiles of "
+                    f"{default_launch['tile_keys']} keys: bound by the latency of its memory round trips, "
+                    "not by bandwidth"},
+            measured_traffic("insert", ins_kernel, {"workload": "small", "n_keys": n, "n_blocks": M},
+                             "traffic_small.json"), default["insert_ms"]),
         "probe": probe,
         "cpu_baseline": cpu_baseline_small(n, M, c, k) if with_cpu else None,
     }
