@@ -77,9 +77,13 @@ def test_fused_query_matches_oracle(dev, c, cost, shape):
         f.close()
 
 
-@pytest.mark.parametrize("shape", [(8, 1), (4, 2)])
+@pytest.mark.parametrize("tile,shape", [(0, (8, 1)), (1, (8, 1)), (1, (4, 2)), (2, (8, 1))])
 @pytest.mark.parametrize("c,cost", [(1, "none"), (3, "mix")])
-def test_fused_insert(dev, c, cost, shape):
+def test_fused_insert(dev, c, cost, tile, shape):
+    """The racing insert of fused q-grams in tiles of 64 keys (two launch
+    shapes) and of 8 keys (tile 2, and the default for c = 3 at this size):
+    bit-exact with one choice, inside the envelope with three, and every
+    q-gram answers true."""
     q = 31
     genome = workload.random_bases(21, 300_000)
     gkeys = oracle.qgrams(genome, 1, len(genome), q)
@@ -90,6 +94,7 @@ def test_fused_insert(dev, c, cost, shape):
     f = bbfc.Filter(M, c, 8, cost, block_mult=bm, bit_mult=am)
     try:
         f.set_shape(bbfc.OP_INSERT, *shape)
+        f.set_option(bbfc.OPT_INSERT_TILE, tile)
         seq = to_dev(workload.pack_2bit(genome), dev)
         f.insert_kmers(seq, 1, len(genome), q)
         words = f.download()
