@@ -387,6 +387,10 @@ class Filter:
 
     # -------------------------------------------------------------- ops
     def insert(self, keys, stream=None) -> None:
+        """Racing insert (bbfc_insert): at most the filter's bound on keys in
+        flight (OPT_INSERT_INFLIGHT; default n_blocks/(8(c-1)), none with one
+        choice), in tiles of 8 keys where that bound is small
+        (OPT_INSERT_TILE; see insert_launch_info)."""
         keys = _device_u64(keys, "keys")
         _check(lib().bbfc_insert(self.handle, keys.data_ptr(), keys.numel(), _stream_handle(stream)))
 
