@@ -19,7 +19,8 @@
  *     (Sections 3.1, 3.2);
  *  7. the sequential insert without allocation, on an input larger than one
  *     window, equals the allocating one and the oracle, twice in a row;
- *  8. the server with device-resident requests answers as the oracle.
+ *  8. the server with device-resident requests (two slots of 8192 keys, so
+ *     that large requests span several batches) answers as the oracle.
  */
 #include <math.h>
 #include <stdio.h>
@@ -252,7 +253,13 @@ int main(void)
      * oracle's words from there, the last one cut at its length */
     {
         bbfc_server_handle srv = NULL;
-        CHECK(bbfc_server_create(a, NULL, &srv) == BBFC_OK, "server_create: %s", bbfc_last_error());
+        bbfc_server_config scfg;
+        CHECK(bbfc_server_default_config(&scfg) == BBFC_OK && scfg.n_slots >= 1 && scfg.max_batch_keys % 64 == 0,
+              "server defaults");
+        CHECK(bbfc_server_default_config(NULL) == BBFC_EINVAL, "null config accepted");
+        scfg.n_slots = 2;
+        scfg.max_batch_keys = 8192; /* the 30000- and 49000-key requests span several batches */
+        CHECK(bbfc_server_create(a, &scfg, &srv) == BBFC_OK, "server_create: %s", bbfc_last_error());
         const uint64_t starts[4] = {0, 640, 6400, 50048}, lens[4] = {1, 4097, 30000, 49000};
         uint64_t *d_ans = NULL;
         HIP(hipMalloc((void **)&d_ans, 4 * 1024 * 8));
