@@ -192,10 +192,15 @@ def test_deterministic_insert_default_parameters_match_oracle_derivation(dev):
         gpu.close()
 
 
+@pytest.mark.parametrize("tile", [0, 2])
 @pytest.mark.parametrize("M", [1, 64, 1 << 16, 3000, 1001])
-def test_one_choice_racing_insert_is_bit_exact(dev, M):
+def test_one_choice_racing_insert_is_bit_exact(dev, M, tile):
+    """With one choice the racing insert is the OR of all masks whatever the
+    schedule: bit-exact with the oracle, in tiles of 64 keys (the default,
+    every resident wavefront working) and of 8 keys."""
     ref, gpu = make_pair(M, 1, 10, "none", seed=M)
     try:
+        gpu.set_option(bbfc.OPT_INSERT_TILE, tile)
         keys = workload.positive_keys(M, 200_000)
         ref.insert(keys)
         gpu.insert(to_dev(keys, dev))
