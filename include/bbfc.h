@@ -463,7 +463,11 @@ bbfc_status bbfc_batch_tune(bbfc_batch_handle b, int32_t op, const uint64_t *d_k
  * tiles per wavefront 1|2, workgroups per CU unbounded|2) of `op` on
  * d_keys[0..n), `reps` timed runs each after one warm-up, and makes the
  * fastest the filter's shape for `op` (returned in *best, may be null);
- * the shape in force is kept unless another is more than 2% faster.
+ * the shape and insert tile in force are kept unless another is more than
+ * 2% faster. For inserts the shapes run in tiles of 64 keys and one more
+ * trial runs in tiles of 8 keys; the winner's tile becomes the filter's
+ * BBFC_OPT_INSERT_TILE (unchanged when the tile in force wins), under the
+ * filter's bound on keys in flight.
  * Insert trials run on a snapshot (8*n_blocks words of device memory for
  * the duration), restored before every trial and at the end, so the
  * filter is unchanged on return; query trials write d_out_bits. The same

@@ -775,17 +775,28 @@ bbfc_status bbfc_tune(bbfc_handle h, int32_t op, const uint64_t *d_keys, uint64_
         e = hipEventCreate(&ev0);
     if (e == hipSuccess)
         e = hipEventCreate(&ev1);
-    bbfc_launch_shape winner{saved[0], saved[1], saved[2], 0, 0.0f};
-    float best_ms = -1.0f;
-    std::vector<std::array<int, 3>> cands = {{saved[0], saved[1], saved[2]}};
+    // Candidates: the shape and insert tile in force first, then every
+    // shape of tiles of 64 keys and, for inserts, tiles of 8 keys (which
+    // use no shape). tile: the BBFC_OPT_INSERT_TILE value tried.
+    struct Cand {
+        int lpk, tpw, occ, tile;
+    };
+    const int saved_tile = h->insert_tile;
+    std::vector<Cand> cands = {{saved[0], saved[1], saved[2], saved_tile}};
     for (int lpk : {8, 4})
         for (int tpw : {1, 2})
             for (int occ : {0, 2})
-                if (!(lpk == saved[0] && tpw == saved[1] && occ == saved[2]))
-                    cands.push_back({lpk, tpw, occ});
+                if (op == BBFC_OP_INSERT || !(lpk == saved[0] && tpw == saved[1] && occ == saved[2]))
+                    cands.push_back({lpk, tpw, occ, op == BBFC_OP_INSERT ? 1 : saved_tile});
+    if (op == BBFC_OP_INSERT)
+        cands.push_back({saved[0], saved[1], saved[2], 2});
+    size_t winner_ci = 0;
+    bbfc_launch_shape winner{saved[0], saved[1], saved[2], 0, 0.0f};
+    float best_ms = -1.0f;
     for (size_t ci = 0; ci < cands.size() && e == hipSuccess; ++ci) {
-        const int lpk = cands[ci][0], tpw = cands[ci][1], occ = cands[ci][2];
+        const int lpk = cands[ci].lpk, tpw = cands[ci].tpw, occ = cands[ci].occ;
         h->shape[op] = bbfc_launch_shape{lpk, tpw, occ, 0, 0.0f};
+        h->insert_tile = cands[ci].tile;
         float total = 0.0f;
         for (uint32_t r = 0; r <= reps && e == hipSuccess; ++r) { // r == 0 warms up
             if (op == BBFC_OP_INSERT)
@@ -808,14 +819,14 @@ bbfc_status bbfc_tune(bbfc_handle h, int32_t op, const uint64_t *d_keys, uint64_
         const float avg = total / (float)reps;
         // the shape in force before tuning (candidate 0) keeps its place
         // unless another is more than 2% faster
-        const bool winner_is_current = ci > 0 && winner.lanes_per_key == saved[0] &&
-                                       winner.tiles_per_wave == saved[1] && winner.wgs_per_cu == saved[2];
-        const float margin = winner_is_current ? 0.98f : 1.0f;
+        const float margin = ci > 0 && winner_ci == 0 ? 0.98f : 1.0f;
         if (e == hipSuccess && (best_ms < 0.0f || avg < best_ms * margin)) {
             best_ms = avg;
+            winner_ci = ci;
             winner = bbfc_launch_shape{lpk, tpw, occ, 0, avg};
         }
     }
+    h->insert_tile = cands[winner_ci].tile;
     if (e == hipSuccess && snap)
         e = hipMemcpyAsync(h->d_words, snap, h->M * 64, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess)
@@ -828,6 +839,7 @@ bbfc_status bbfc_tune(bbfc_handle h, int32_t op, const uint64_t *d_keys, uint64_
         (void)hipEventDestroy(ev1);
     if (e != hipSuccess) {
         h->shape[op] = bbfc_launch_shape{saved[0], saved[1], saved[2], 0, 0.0f};
+        h->insert_tile = saved_tile;
         return hip_fail(e, "autotuning");
     }
     h->shape[op] = winner;

@@ -376,6 +376,15 @@ def test_single_filter_tuner(dev, op):
         assert gpu.get_shape(other)["lanes_per_key"] == 8 and gpu.get_shape(other)["tiles_per_wave"] == 1
         assert np.array_equal(gpu.download(), ref.words), "tuning changed the filter"
         assert np.array_equal(from_dev(gpu.query(pd)), ref.query_bits(probe))
+        if op == bbfc.OP_INSERT:
+            # 2048 keys in flight on this filter: tiles of 8 keys (the
+            # default here) are about 3x faster than any shape of 64 keys
+            assert gpu.get_option(bbfc.OPT_INSERT_TILE) in (0, 2)
+            assert gpu.insert_launch_info(1 << 18)["tile_keys"] == 8
+            gpu.set_option(bbfc.OPT_INSERT_TILE, 1)
+            gpu.tune(op, to_dev(keys, dev), reps=2)
+            assert gpu.get_option(bbfc.OPT_INSERT_TILE) == 2
+            assert np.array_equal(gpu.download(), ref.words), "tuning changed the filter"
     finally:
         gpu.close()
 
