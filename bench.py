@@ -656,6 +656,7 @@ CAP_SWEEP_CONFIGS = [
     (1 << 15, 2, 6, "exp", 8),
     (1 << 15, 3, 14, "exp", 20),
     (1 << 18, 2, 11, "la", 16),
+    (1 << 20, 2, 11, "la", 16),  # the default bound 131072 takes tiles of 64 keys and still binds
     (3000, 2, 11, "la", 16),
 ]
 
