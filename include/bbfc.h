@@ -317,7 +317,8 @@ bbfc_status bbfc_get_option(bbfc_handle h, int32_t option, int64_t *value);
  * tile (64 or 8); *keys_in_flight: the most keys the launch works on at
  * once (working wavefronts x tiles per wavefront x keys per tile), which
  * is the bound of BBFC_OPT_INSERT_INFLIGHT rounded down to whole
- * wavefronts (at least one), and at most n rounded up to whole tiles;
+ * wavefronts (at least one), at most what the launch holds resident, and
+ * at most n rounded up to whole tiles;
  * *workgroups: the grid. Outputs may be null. Errors: EINVAL (null
  * handle), EHIP. */
 bbfc_status bbfc_insert_launch_info(bbfc_handle h, uint64_t n, uint32_t *tile_keys, uint64_t *keys_in_flight,
