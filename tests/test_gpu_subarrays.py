@@ -102,6 +102,27 @@ def test_per_key_inserts(dev, M, T, c, k, cost, n):
         gpu.close()
 
 
+@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("M,T,c,k,cost,n", [cfg for cfg in CONFIGS if cfg[2] > 1])
+def test_racing_insert_decisions_rebuild_the_filter(dev, M, T, c, k, cost, n, tile):
+    """The racing insert on sub-array filters, in tiles of 64 and of 8 keys:
+    every recorded decision names a candidate inside the key's sub-array or
+    "present", and the oracle's placement of the decided keys is the filter
+    word for word (Sections 3.1, 3.2, 3.4)."""
+    ref, gpu = make_pair(M, T, c, k, cost, seed=4 * M + T + tile)
+    try:
+        gpu.set_option(bbfc.OPT_INSERT_TILE, tile)
+        keys = workload.positive_keys(M + 9, min(n, 1 << 17))
+        keys = np.concatenate([keys, keys[: len(keys) // 8]])
+        dec = gpu.insert_recorded(to_dev(keys, dev)).cpu().numpy()
+        words = gpu.download()
+        assert not ((dec >= c) & (dec != 0xFF)).any()
+        assert np.array_equal(ref.place(keys, dec), words)
+        assert bbfc.unpack_bits(from_dev(gpu.query(to_dev(keys, dev))), len(keys)).all()
+    finally:
+        gpu.close()
+
+
 @pytest.mark.parametrize("M,T,c,k,cost,n", [
     (1 << 17, 1 << 9, 2, 11, "la", 3 * (1 << 16) + 4321),  # several windows and a ragged one
     (777 * 4 * 15, 4, 4, 20, "la", (1 << 17) + 777),      # four choices, odd S = 11655
