@@ -1595,7 +1595,7 @@ _LEG_DROP = ("metric", "n_gpus", "higher_is_better", "scaling", "vs_baseline", "
              "kernel_source_sha", "steps", "warmup")
 
 
-def serve_leg(filt, n: int, n_requests: int = 10000) -> dict:
+def serve_leg(filt, n: int, n_requests: int = 20000) -> dict:
     """Serving, compact, on the headline's built filter: a Poisson stream of
     query requests (sizes log-uniform in [1, 65536], half inserted keys) with
     keys and answers in device memory, replayed through the continuous-
