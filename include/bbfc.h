@@ -635,9 +635,10 @@ bbfc_status bbfc_probe_insert_pattern(uint64_t *d_buf, uint64_t n_lines, uint64_
  *      atomics (an OR of zero where a word gains nothing) and right after
  *      them the next unit's reads, so no wait for reads covers atomics;
  *   2  the line that receives the mask is chosen from the key alone, not
- *      from the words read, so the atomics do not wait for the reads. Not
- *      an insert: it measures the same traffic without the dependency of
- *      the write on the reads.
+ *      from the words read, so the atomics do not wait for the reads (the
+ *      reads are still made; their words are summed into d_sink's
+ *      condition). Not an insert: it measures the same traffic without the
+ *      dependency of the write on the reads.
  * Arguments and errors as bbfc_probe_insert_pattern, plus EINVAL for
  * another schedule. */
 bbfc_status bbfc_probe_insert_schedule(uint64_t *d_buf, uint64_t n_lines, uint64_t n_keys, int32_t mask_bits,

@@ -167,13 +167,16 @@ __global__ __launch_bounds__(kProbeWG) void probe_insert_pattern_kernel(uint64_t
 //              reads, so no wait for reads ever covers the atomics;
 //   BLIND      the line is chosen from the key alone (one hash bit), not
 //              from the words read: the atomics no longer depend on the
-//              reads and issue together with them. This is not an insert
+//              reads and issue together with them. The words read are still
+//              consumed (summed after the atomics are issued), so that the
+//              loads are not dropped as dead code. This is not an insert
 //              (the choice ignores the blocks); it shows what the same
 //              traffic costs without the read-to-write dependency.
 template <int MODE>
 __global__ __launch_bounds__(kProbeWG) void probe_insert_schedule_kernel(uint64_t *__restrict__ buf,
                                                                           uint64_t line_mask, uint64_t n_keys,
-                                                                          int mask_bits, uint64_t seed)
+                                                                          int mask_bits, uint64_t seed,
+                                                                          uint64_t *__restrict__ sink)
 {
     const uint32_t lane = threadIdx.x & 63;
     const uint32_t g = lane >> 3;
@@ -194,6 +197,7 @@ __global__ __launch_bounds__(kProbeWG) void probe_insert_schedule_kernel(uint64_
             v1[r] = buf[l1[r] * 8 + w];
         }
     };
+    uint64_t acc = 0; // BLIND: the words read feed only this, so the loads stay
     read_unit(base);
     for (;;) {
         uint64_t cl[8], cm[8];
@@ -220,11 +224,19 @@ __global__ __launch_bounds__(kProbeWG) void probe_insert_schedule_kernel(uint64_
 #pragma unroll
         for (int r = 0; r < 8; ++r)
             __hip_atomic_fetch_or(&buf[cl[r] * 8 + w], cm[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if constexpr (MODE == 2) {
+            // consumed after the atomics are issued: they do not wait for these reads
+#pragma unroll
+            for (int r = 0; r < 8; ++r)
+                acc += v0[r] ^ v1[r];
+        }
         if (next >= n_keys)
             break;
         base = next;
         read_unit(base);
     }
+    if (acc == 0x9E3779B97F4A7C15ull)
+        sink[blockIdx.x & 0xFFFF] = acc;
 }
 
 // 64-byte requests: a wavefront takes 8 consecutive 128-byte lines per
@@ -363,10 +375,10 @@ hipError_t launch_probe_insert_schedule(uint64_t *buf, uint64_t n_lines, uint64_
         grid = (uint32_t)(need ? need : 1);
     if (schedule == 1)
         hipLaunchKernelGGL(probe_insert_schedule_kernel<1>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_keys,
-                           mask_bits, seed);
+                           mask_bits, seed, sink);
     else
         hipLaunchKernelGGL(probe_insert_schedule_kernel<2>, dim3(grid), dim3(kProbeWG), 0, s, buf, n_lines - 1, n_keys,
-                           mask_bits, seed);
+                           mask_bits, seed, sink);
     return hipGetLastError();
 }
 
